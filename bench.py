@@ -1,0 +1,176 @@
+"""Benchmark: point moves per second of the kinetic Delaunay repair on one GPU.
+
+Workload (the measured configuration): 1024 blocks -- the 32 x 32 square
+cells of side 2048 tiling [0, 65536)^2, i.e. a depth-5 quad-tree -- with
+1024 distinct uniform lattice points each (1,048,576 points), and in every
+time step one move per block of 1..8 units in one of four directions.  One
+kernel launch per time step; inputs (points, triangulations, the whole move
+stream) are resident in device memory before the timed region.
+
+A "step" is one time step: every block deletes its moved point and
+reinserts it (Fig. 4).  `value` counts applied moves (blocked moves are not
+counted) per second of the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --copy-probe     # plain copy kernel for counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "point moves/sec (delete+reinsert, bit-exact) at 1 MI355X; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def copy_probe():
+    """A plain device copy of known size (256 MiB read + 256 MiB written),
+    used to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 256 << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n, "launches": 3}), flush=True)
+
+
+def cpu_baseline(w, threads, budget_s=12.0, max_steps=16):
+    """The CPU oracle as it stands: apply the same moves, rebuild every block
+    whose points changed from scratch; applied moves per second."""
+    from oracle.kinetic import Kinetic
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    t0 = time.perf_counter()
+    applied, steps = 0, 0
+    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+        a = ref.apply_step(w["mv"], w["mv_off"][steps])
+        ref.all_dt(threads)
+        applied += int(a.sum())
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=applied / dt, unit="point moves/s", cores=threads, kind="oracle",
+                sample=f"first {steps} time steps of the same stream ({applied} applied moves), "
+                       f"every block rebuilt from scratch by Bowyer-Watson after each step, "
+                       f"{threads} host threads over blocks")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=980)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused", action="store_true", help="time the fused multi-step launch instead")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(blocks are independent: sharding them over GPUs needs no exchange, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2308_06484_amd import workloads as W
+    from paper_2308_06484_amd.kdt import KineticDT
+
+    K, Wu = args.steps, args.warmup
+    log(f"generating grid1024 with {K + Wu} steps")
+    w = W.grid1024(seed=args.seed, steps=K + Wu)
+    dev = torch.device("cuda:0")
+    dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev)
+    mv = torch.from_numpy(w["mv"]).to(dev)
+    off = torch.from_numpy(w["mv_off"]).to(dev)
+    torch.cuda.synchronize()
+    log("warmup")
+    if Wu:
+        dt.run(mv, off[:Wu].contiguous(), fused=args.fused)
+    dt.sync()
+    s0 = dt.stats()
+    dt.timing(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_host = time.perf_counter()
+    e0.record()
+    dt.run(mv, off[Wu:Wu + K].contiguous(), fused=args.fused)
+    e1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = e0.elapsed_time(e1)
+    kern_ms, launches = dt.timing_read()
+    dt.timing(False)
+    dt.sync()
+    s1 = dt.stats()
+    applied = s1["applied"] - s0["applied"]
+    blocked = s1["blocked"] - s0["blocked"]
+    alg = s1["alg_bytes"] - s0["alg_bytes"]
+    touched = s1["tri_touched"] - s0["tri_touched"]
+    value = applied / (ms / 1e3)
+    avg_launch_s = kern_ms / 1e3 / max(1, launches)
+    achieved = alg / max(1, launches) / avg_launch_s / 1e9
+    log(f"timed {K} steps: {ms:.2f} ms (host {t_host * 1e3:.1f} ms), kernels {kern_ms:.2f} ms over "
+        f"{launches} launches, applied {applied}, blocked {blocked}")
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point moves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wu,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "grid1024: 1024 blocks = 32x32 cells of 2048^2 over [0,65536)^2, "
+                        "1024 distinct uniform lattice points per block, one move per block per "
+                        "time step of 1-8 units in one of 4 directions, "
+                        + ("all steps in one fused launch" if args.fused else "one kernel launch per time step"),
+            "blocks": 1024,
+            "points_per_block": 1024,
+            "moves_per_step": 1024,
+            "seed": args.seed,
+        },
+        "applied_moves": applied,
+        "blocked_moves": blocked,
+        "mtri_touched_per_s": touched / (ms / 1e3) / 1e6,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_run_fused" if args.fused else "k_step",
+            "avg_launch_us": avg_launch_s * 1e6,
+            "alg_bytes_per_launch": alg / max(1, launches),
+        },
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        log(f"cpu baseline (oracle) on {threads} threads")
+        res["cpu_baseline"] = cpu_baseline(w, threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * kdt.h -- C-ABI of the kinetic Delaunay library (libkdt.so) for MI355X.
+ *
+ * The method (Hadiniya & Ghodsi, "A parallel algorithm for Delaunay
+ * triangulation of moving points on the plane"): the point set is split into
+ * blocks (Sec. III, "Data structure"; Sec. IV), every block keeps the Delaunay
+ * triangulation of its points, and at every time step a chosen point of every
+ * block moves in one of four directions (Lemma 1, Sec. V); each block then
+ * deletes the point from its triangulation and inserts it at its new place
+ * (Fig. 4; Sec. IV, "Insertion and Deletion"), all blocks in parallel.
+ *
+ * The triangulation kept is DT*: the Delaunay triangulation made unique on
+ * cocircular input by lifting every point by an infinitesimal that grows
+ * with its global id (Sec. I states uniqueness, which lattice input needs
+ * this rule for).  Collinear points on the hull are vertices.
+ *
+ * Conventions for every call:
+ *  - Coordinates are int32 lattice points in [0, 2^24).
+ *  - A point's global id is its row in the xy array given to kdt_init.
+ *    Block b owns the ids block_off[b] .. block_off[b+1]-1 (points grouped
+ *    by block), and its frame is the half-open rectangle
+ *    [x0, x1) x [y0, y1) from frames[4b .. 4b+3] = (x0, y0, x1, y1).
+ *  - Directions: 0 = +x (right), 1 = -x (left), 2 = +y (up), 3 = -y (down).
+ *  - Move rule: within a block the moves of one step apply one after the
+ *    other in the order given; a move jumps the point `dist` >= 1 lattice
+ *    units; it is BLOCKED (a no-op, counted apart) if the target lies
+ *    outside the block's frame or on a cell held by a point of the block.
+ *  - "dev" marks a device pointer, "host" a host pointer.  The caller owns
+ *    every buffer it passes; the library never allocates or frees device
+ *    memory: all device state lives in the caller's workspace.
+ *  - One context = one stream = one host thread.  Calls that launch work
+ *    are asynchronous on that stream; errors raised by kernels are sticky
+ *    and surface at kdt_sync, kdt_query* and kdt_stats.
+ *  - Status: 0 KDT_OK, negative KDT_E_* on error.  Nothing aborts and no
+ *    C++ exception crosses this interface.
+ */
+#ifndef KDT_H
+#define KDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KDT_OK 0
+#define KDT_E_ARG (-1)      /* bad argument (null pointer, size, index, dir, dist) */
+#define KDT_E_RANGE (-2)    /* coordinate outside [0, 2^24) or outside its frame */
+#define KDT_E_DUP (-3)      /* two points of a block on one lattice cell */
+#define KDT_E_DEGEN (-4)    /* a block with fewer than 4 points, or all collinear */
+#define KDT_E_CAPACITY (-5) /* workspace too small, or a local limit exceeded */
+#define KDT_E_DEVICE (-6)   /* HIP runtime error */
+#define KDT_E_STATE (-7)    /* call out of order (e.g. use after an error) */
+#define KDT_E_INTERNAL (-8) /* a device-side invariant check failed */
+
+/* One move: `point` is the LOCAL index of the point in its block
+ * (global id - block_off[block]); the block is implied by where the record
+ * sits in a step's per-block offsets.  16 bytes. */
+typedef struct kdt_move_s {
+    int32_t point;
+    int32_t dir;
+    int32_t dist;
+    int32_t pad;
+} kdt_move_t;
+
+/* Counters accumulated on the device since kdt_init (read by kdt_stats). */
+typedef struct kdt_stats_t {
+    int64_t applied;      /* moves applied (delete + reinsert done) */
+    int64_t blocked;      /* moves blocked by the move rule */
+    int64_t star_sum;     /* sum over applied moves of the moved point's degree */
+    int64_t cavity_sum;   /* sum of Bowyer-Watson cavity sizes (triangles) */
+    int64_t walk_sum;     /* sum of visibility-walk steps */
+    int64_t tri_touched;  /* triangle records read or written */
+    int64_t alg_bytes;    /* algorithmic HBM bytes of the repair (see DESIGN) */
+    int64_t errors;       /* blocks stopped by an error */
+} kdt_stats_t;
+
+typedef struct kdt_ctx kdt_ctx;
+
+/* Size in bytes of the device workspace kdt_init needs for n points in
+ * n_blocks blocks with the given host block offsets (n_blocks + 1 entries,
+ * block_off[0] = 0, block_off[n_blocks] = n) and room to stage up to
+ * max_staged moves per step through kdt_move.  Pure host computation. */
+int kdt_workspace_size(int64_t n, int32_t n_blocks, const int64_t* block_off,
+                       int32_t max_staged, size_t* dev_bytes);
+
+/* Create a context and build every block's DT* on the device (paper's
+ * starting state: a dataset that satisfies the Delaunay constraints, Fig. 4).
+ *   xy         host int32 [n][2]
+ *   block_off  host int64 [n_blocks + 1]
+ *   frames     host int32 [n_blocks][4], or NULL for [0, 2^24)^2 everywhere
+ *   dev_ws     dev workspace of ws_bytes >= kdt_workspace_size(...) bytes,
+ *              256-byte aligned, owned by the caller, must outlive the ctx
+ *   stream     hipStream_t to run on (NULL: the null stream)
+ * Validation is done on the host first: RANGE, DUP, DEGEN, ARG, CAPACITY. */
+int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
+             const int64_t* block_off, const int32_t* frames, int32_t max_staged,
+             void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Stage one move of the current step (host call; nothing runs yet).
+ * `point` is the GLOBAL id; it must belong to `block`. */
+int kdt_move(kdt_ctx* ctx, int32_t block, int64_t point, int32_t dir, int32_t dist);
+
+/* Apply the staged moves as one time step (one kernel launch) and clear the
+ * stage.  Fig. 4: every block deletes its moved point and reinserts it. */
+int kdt_step(kdt_ctx* ctx);
+
+/* Apply n_steps time steps from a move stream already in device memory:
+ *   moves     dev kdt_move_t [M]
+ *   step_off  dev int32 [n_steps][n_blocks + 1]: the moves of step t for
+ *             block b are moves[step_off[t][b] .. step_off[t][b+1]-1]
+ *   applied   dev int8 [M] or NULL: 1 if the move was applied, 0 if blocked
+ *   flags     KDT_RUN_* below
+ * KDT_RUN_PER_STEP (0) launches one kernel per step.  KDT_RUN_FUSED runs
+ * all steps of a block in one persistent launch; blocks are independent, so
+ * the result is the same. */
+#define KDT_RUN_PER_STEP 0
+#define KDT_RUN_FUSED 1
+int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
+            int32_t n_steps, int8_t* applied, int32_t flags);
+
+/* Query the current triangulation (synchronises the stream).
+ *   tris      dev int32 [cap][3]: real triangles as global ids,
+ *             counter-clockwise, each rotated to start at its smallest id,
+ *             grouped by block
+ *   adj       dev int32 [cap][3] or NULL: adj[t][j] is the index (in this
+ *             output) of the triangle across the edge opposite vertex j,
+ *             -1 on the convex hull of the block
+ *   blk_off   host int64 [n_blocks + 1] or NULL: block b's triangles are
+ *             rows blk_off[b] .. blk_off[b+1]-1
+ *   n_tri     host: number of triangles (written even if > cap, then
+ *             KDT_E_CAPACITY is returned and nothing else is written) */
+int kdt_query(kdt_ctx* ctx, int32_t* tris, int32_t* adj, int64_t* blk_off,
+              int64_t cap, int64_t* n_tri);
+
+/* Same triangles in canonical order (rows sorted lexicographically) written
+ * to a HOST buffer int32 [cap][3]; used to compare with a reference. */
+int kdt_query_canonical(kdt_ctx* ctx, int32_t* host_tris, int64_t cap, int64_t* n_tri);
+
+/* Current positions: host int32 [n][2] (synchronises). */
+int kdt_positions(kdt_ctx* ctx, int32_t* host_xy);
+
+/* Sum of the per-block counters (synchronises). */
+int kdt_stats(kdt_ctx* ctx, kdt_stats_t* out);
+
+/* Per-block status (synchronises): host int32 [n_blocks], 0 or KDT_E_*. */
+int kdt_block_status(kdt_ctx* ctx, int32_t* host_status);
+
+/* Kernel timing.  With enable != 0, kdt_run and kdt_step record a HIP event
+ * pair on the context's stream around every kernel they launch;
+ * kdt_timing_read waits for them and returns the summed kernel time (ms) and
+ * the number of launches since timing was last enabled.  Recording stops
+ * (and the pairs are released) when enable == 0. */
+int kdt_timing(kdt_ctx* ctx, int32_t enable);
+int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Wait for the stream; return the first sticky error, or KDT_OK. */
+int kdt_sync(kdt_ctx* ctx);
+
+/* Release the context (not the workspace, which the caller owns). */
+void kdt_destroy(kdt_ctx* ctx);
+
+/* Text for a status code. */
+const char* kdt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KDT_H */

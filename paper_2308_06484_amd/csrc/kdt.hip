@@ -1,0 +1,709 @@
+// libkdt: kinetic Delaunay triangulation of moving lattice points on MI355X.
+//
+// Kernels (one 64-lane wavefront per block of the partition, Sec. IV):
+//   k_build      every block's DT* from scratch (Bowyer-Watson insertion in
+//                Hilbert order); the starting state of Fig. 4
+//   k_step       one time step: for each block, its moves in order, each a
+//                walk to the target, Delete, Insert (Fig. 4)
+//   k_run_fused  all steps of a move stream; blocks are independent, so each
+//                wavefront runs its block's steps back to back
+//   k_qcount / k_qwrite   compaction of the real triangles (query)
+// plus the host implementation of include/kdt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/kdt.h"
+#include "kdt_device.hpp"
+
+using namespace kdt;
+
+namespace {
+
+constexpr int KDT_COORD_LIMIT = 1 << 24;
+
+// ------------------------------------------------------------------ device
+
+struct DevState {
+    Tri* tri;
+    int2* xy;
+    int* vtri;
+    const long long* pt_off;
+    const long long* tri_off;
+    const int4* frame;
+    int* status;
+    BlockStats* stats;
+    int* sticky;
+};
+
+__device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
+    BlockView B;
+    const long long p0 = s.pt_off[b], p1 = s.pt_off[b + 1];
+    B.tri = s.tri + s.tri_off[b];
+    B.xy = s.xy + p0;
+    B.vtri = s.vtri + p0;
+    B.n = (int)(p1 - p0);
+    B.ntri = 2 * B.n - 2;
+    return B;
+}
+
+__device__ void fail_block(const DevState& s, int b, int code) {
+    if (lane_id() == 0) {
+        s.status[b] = code;
+        s.stats[b].errors += 1;
+        atomicMin(s.sticky, code);
+    }
+}
+
+__global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
+    __shared__ WaveLDS S;
+    const int b = blockIdx.x;
+    const int lane = lane_id();
+    BlockView B = view_of(s, b);
+    const int* ord = order + s.pt_off[b];
+    const int n = B.n;
+    // first triangle: the first two points and the first point off their line
+    int a = ord[0], c1 = ord[1];
+    const int2 pa = B.xy[a], pb = B.xy[c1];
+    int kidx = -1;
+    for (int base = 2; base < n && kidx < 0; base += WAVE) {
+        const int i = base + lane;
+        const bool off_line = i < n && orient(pa, pb, B.xy[ord[i]]) != 0;
+        const uint64_t m = ballot(off_line);
+        if (m) kidx = base + __ffsll((long long)m) - 1;
+    }
+    if (kidx < 0) { fail_block(s, b, ST_DEGEN); return; }
+    int c = ord[kidx];
+    if (orient(pa, pb, B.xy[c]) < 0) { int t = a; a = c1; c1 = t; }
+    if (lane == 0) {
+        // slot 0: (a, c1, c); ghosts 1: (c1, a, inf), 2: (c, c1, inf), 3: (a, c, inf)
+        Tri t;
+        t.v = make_int4(a, c1, c, 0);
+        t.n = make_int4(2 * 4 + 2, 3 * 4 + 2, 1 * 4 + 2, 0);
+        B.tri[0] = t;
+        t.v = make_int4(c1, a, GHOST, 0);
+        t.n = make_int4(3 * 4 + 1, 2 * 4 + 0, 0 * 4 + 2, 0);
+        B.tri[1] = t;
+        t.v = make_int4(c, c1, GHOST, 0);
+        t.n = make_int4(1 * 4 + 1, 3 * 4 + 0, 0 * 4 + 0, 0);
+        B.tri[2] = t;
+        t.v = make_int4(a, c, GHOST, 0);
+        t.n = make_int4(2 * 4 + 1, 1 * 4 + 0, 0 * 4 + 1, 0);
+        B.tri[3] = t;
+        B.vtri[a] = 0;
+        B.vtri[c1] = 0;
+        B.vtri[c] = 0;
+    }
+    wsync();
+    int nt = 4, last = 0;
+    for (int idx = 2; idx < n; ++idx) {
+        if (idx == kidx) continue;
+        const int v = ord[idx];
+        const int2 q = B.xy[v];
+        int hit, hops = 0;
+        const int seed = walk(B, last, q, &hit, &hops);
+        if (seed < 0 || hit >= 0) { fail_block(s, b, ST_INTERNAL); return; }
+        const int rc = insert_vertex(B, S, v, q, seed, nt, nt + 1, nullptr);
+        if (rc != ST_OK) { fail_block(s, b, rc); return; }
+        nt += 2;
+        last = B.vtri[v];
+    }
+    if (nt != B.ntri) { fail_block(s, b, ST_INTERNAL); return; }
+}
+
+// One move of one block: walk to the target, delete, insert (Fig. 4).
+// Returns ST_OK (applied or blocked; *applied tells which) or an error.
+__device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
+                          BlockStats* st, int* applied) {
+    const int lane = lane_id();
+    *applied = 0;
+    const int p = mv.point, dir = mv.dir, dist = mv.dist;
+    if (p < 0 || p >= B.n || dir < 0 || dir > 3 || dist < 1) return ST_ARG;
+    const int2 o = B.xy[p];
+    long long qx = o.x, qy = o.y;
+    if (dir == 0) qx += dist;
+    else if (dir == 1) qx -= dist;
+    else if (dir == 2) qy += dist;
+    else qy -= dist;
+    if (qx < fr.x || qx >= fr.z || qy < fr.y || qy >= fr.w) {
+        if (lane == 0) st->blocked += 1;
+        return ST_OK;
+    }
+    const int2 q = make_int2((int)qx, (int)qy);
+    int hit, hops = 0;
+    const int tq = walk(B, B.vtri[p], q, &hit, &hops);
+    if (tq < 0) return ST_INTERNAL;
+    if (hit >= 0) {
+        if (lane == 0) {
+            st->blocked += 1;
+            st->walk_sum += hops;
+        }
+        return ST_OK;
+    }
+    const int k = remove_vertex(B, S, p, st);
+    if (k < 0) return k;
+    // a triangle of DT*(S - p) that q destroys: the one the walk found if it
+    // survived the deletion, else a hole triangle, else walk again
+    const bool instar = ballot(lane < k && S.star_slot[lane] == tq) != 0;
+    int seed = tq;
+    if (instar) {
+        const bool c = lane < k - 2 && conflicts(B, S.hole_rec[lane], q, p);
+        const uint64_t m = ballot(c);
+        if (m) {
+            seed = S.star_slot[__ffsll((long long)m) - 1];
+        } else {
+            int hit2;
+            seed = walk(B, S.star_slot[0], q, &hit2, &hops);
+            if (seed < 0 || hit2 >= 0) return ST_INTERNAL;
+        }
+    }
+    if (lane == 0) B.xy[p] = q;
+    wsync();
+    const int rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], st);
+    if (rc != ST_OK) return rc;
+    if (lane == 0) {
+        st->applied += 1;
+        st->walk_sum += hops;
+        st->tri_touched += hops;
+        // move record, own position and vtri read, walk records and their
+        // coordinates, new position written
+        st->alg_bytes += 16 + 12 + 56LL * hops + 8;
+    }
+    *applied = 1;
+    return ST_OK;
+}
+
+__device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
+                                int m0, int m1, int8_t* applied) {
+    BlockView B = view_of(s, b);
+    const int4 fr = s.frame[b];
+    BlockStats st = s.stats[b];
+    for (int m = m0; m < m1; ++m) {
+        int app = 0;
+        const int rc = apply_move(B, S, mv[m], fr, &st, &app);
+        if (applied && lane_id() == 0) applied[m] = (int8_t)app;
+        if (rc != ST_OK) {
+            if (lane_id() == 0) s.stats[b] = st;
+            fail_block(s, b, rc);
+            return;
+        }
+    }
+    if (lane_id() == 0) s.stats[b] = st;
+}
+
+__global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* mv, const int* off,
+                                               int8_t* applied) {
+    __shared__ WaveLDS S;
+    const int b = blockIdx.x;
+    if (s.status[b] != 0) return;
+    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied);
+}
+
+__global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* mv, const int* off,
+                                                    int n_steps, int n_blocks, int8_t* applied) {
+    __shared__ WaveLDS S;
+    const int b = blockIdx.x;
+    for (int t = 0; t < n_steps; ++t) {
+        if (s.status[b] != 0) return;
+        const int* o = off + (long long)t * (n_blocks + 1);
+        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied);
+    }
+}
+
+// query: number the real triangles of every block
+__global__ void __launch_bounds__(WAVE) k_qcount(DevState s, int* qmap, int* qcount) {
+    const int b = blockIdx.x;
+    const int lane = lane_id();
+    BlockView B = view_of(s, b);
+    int* map = qmap + s.tri_off[b];
+    int base = 0;
+    for (int i0 = 0; i0 < B.ntri; i0 += WAVE) {
+        const int i = i0 + lane;
+        const bool real = i < B.ntri && B.tri[i].v.z != GHOST;
+        const uint64_t m = ballot(real);
+        if (i < B.ntri) map[i] = real ? base + lanes_below(m) : -1;
+        base += __popcll(m);
+    }
+    if (lane == 0) qcount[b] = base;
+}
+
+__global__ void __launch_bounds__(WAVE) k_qwrite(DevState s, const int* qmap, const long long* qoff,
+                                                 int* tris, int* adj) {
+    const int b = blockIdx.x;
+    BlockView B = view_of(s, b);
+    const int* map = qmap + s.tri_off[b];
+    const long long o = qoff[b];
+    const int g0 = (int)s.pt_off[b];
+    for (int i = lane_id(); i < B.ntri; i += WAVE) {
+        const int idx = map[i];
+        if (idx < 0) continue;
+        const Tri t = B.tri[i];
+        int r = 0;
+        if (t.v.y < vget(t.v, r)) r = 1;
+        if (t.v.z < vget(t.v, r)) r = 2;
+        for (int j = 0; j < 3; ++j) {
+            const int e = (r + j) % 3;
+            tris[3 * (o + idx) + j] = g0 + vget(t.v, e);
+            if (adj) {
+                const int nb = vget(t.n, e) >> 2;
+                const int m = bad_slot(B, nb) ? -1 : map[nb];
+                adj[3 * (o + idx) + j] = m < 0 ? -1 : (int)(o + m);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, qcount, qoff,
+        qtris, stage_mv, stage_off, sticky, total;
+};
+
+Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
+    Layout L;
+    const int64_t ntri = 2 * n - 2 * (int64_t)B;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    L.tri = take(sizeof(Tri) * ntri);
+    L.xy = take(sizeof(int2) * n);
+    L.vtri = take(sizeof(int) * n);
+    L.order = take(sizeof(int) * n);
+    L.pt_off = take(sizeof(long long) * (B + 1));
+    L.tri_off = take(sizeof(long long) * (B + 1));
+    L.frame = take(sizeof(int4) * B);
+    L.status = take(sizeof(int) * B);
+    L.stats = take(sizeof(BlockStats) * B);
+    L.qmap = take(sizeof(int) * ntri);
+    L.qcount = take(sizeof(int) * B);
+    L.qoff = take(sizeof(long long) * (B + 1));
+    L.qtris = take(sizeof(int) * 3 * ntri);
+    L.stage_mv = take(sizeof(kdt_move_t) * (size_t)std::max(max_staged, 1));
+    L.stage_off = take(sizeof(int) * (B + 1));
+    L.sticky = take(sizeof(int) * 4);
+    L.total = o;
+    return L;
+}
+
+// Hilbert index of (x, y) on a 2^16 x 2^16 grid (classic rotate-and-flip
+// construction); used only to order insertions for short walks.
+uint64_t hilbert16(uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+        uint32_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+        d += (uint64_t)s * s * ((3 * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) { x = s - 1 - x; y = s - 1 - y; }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+}  // namespace
+
+struct kdt_ctx {
+    hipStream_t stream;
+    int32_t B;
+    int64_t n;
+    int32_t max_staged;
+    DevState dev;
+    char* ws;
+    Layout L;
+    std::vector<long long> pt_off, tri_off;
+    std::vector<kdt_move_t> staged;
+    std::vector<int32_t> staged_block;
+    int sticky;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
+    size_t ev_used = 0;
+};
+
+namespace {
+
+int check_hip(kdt_ctx* c, hipError_t e) {
+    if (e == hipSuccess) return KDT_OK;
+    if (c) c->sticky = KDT_E_DEVICE;
+    return KDT_E_DEVICE;
+}
+
+// Event pair around one launch when timing is on.
+hipEvent_t timing_begin(kdt_ctx* c) {
+    if (!c->timing) return nullptr;
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return nullptr;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
+        c->ev.push_back({a, b});
+    }
+    hipEvent_t a = c->ev[c->ev_used].first;
+    (void)hipEventRecord(a, c->stream);
+    return a;
+}
+void timing_end(kdt_ctx* c, hipEvent_t a) {
+    if (!a) return;
+    (void)hipEventRecord(c->ev[c->ev_used].second, c->stream);
+    c->ev_used++;
+}
+void release_events(kdt_ctx* c) {
+    for (auto& p : c->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    c->ev.clear();
+    c->ev_used = 0;
+}
+
+int64_t orient_h(const int32_t* a, const int32_t* b, const int32_t* c) {
+    return (int64_t)(b[0] - a[0]) * (c[1] - a[1]) - (int64_t)(b[1] - a[1]) * (c[0] - a[0]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kdt_strerror(int code) {
+    switch (code) {
+    case KDT_OK: return "ok";
+    case KDT_E_ARG: return "bad argument";
+    case KDT_E_RANGE: return "coordinate out of range or outside its frame";
+    case KDT_E_DUP: return "duplicate point in a block";
+    case KDT_E_DEGEN: return "block with fewer than 4 points or all collinear";
+    case KDT_E_CAPACITY: return "capacity exceeded";
+    case KDT_E_DEVICE: return "HIP runtime error";
+    case KDT_E_STATE: return "call out of order";
+    case KDT_E_INTERNAL: return "device invariant check failed";
+    default: return "unknown status";
+    }
+}
+
+int kdt_workspace_size(int64_t n, int32_t n_blocks, const int64_t* block_off, int32_t max_staged,
+                       size_t* dev_bytes) {
+    if (!dev_bytes || !block_off || n_blocks < 1 || n < 1 || max_staged < 0) return KDT_E_ARG;
+    if (block_off[0] != 0 || block_off[n_blocks] != n) return KDT_E_ARG;
+    if (2 * n >= (int64_t)1 << 31) return KDT_E_CAPACITY;
+    *dev_bytes = make_layout(n, n_blocks, max_staged).total;
+    return KDT_OK;
+}
+
+int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
+             const int64_t* block_off, const int32_t* frames, int32_t max_staged, void* dev_ws,
+             size_t ws_bytes, void* stream) {
+    if (!out) return KDT_E_ARG;
+    *out = nullptr;
+    if (!xy || !block_off || n_blocks < 1 || n < 1 || max_staged < 0) return KDT_E_ARG;
+    if (block_off[0] != 0 || block_off[n_blocks] != n) return KDT_E_ARG;
+    if (2 * n >= (int64_t)1 << 31) return KDT_E_CAPACITY;
+    for (int32_t b = 0; b < n_blocks; ++b) {
+        const int64_t cnt = block_off[b + 1] - block_off[b];
+        if (cnt < 0) return KDT_E_ARG;
+        if (cnt < 4) return KDT_E_DEGEN;
+        if (cnt > (1 << 22)) return KDT_E_CAPACITY;  // link indices are packed in 8 bits, slots in 30
+    }
+    // frames
+    std::vector<int4> fr(n_blocks);
+    for (int32_t b = 0; b < n_blocks; ++b) {
+        if (frames) {
+            const int32_t* f = frames + 4 * b;
+            if (f[0] < 0 || f[1] < 0 || f[2] > KDT_COORD_LIMIT || f[3] > KDT_COORD_LIMIT ||
+                f[0] >= f[2] || f[1] >= f[3])
+                return KDT_E_RANGE;
+            fr[b] = make_int4(f[0], f[1], f[2], f[3]);
+        } else {
+            fr[b] = make_int4(0, 0, KDT_COORD_LIMIT, KDT_COORD_LIMIT);
+        }
+    }
+    // per block: range, frame, duplicates, collinearity; Hilbert order
+    std::vector<int> order(n);
+    {
+        std::vector<std::pair<uint64_t, int>> key;
+        for (int32_t b = 0; b < n_blocks; ++b) {
+            const int64_t lo = block_off[b], hi = block_off[b + 1];
+            const int4 f = fr[b];
+            int32_t mnx = INT32_MAX, mny = INT32_MAX, mxx = 0, mxy = 0;
+            for (int64_t i = lo; i < hi; ++i) {
+                const int32_t x = xy[2 * i], y = xy[2 * i + 1];
+                if (x < 0 || y < 0 || x >= KDT_COORD_LIMIT || y >= KDT_COORD_LIMIT) return KDT_E_RANGE;
+                if (x < f.x || x >= f.z || y < f.y || y >= f.w) return KDT_E_RANGE;
+                mnx = std::min(mnx, x); mny = std::min(mny, y);
+                mxx = std::max(mxx, x); mxy = std::max(mxy, y);
+            }
+            key.clear();
+            for (int64_t i = lo; i < hi; ++i)
+                key.push_back({((uint64_t)(uint32_t)xy[2 * i] << 32) | (uint32_t)xy[2 * i + 1], (int)(i - lo)});
+            std::sort(key.begin(), key.end());
+            for (size_t i = 1; i < key.size(); ++i)
+                if (key[i].first == key[i - 1].first) return KDT_E_DUP;
+            bool off_line = false;
+            const int32_t* p0 = xy + 2 * lo;
+            const int32_t* p1 = xy + 2 * (lo + 1);
+            for (int64_t i = lo + 2; i < hi && !off_line; ++i) off_line = orient_h(p0, p1, xy + 2 * i) != 0;
+            if (!off_line) return KDT_E_DEGEN;
+            // Hilbert order over the block's bounding box
+            const double sx = 65535.0 / std::max(1, mxx - mnx), sy = 65535.0 / std::max(1, mxy - mny);
+            key.clear();
+            for (int64_t i = lo; i < hi; ++i) {
+                const uint32_t hx = (uint32_t)((xy[2 * i] - mnx) * sx), hy = (uint32_t)((xy[2 * i + 1] - mny) * sy);
+                key.push_back({hilbert16(hx, hy), (int)(i - lo)});
+            }
+            std::sort(key.begin(), key.end());
+            for (int64_t i = lo; i < hi; ++i) order[i] = key[i - lo].second;
+        }
+    }
+    const Layout L = make_layout(n, n_blocks, max_staged);
+    if (!dev_ws || ws_bytes < L.total) return KDT_E_CAPACITY;
+    if (((uintptr_t)dev_ws & 255) != 0) return KDT_E_ARG;
+
+    kdt_ctx* c = new (std::nothrow) kdt_ctx();
+    if (!c) return KDT_E_CAPACITY;
+    c->stream = (hipStream_t)stream;
+    c->B = n_blocks;
+    c->n = n;
+    c->max_staged = max_staged;
+    c->ws = (char*)dev_ws;
+    c->L = L;
+    c->sticky = KDT_OK;
+    c->pt_off.assign(block_off, block_off + n_blocks + 1);
+    c->tri_off.resize(n_blocks + 1);
+    c->tri_off[0] = 0;
+    for (int32_t b = 0; b < n_blocks; ++b)
+        c->tri_off[b + 1] = c->tri_off[b] + 2 * (c->pt_off[b + 1] - c->pt_off[b]) - 2;
+    char* w = c->ws;
+    c->dev.tri = (Tri*)(w + L.tri);
+    c->dev.xy = (int2*)(w + L.xy);
+    c->dev.vtri = (int*)(w + L.vtri);
+    c->dev.pt_off = (const long long*)(w + L.pt_off);
+    c->dev.tri_off = (const long long*)(w + L.tri_off);
+    c->dev.frame = (const int4*)(w + L.frame);
+    c->dev.status = (int*)(w + L.status);
+    c->dev.stats = (BlockStats*)(w + L.stats);
+    c->dev.sticky = (int*)(w + L.sticky);
+    hipStream_t s = c->stream;
+    int rc = KDT_OK;
+    // The host arrays are pageable: these copies complete before returning.
+    rc |= check_hip(c, hipMemcpyAsync(w + L.xy, xy, sizeof(int2) * n, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.pt_off, c->pt_off.data(), sizeof(long long) * (n_blocks + 1), hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.tri_off, c->tri_off.data(), sizeof(long long) * (n_blocks + 1), hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.frame, fr.data(), sizeof(int4) * n_blocks, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int) * n_blocks, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
+    if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
+    k_build<<<n_blocks, WAVE, 0, s>>>(c->dev, (const int*)(w + L.order));
+    if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
+    rc = check_hip(c, hipStreamSynchronize(s));
+    if (rc != KDT_OK) { delete c; return rc; }
+    *out = c;
+    return KDT_OK;
+}
+
+int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist) {
+    if (!c) return KDT_E_ARG;
+    if (block < 0 || block >= c->B) return KDT_E_ARG;
+    if (point < c->pt_off[block] || point >= c->pt_off[block + 1]) return KDT_E_ARG;
+    if (dir < 0 || dir > 3 || dist < 1) return KDT_E_ARG;
+    if ((int64_t)c->staged.size() >= c->max_staged) return KDT_E_CAPACITY;
+    kdt_move_t m;
+    m.point = (int32_t)(point - c->pt_off[block]);
+    m.dir = dir;
+    m.dist = dist;
+    m.pad = 0;
+    c->staged.push_back(m);
+    c->staged_block.push_back(block);
+    return KDT_OK;
+}
+
+int kdt_step(kdt_ctx* c) {
+    if (!c) return KDT_E_ARG;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    // group the staged moves by block, keeping their order within a block
+    std::vector<int> idx(c->staged.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int a, int b) { return c->staged_block[a] < c->staged_block[b]; });
+    std::vector<kdt_move_t> mv(idx.size());
+    std::vector<int> off(c->B + 1, 0);
+    for (size_t i = 0; i < idx.size(); ++i) {
+        mv[i] = c->staged[idx[i]];
+        off[c->staged_block[idx[i]] + 1]++;
+    }
+    for (int32_t b = 0; b < c->B; ++b) off[b + 1] += off[b];
+    c->staged.clear();
+    c->staged_block.clear();
+    char* w = c->ws;
+    int rc = KDT_OK;
+    if (!mv.empty())
+        rc |= check_hip(c, hipMemcpyAsync(w + c->L.stage_mv, mv.data(), sizeof(kdt_move_t) * mv.size(),
+                                          hipMemcpyHostToDevice, c->stream));
+    rc |= check_hip(c, hipMemcpyAsync(w + c->L.stage_off, off.data(), sizeof(int) * (c->B + 1),
+                                      hipMemcpyHostToDevice, c->stream));
+    if (rc != KDT_OK) return KDT_E_DEVICE;
+    hipEvent_t e0 = timing_begin(c);
+    k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
+                                         (const int*)(w + c->L.stage_off), nullptr);
+    timing_end(c, e0);
+    return check_hip(c, hipGetLastError());
+}
+
+int kdt_run(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_t n_steps,
+            int8_t* applied, int32_t flags) {
+    if (!c || n_steps < 0 || (n_steps > 0 && (!moves || !step_off))) return KDT_E_ARG;
+    if (flags != KDT_RUN_PER_STEP && flags != KDT_RUN_FUSED) return KDT_E_ARG;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    if (n_steps == 0) return KDT_OK;
+    if (flags == KDT_RUN_FUSED) {
+        hipEvent_t e0 = timing_begin(c);
+        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied);
+        timing_end(c, e0);
+        return check_hip(c, hipGetLastError());
+    }
+    for (int32_t t = 0; t < n_steps; ++t) {
+        hipEvent_t e0 = timing_begin(c);
+        k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off + (int64_t)t * (c->B + 1), applied);
+        timing_end(c, e0);
+    }
+    return check_hip(c, hipGetLastError());
+}
+
+int kdt_sync(kdt_ctx* c) {
+    if (!c) return KDT_E_ARG;
+    if (c->sticky != KDT_OK) return c->sticky;
+    if (check_hip(c, hipStreamSynchronize(c->stream)) != KDT_OK) return KDT_E_DEVICE;
+    int dev_sticky = 0;
+    if (check_hip(c, hipMemcpy(&dev_sticky, c->dev.sticky, sizeof(int), hipMemcpyDeviceToHost)) != KDT_OK)
+        return KDT_E_DEVICE;
+    if (dev_sticky != 0) c->sticky = dev_sticky;
+    return c->sticky;
+}
+
+int kdt_query(kdt_ctx* c, int32_t* tris, int32_t* adj, int64_t* blk_off, int64_t cap, int64_t* n_tri) {
+    if (!c || !n_tri || cap < 0 || (cap > 0 && !tris)) return KDT_E_ARG;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    char* w = c->ws;
+    int* qmap = (int*)(w + c->L.qmap);
+    int* qcount = (int*)(w + c->L.qcount);
+    k_qcount<<<c->B, WAVE, 0, c->stream>>>(c->dev, qmap, qcount);
+    if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
+    std::vector<int> cnt(c->B);
+    if (check_hip(c, hipMemcpyAsync(cnt.data(), qcount, sizeof(int) * c->B, hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipStreamSynchronize(c->stream)))
+        return KDT_E_DEVICE;
+    std::vector<long long> off(c->B + 1, 0);
+    for (int32_t b = 0; b < c->B; ++b) off[b + 1] = off[b] + cnt[b];
+    *n_tri = off[c->B];
+    if (blk_off)
+        for (int32_t b = 0; b <= c->B; ++b) blk_off[b] = off[b];
+    if (off[c->B] > cap) return KDT_E_CAPACITY;
+    if (check_hip(c, hipMemcpyAsync(w + c->L.qoff, off.data(), sizeof(long long) * (c->B + 1),
+                                    hipMemcpyHostToDevice, c->stream)))
+        return KDT_E_DEVICE;
+    k_qwrite<<<c->B, WAVE, 0, c->stream>>>(c->dev, qmap, (const long long*)(w + c->L.qoff), tris, adj);
+    if (check_hip(c, hipGetLastError()) || check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    return KDT_OK;
+}
+
+int kdt_query_canonical(kdt_ctx* c, int32_t* host_tris, int64_t cap, int64_t* n_tri) {
+    if (!c || !n_tri || cap < 0 || (cap > 0 && !host_tris)) return KDT_E_ARG;
+    // device staging of the compacted list lives in the workspace
+    const int64_t max_tri = 2 * c->n - 2 * (int64_t)c->B;
+    void* dbuf = c->ws + c->L.qtris;
+    int64_t nt = 0;
+    int rc = kdt_query(c, (int32_t*)dbuf, nullptr, nullptr, max_tri, &nt);
+    *n_tri = nt;
+    std::vector<int32_t> h;
+    if (rc == KDT_OK) {
+        h.resize(3 * (size_t)nt);
+        if (check_hip(c, hipMemcpy(h.data(), dbuf, sizeof(int32_t) * 3 * (size_t)nt, hipMemcpyDeviceToHost)))
+            rc = KDT_E_DEVICE;
+    }
+    if (rc != KDT_OK) return rc;
+    if (nt > cap) return KDT_E_CAPACITY;
+    std::vector<int64_t> idx(nt);
+    for (int64_t i = 0; i < nt; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        const int32_t* x = &h[3 * a];
+        const int32_t* y = &h[3 * b];
+        if (x[0] != y[0]) return x[0] < y[0];
+        if (x[1] != y[1]) return x[1] < y[1];
+        return x[2] < y[2];
+    });
+    for (int64_t i = 0; i < nt; ++i)
+        for (int j = 0; j < 3; ++j) host_tris[3 * i + j] = h[3 * idx[i] + j];
+    return KDT_OK;
+}
+
+int kdt_positions(kdt_ctx* c, int32_t* host_xy) {
+    if (!c || !host_xy) return KDT_E_ARG;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK && rc != KDT_E_INTERNAL && rc != KDT_E_CAPACITY) return rc;
+    if (check_hip(c, hipMemcpy(host_xy, c->dev.xy, sizeof(int2) * c->n, hipMemcpyDeviceToHost))) return KDT_E_DEVICE;
+    return KDT_OK;
+}
+
+int kdt_stats(kdt_ctx* c, kdt_stats_t* out) {
+    if (!c || !out) return KDT_E_ARG;
+    if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    std::vector<BlockStats> st(c->B);
+    if (check_hip(c, hipMemcpy(st.data(), c->dev.stats, sizeof(BlockStats) * c->B, hipMemcpyDeviceToHost)))
+        return KDT_E_DEVICE;
+    std::memset(out, 0, sizeof(*out));
+    for (const BlockStats& s : st) {
+        out->applied += s.applied;
+        out->blocked += s.blocked;
+        out->star_sum += s.star_sum;
+        out->cavity_sum += s.cavity_sum;
+        out->walk_sum += s.walk_sum;
+        out->tri_touched += s.tri_touched;
+        out->alg_bytes += s.alg_bytes;
+        out->errors += s.errors;
+    }
+    return KDT_OK;
+}
+
+int kdt_block_status(kdt_ctx* c, int32_t* host_status) {
+    if (!c || !host_status) return KDT_E_ARG;
+    if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    if (check_hip(c, hipMemcpy(host_status, c->dev.status, sizeof(int) * c->B, hipMemcpyDeviceToHost)))
+        return KDT_E_DEVICE;
+    return KDT_OK;
+}
+
+int kdt_timing(kdt_ctx* c, int32_t enable) {
+    if (!c) return KDT_E_ARG;
+    if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    c->ev_used = 0;
+    c->timing = enable != 0;
+    if (!c->timing) release_events(c);
+    return KDT_OK;
+}
+
+int kdt_timing_read(kdt_ctx* c, double* total_ms, int64_t* launches) {
+    if (!c || !total_ms || !launches) return KDT_E_ARG;
+    if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    double tot = 0.0;
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        if (check_hip(c, hipEventElapsedTime(&ms, c->ev[i].first, c->ev[i].second))) return KDT_E_DEVICE;
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)c->ev_used;
+    return KDT_OK;
+}
+
+void kdt_destroy(kdt_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release_events(c);
+    delete c;
+}
+
+}  // extern "C"
