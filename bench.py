@@ -127,6 +127,16 @@ def main():
     achieved = alg / max(1, launches) / avg_launch_s / 1e9
     log(f"timed {K} steps: {ms:.2f} ms (host {t_host * 1e3:.1f} ms), kernels {kern_ms:.2f} ms over "
         f"{launches} launches, applied {applied}, blocked {blocked}")
+    khz = max(1, s1["clock_khz"])
+    phases = {ph: (s1["t_" + ph] - s0["t_" + ph]) / khz * 1e3 / max(1, applied)
+              for ph in ("star", "locate", "hole", "insert")}
+    log("per applied move, us of one wavefront: " + ", ".join(f"{k} {v:.2f}" for k, v in phases.items())
+        + f"; mean degree {(s1['star_sum'] - s0['star_sum']) / max(1, applied):.2f}"
+        + f", mean cavity {(s1['cavity_sum'] - s0['cavity_sum']) / max(1, applied):.2f}"
+        + f", mean walk {(s1['walk_sum'] - s0['walk_sum']) / max(1, applied + blocked):.2f}")
+    hist = [a - b for a, b in zip(s1["hist"], s0["hist"])]
+    log("move time histogram (us upper edge: count): " + ", ".join(
+        f"{(2 ** (i + 1)) / khz * 1e3:.2f}: {c}" for i, c in enumerate(hist) if c))
     res = {
         "metric": METRIC,
         "value": value,
@@ -151,6 +161,9 @@ def main():
             "seed": args.seed,
         },
         "applied_moves": applied,
+        "phase_us_per_move": phases,
+        "move_time_hist": {f"<{(2 ** (i + 1)) / khz * 1e3:.2f}us": c
+                           for i, c in enumerate([a - b for a, b in zip(s1["hist"], s0["hist"])]) if c},
         "blocked_moves": blocked,
         "mtri_touched_per_s": touched / (ms / 1e3) / 1e6,
         "roofline": {

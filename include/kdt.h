@@ -74,6 +74,15 @@ typedef struct kdt_stats_t {
     int64_t tri_touched;  /* triangle records read or written */
     int64_t alg_bytes;    /* algorithmic HBM bytes of the repair (see DESIGN) */
     int64_t errors;       /* blocks stopped by an error */
+    /* time the blocks' wavefronts spent per phase of applied moves, in
+     * ticks of the device wall clock (clock_khz ticks per millisecond):
+     * gathering the star, locating the target, retriangulating the hole,
+     * inserting (cavity and fan) */
+    int64_t t_star, t_locate, t_hole, t_insert;
+    int64_t clock_khz;
+    /* applied moves by the time one move took: bucket b counts moves of
+     * [2^b, 2^(b+1)) wall-clock ticks */
+    int64_t hist[16];
 } kdt_stats_t;
 
 typedef struct kdt_ctx kdt_ctx;

@@ -54,9 +54,19 @@ __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
 __device__ void fail_block(const DevState& s, int b, int code) {
     if (lane_id() == 0) {
         s.status[b] = code;
-        s.stats[b].errors += 1;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b].errors), 1ull);
         atomicMin(s.sticky, code);
     }
+}
+
+__device__ __forceinline__ Tri make_tri(int a, int b, int c, int2 pa, int2 pb, int2 pc, int na, int nb,
+                                        int nc) {
+    Tri t;
+    t.v = make_int4(a, b, c, 0);
+    t.n = make_int4(na, nb, nc, 0);
+    t.c01 = make_int4(pa.x, pa.y, pb.x, pb.y);
+    t.c2 = c == GHOST ? make_int4(0, 0, 0, 0) : make_int4(pc.x, pc.y, 0, 0);
+    return t;
 }
 
 __global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
@@ -66,57 +76,63 @@ __global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
     BlockView B = view_of(s, b);
     const int* ord = order + s.pt_off[b];
     const int n = B.n;
+    scratch_init(S);
     // first triangle: the first two points and the first point off their line
     int a = ord[0], c1 = ord[1];
-    const int2 pa = B.xy[a], pb = B.xy[c1];
+    int2 pa = B.xy[a], pb = B.xy[c1];
     int kidx = -1;
     for (int base = 2; base < n && kidx < 0; base += WAVE) {
         const int i = base + lane;
         const bool off_line = i < n && orient(pa, pb, B.xy[ord[i]]) != 0;
         const uint64_t m = ballot(off_line);
-        if (m) kidx = base + __ffsll((long long)m) - 1;
+        if (m) kidx = base + first_lane(m);
     }
     if (kidx < 0) { fail_block(s, b, ST_DEGEN); return; }
-    int c = ord[kidx];
-    if (orient(pa, pb, B.xy[c]) < 0) { int t = a; a = c1; c1 = t; }
+    const int c = ord[kidx];
+    const int2 pc = B.xy[c];
+    if (orient(pa, pb, pc) < 0) {
+        const int t = a; a = c1; c1 = t;
+        const int2 tp = pa; pa = pb; pb = tp;
+    }
     if (lane == 0) {
         // slot 0: (a, c1, c); ghosts 1: (c1, a, inf), 2: (c, c1, inf), 3: (a, c, inf)
-        Tri t;
-        t.v = make_int4(a, c1, c, 0);
-        t.n = make_int4(2 * 4 + 2, 3 * 4 + 2, 1 * 4 + 2, 0);
-        B.tri[0] = t;
-        t.v = make_int4(c1, a, GHOST, 0);
-        t.n = make_int4(3 * 4 + 1, 2 * 4 + 0, 0 * 4 + 2, 0);
-        B.tri[1] = t;
-        t.v = make_int4(c, c1, GHOST, 0);
-        t.n = make_int4(1 * 4 + 1, 3 * 4 + 0, 0 * 4 + 0, 0);
-        B.tri[2] = t;
-        t.v = make_int4(a, c, GHOST, 0);
-        t.n = make_int4(2 * 4 + 1, 1 * 4 + 0, 0 * 4 + 1, 0);
-        B.tri[3] = t;
+        const int2 z = make_int2(0, 0);
+        B.tri[0] = make_tri(a, c1, c, pa, pb, pc, 2 * 4 + 2, 3 * 4 + 2, 1 * 4 + 2);
+        B.tri[1] = make_tri(c1, a, GHOST, pb, pa, z, 3 * 4 + 1, 2 * 4 + 0, 0 * 4 + 2);
+        B.tri[2] = make_tri(c, c1, GHOST, pc, pb, z, 1 * 4 + 1, 3 * 4 + 0, 0 * 4 + 0);
+        B.tri[3] = make_tri(a, c, GHOST, pa, pc, z, 2 * 4 + 1, 1 * 4 + 0, 0 * 4 + 1);
         B.vtri[a] = 0;
         B.vtri[c1] = 0;
         B.vtri[c] = 0;
     }
-    wsync();
+    gsync();
     int nt = 4, last = 0;
     for (int idx = 2; idx < n; ++idx) {
         if (idx == kidx) continue;
         const int v = ord[idx];
         const int2 q = B.xy[v];
         int hit, hops = 0;
-        const int seed = walk(B, last, q, &hit, &hops);
+        const int seed = walk<false>(B, S, last, q, &hit, &hops);
         if (seed < 0 || hit >= 0) { fail_block(s, b, ST_INTERNAL); return; }
-        const int rc = insert_vertex(B, S, v, q, seed, nt, nt + 1, nullptr);
+        int used = 0, nvt = 0;
+        const int rc = insert_vertex(B, S, v, q, seed, nt, nt + 1, &used, &nvt, nullptr);
         if (rc != ST_OK) { fail_block(s, b, rc); return; }
+        last = S.vt_s[nvt - 1];  // a triangle incident to v
+        commit(B, S, used, 0, nvt);
+        gsync();
         nt += 2;
-        last = B.vtri[v];
     }
     if (nt != B.ntri) { fail_block(s, b, ST_INTERNAL); return; }
 }
 
-// One move of one block: walk to the target, delete, insert (Fig. 4).
-// Returns ST_OK (applied or blocked; *applied tells which) or an error.
+// One move of one block (Fig. 4): Delete p, Insert it at the target.
+//  1. gather p's star; if the target q lies in the star's closed region the
+//     only points it can meet are the link vertices, else walk to q;
+//  2. blocked (no change) if q is outside the frame or held by a point;
+//  3. retriangulate the hole, insert q seeded by a triangle it destroys;
+//  4. write the changes back.
+// Returns ST_OK (applied or blocked; *applied tells which) or an error, in
+// which case memory is unchanged.
 __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
                           BlockStats* st, int* applied) {
     const int lane = lane_id();
@@ -134,44 +150,65 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
         return ST_OK;
     }
     const int2 q = make_int2((int)qx, (int)qy);
-    int hit, hops = 0;
-    const int tq = walk(B, B.vtri[p], q, &hit, &hops);
-    if (tq < 0) return ST_INTERNAL;
-    if (hit >= 0) {
+    const long long c0 = wall_clock64();
+    int used = 0, nvt = 0;
+    const int k = gather_star(B, S, p, &used, st);
+    if (k < 0) return k;
+    const long long c1 = wall_clock64();
+    bool in_star, on_vertex;
+    locate_in_star(S, k, o, q, &in_star, &on_vertex);
+    int hops = 0, tq = -1;
+    if (!in_star) {
+        int hit;
+        tq = walk<false>(B, S, S.star_slot[0], q, &hit, &hops);
+        if (tq < 0) return ST_INTERNAL;
+        on_vertex = hit >= 0;
+    }
+    if (on_vertex) {
+        table_clear(S);
         if (lane == 0) {
             st->blocked += 1;
             st->walk_sum += hops;
         }
         return ST_OK;
     }
-    const int k = remove_vertex(B, S, p, st);
-    if (k < 0) return k;
-    // a triangle of DT*(S - p) that q destroys: the one the walk found if it
-    // survived the deletion, else a hole triangle, else walk again
-    const bool instar = ballot(lane < k && S.star_slot[lane] == tq) != 0;
+    const long long c2 = wall_clock64();
+    int rc = retriangulate_hole(B, S, k, &used, &nvt, st);
+    if (rc != ST_OK) return rc;
+    const long long c3 = wall_clock64();
+    // a triangle of DT*(S - p) that q destroys: the one the walk found
+    // (outside the star, so untouched by the deletion), else a hole
+    // triangle, else the end of a walk from the hole
     int seed = tq;
-    if (instar) {
-        const bool c = lane < k - 2 && conflicts(B, S.hole_rec[lane], q, p);
+    if (in_star) {
+        const bool c = lane < k - 2 && conflicts(S.trec[S.hole_ent[lane]], q, p);
         const uint64_t m = ballot(c);
         if (m) {
-            seed = S.star_slot[__ffsll((long long)m) - 1];
+            seed = S.star_slot[first_lane(m)];
         } else {
             int hit2;
-            seed = walk(B, S.star_slot[0], q, &hit2, &hops);
+            seed = walk<true>(B, S, S.star_slot[0], q, &hit2, &hops);
             if (seed < 0 || hit2 >= 0) return ST_INTERNAL;
         }
     }
-    if (lane == 0) B.xy[p] = q;
-    wsync();
-    const int rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], st);
+    const int nvt_del = nvt;
+    rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], &used, &nvt, st);
     if (rc != ST_OK) return rc;
+    commit(B, S, used, nvt_del, nvt);
+    if (lane == 0) B.xy[p] = q;
+    const long long c4 = wall_clock64();
     if (lane == 0) {
+        const long long dt = c4 - c0;
+        st->hist[dt <= 1 ? 0 : min(15, 63 - __clzll(dt))] += 1;
+        st->t_star += c1 - c0;
+        st->t_locate += c2 - c1;
+        st->t_hole += c3 - c2;
+        st->t_insert += c4 - c3;
         st->applied += 1;
         st->walk_sum += hops;
         st->tri_touched += hops;
-        // move record, own position and vtri read, walk records and their
-        // coordinates, new position written
-        st->alg_bytes += 16 + 12 + 56LL * hops + 8;
+        // move record, own position, walk records, new position
+        st->alg_bytes += 16 + 8 + 64LL * hops + 8;
     }
     *applied = 1;
     return ST_OK;
@@ -181,36 +218,47 @@ __device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_
                                 int m0, int m1, int8_t* applied) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
-    BlockStats st = s.stats[b];
+    // counters start at zero in LDS and are added to the block's totals at
+    // the end (no load of the totals on the way in)
+    constexpr int NF = sizeof(BlockStats) / sizeof(long long);
+    if (lane_id() < NF) reinterpret_cast<long long*>(&S.st)[lane_id()] = 0;
+    wsync();
+    int rc = ST_OK;
     for (int m = m0; m < m1; ++m) {
         int app = 0;
-        const int rc = apply_move(B, S, mv[m], fr, &st, &app);
+        if (m > m0) gsync();  // the previous move's stores are visible
+        rc = apply_move(B, S, mv[m], fr, &S.st, &app);
         if (applied && lane_id() == 0) applied[m] = (int8_t)app;
-        if (rc != ST_OK) {
-            if (lane_id() == 0) s.stats[b] = st;
-            fail_block(s, b, rc);
-            return;
-        }
+        if (rc != ST_OK) break;
     }
-    if (lane_id() == 0) s.stats[b] = st;
+    wsync();
+    if (lane_id() < NF) {
+        const long long v = reinterpret_cast<const long long*>(&S.st)[lane_id()];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b]) + lane_id(), (unsigned long long)v);
+    }
+    if (rc != ST_OK) fail_block(s, b, rc);
 }
 
-__global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* mv, const int* off,
-                                               int8_t* applied) {
+__global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
+                                               const int* __restrict__ off, int8_t* applied) {
     __shared__ WaveLDS S;
     const int b = blockIdx.x;
     if (s.status[b] != 0) return;
+    scratch_init(S);
     run_block_moves(s, S, b, mv, off[b], off[b + 1], applied);
 }
 
-__global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* mv, const int* off,
-                                                    int n_steps, int n_blocks, int8_t* applied) {
+__global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* __restrict__ mv,
+                                                    const int* __restrict__ off, int n_steps, int n_blocks,
+                                                    int8_t* applied) {
     __shared__ WaveLDS S;
     const int b = blockIdx.x;
+    scratch_init(S);
     for (int t = 0; t < n_steps; ++t) {
         if (s.status[b] != 0) return;
         const int* o = off + (long long)t * (n_blocks + 1);
         run_block_moves(s, S, b, mv, o[b], o[b + 1], applied);
+        gsync();
     }
 }
 
@@ -320,6 +368,7 @@ struct kdt_ctx {
     std::vector<kdt_move_t> staged;
     std::vector<int32_t> staged_block;
     int sticky;
+    int device = 0;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
     size_t ev_used = 0;
@@ -469,6 +518,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->ws = (char*)dev_ws;
     c->L = L;
     c->sticky = KDT_OK;
+    (void)hipGetDevice(&c->device);
     c->pt_off.assign(block_off, block_off + n_blocks + 1);
     c->tri_off.resize(n_blocks + 1);
     c->tri_off[0] = 0;
@@ -664,7 +714,14 @@ int kdt_stats(kdt_ctx* c, kdt_stats_t* out) {
         out->tri_touched += s.tri_touched;
         out->alg_bytes += s.alg_bytes;
         out->errors += s.errors;
+        out->t_star += s.t_star;
+        out->t_locate += s.t_locate;
+        out->t_hole += s.t_hole;
+        out->t_insert += s.t_insert;
+        for (int i = 0; i < 16; ++i) out->hist[i] += s.hist[i];
     }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess) out->clock_khz = khz;
     return KDT_OK;
 }
 

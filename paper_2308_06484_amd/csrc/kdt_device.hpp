@@ -8,16 +8,31 @@
 // point by an infinitesimal that grows with its id.
 //
 // Layout of one block in HBM:
-//   tri[s]   32-byte record {v0, v1, v2, 0 | n0, n1, n2, 0}; v are local
-//            point indices, GHOST (-1) for the vertex at infinity (a ghost
-//            triangle keeps it in v2); n_e = 4 * slot + e' names the
-//            triangle across the edge opposite v_e and that edge's index e'
-//            in it.  A block of n points always holds exactly 2n - 2 records
-//            (real triangles plus one ghost per hull edge).
+//   tri[s]   64-byte record (one aligned half cache line):
+//              v  = {v0, v1, v2, 0}   local point indices; GHOST (-1) is the
+//                                     vertex at infinity, kept in v2
+//              n  = {n0, n1, n2, 0}   n_e = 4 * slot + e': the triangle across
+//                                     the edge opposite v_e, and that edge's
+//                                     index e' in it
+//              c01 = {x0, y0, x1, y1}, c2 = {x2, y2, 0, 0}: vertex positions
+//            A point changes position only by being deleted and inserted
+//            again, so the copies of its position in the records of its
+//            triangles are always current.  With them a walk step or a
+//            conflict test needs one record load and no other.
+//            A block of n points always holds exactly 2n - 2 records (real
+//            triangles plus one ghost per hull edge).
 //   xy[i]    int2 position of local point i
 //   vtri[i]  slot of one triangle incident to point i
 // Local point order follows global id order, so local indices serve as the
 // perturbation order.
+//
+// Write-back table.  A move reads every record it needs into a small hash
+// table in LDS (keyed by slot) and makes every change there; the changed
+// records, the incident-triangle updates and the new position go to memory
+// in one burst at the end of the move.  On this hardware the vector-memory
+// counter covers stores as well as loads, so a load issued after a store
+// waits for that store; keeping the stores to the end keeps every load of
+// the move free of that wait.  A move that fails leaves memory unchanged.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,19 +44,28 @@ constexpr int GHOST = -1;
 constexpr int WAVE = 64;
 constexpr int KMAX = 64;         // largest degree of a deleted vertex
 constexpr int TRIPLE_KMAX = 40;  // link-triple retriangulation limit
-constexpr int CMAX = 320;        // largest Bowyer-Watson cavity
-constexpr int BMAX = CMAX + 2;   // its boundary
+constexpr int HT = 256;          // write-back table entries (power of two)
+constexpr int HT_LIMIT = 200;    // entries a move may use (keeps probe chains short)
+constexpr int CMAX = 160;        // largest Bowyer-Watson cavity
+constexpr int BMAX = CMAX + 2;   // cavity boundary
+constexpr int VTMAX = KMAX + BMAX + 1;  // pending incident-triangle updates
+constexpr int EMK = 16;          // links up to this size use the closed-form triple decode and edge matrix
+
+constexpr int F_DIRTY = 1;  // table entry changed: write back
+constexpr int F_CAV = 2;    // table entry is in the current cavity
 
 // status codes (mirror kdt.h)
 constexpr int ST_OK = 0;
 constexpr int ST_ARG = -1;
+constexpr int ST_DEGEN = -4;
 constexpr int ST_CAPACITY = -5;
 constexpr int ST_INTERNAL = -8;
-constexpr int ST_DEGEN = -4;
 
-struct alignas(32) Tri {
+struct alignas(64) Tri {
     int4 v;
     int4 n;
+    int4 c01;
+    int4 c2;
 };
 
 struct BlockView {
@@ -55,47 +79,62 @@ struct BlockView {
 // per-block counters, owned by the block's wavefront (no atomics needed)
 struct BlockStats {
     long long applied, blocked, star_sum, cavity_sum, walk_sum, tri_touched, alg_bytes, errors;
+    // wall-clock ticks spent by the block's wavefront in each phase of a move
+    long long t_star, t_locate, t_hole, t_insert;
+    // applied moves by wavefront time, bucket b: [2^b, 2^(b+1)) wall-clock ticks
+    long long hist[16];
 };
 
 // per-wavefront scratch in LDS
 struct WaveLDS {
+    // star of the deleted point, counter-clockwise
     int star_slot[KMAX];
-    int link[KMAX];
-    int outref[KMAX];
+    int link[KMAX];      // link vertex q_s (star triangle s = (p, q_s, q_s+1))
+    int2 lxy[KMAX];      // its position
+    int outref[KMAX];    // triangle outside link edge (q_s, q_s+1)
+    int out_ent[KMAX];   // its table entry
     int edge_tri[KMAX];  // link edge s -> 4 * hole triangle + edge index
     int hole_key[KMAX];  // packed link indices (i, j, l) of hole triangles
-    Tri hole_rec[KMAX];
-    int cav_slot[CMAX];
-    Tri cav_rec[CMAX];
+    int hole_ent[KMAX];  // table entry of hole triangle h
+    // write-back table
+    int tkey[HT];  // slot, or -1
+    int tflag[HT];
+    Tri trec[HT];
+    int tused[HT];  // entries in use, in claim order
+    // the directed edges (u, w) of the hole triangles: 4 * triangle + edge
+    int emat[EMK * EMK];
+    // Bowyer-Watson cavity: table entries, boundary edges (a, b) with the
+    // surviving triangle behind them and the positions of a and b
+    int cav_ent[CMAX];
     int bnd_a[BMAX], bnd_b[BMAX], bnd_out[BMAX];
-    int cand[WAVE];
-    int ncav, nbnd, nhole, pad;
+    int2 bnd_pa[BMAX], bnd_pb[BMAX];
+    // incident-triangle updates: those of the deletion, then those of the
+    // insertion (a point in both lists gets the later value)
+    int vt_v[VTMAX], vt_s[VTMAX];
+    int nvt_del;
+    int bnd_slot[BMAX];  // slot of the fan triangle on boundary edge i
+    int bnd_ph[BMAX];    // its stored index of a (bits 0-1), b (2-3), q (4-5)
+    int nhole, pad[3];
+    BlockStats st;  // the block's counters while its wavefront works on it
 };
 
 // ---------------------------------------------------------------- wave ops
 
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    return (1ull << lane_id()) - 1ull;
-}
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 __device__ __forceinline__ int lanes_below(uint64_t m) { return __popcll(m & lanemask_lt()); }
-// LDS and global memory ordering between the lanes of the (single-wave)
-// workgroup: a workgroup barrier carries the needed fence.
-__device__ __forceinline__ void wsync() { __syncthreads(); }
-
-// Every slot and vertex index read from memory is checked against the
-// block's ranges before use, so corrupted state ends in an error code,
-// never in an access outside the block.
-__device__ __forceinline__ bool bad_slot(const BlockView& B, int s) {
-    return (unsigned)s >= (unsigned)B.ntri;
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((long long)m) - 1; }
+// Ordering between the lanes of the wavefront for LDS traffic: LDS
+// operations of one wavefront complete in issue order, so only the compiler
+// must be kept from moving memory operations across this point.
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
-__device__ __forceinline__ bool bad_vert(const BlockView& B, int v) {
-    return v != -1 && (unsigned)v >= (unsigned)B.n;
-}
-__device__ __forceinline__ bool bad_tri(const BlockView& B, const int4& v) {
-    return (unsigned)v.x >= (unsigned)B.n || (unsigned)v.y >= (unsigned)B.n || bad_vert(B, v.z);
-}
+// Full workgroup barrier with fence: global stores of the wavefront are
+// complete and visible before any later load (used between two moves).
+__device__ __forceinline__ void gsync() { __syncthreads(); }
 
 __device__ __forceinline__ int vget(const int4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : v.z);
@@ -105,81 +144,206 @@ __device__ __forceinline__ void vset(int4& v, int i, int val) {
     else if (i == 1) v.y = val;
     else v.z = val;
 }
+__device__ __forceinline__ int2 cget(const Tri& t, int i) {
+    return i == 0 ? make_int2(t.c01.x, t.c01.y)
+                  : (i == 1 ? make_int2(t.c01.z, t.c01.w) : make_int2(t.c2.x, t.c2.y));
+}
+__device__ __forceinline__ void cset(Tri& t, int i, int2 p) {
+    if (i == 0) { t.c01.x = p.x; t.c01.y = p.y; }
+    else if (i == 1) { t.c01.z = p.x; t.c01.w = p.y; }
+    else { t.c2.x = p.x; t.c2.y = p.y; }
+}
+__device__ __forceinline__ bool same(int2 a, int2 b) { return a.x == b.x && a.y == b.y; }
 
-// ---------------------------------------------------------------- predicates
-// Every coordinate is in [0, 2^24), so differences fit in 25 bits.
-
-// Twice the signed area of (a, b, c): > 0 counter-clockwise.  Exact.
-__device__ __forceinline__ long long orient(int2 a, int2 b, int2 c) {
-    return (long long)(b.x - a.x) * (long long)(c.y - a.y) -
-           (long long)(b.y - a.y) * (long long)(c.x - a.x);
+// Every slot and vertex index read from memory is checked against the
+// block's ranges before use, so corrupted state ends in an error code,
+// never in an access outside the block.
+__device__ __forceinline__ bool bad_slot(const BlockView& B, int s) {
+    return (unsigned)s >= (unsigned)B.ntri;
+}
+__device__ __forceinline__ bool bad_tri(const BlockView& B, const int4& v) {
+    return (unsigned)v.x >= (unsigned)B.n || (unsigned)v.y >= (unsigned)B.n ||
+           (v.z != GHOST && (unsigned)v.z >= (unsigned)B.n);
 }
 
-__device__ __noinline__ int incircle_exact(long long al, long long bl, long long cl,
-                                           long long m_bc, long long m_ca, long long m_ab) {
-    __int128 d = (__int128)al * m_bc + (__int128)bl * m_ca + (__int128)cl * m_ab;
+// ---------------------------------------------------------------- predicates
+// Every coordinate is in [0, 2^24), so differences are below 2^24 in
+// magnitude.
+
+// Twice the signed area of (a, b, c): > 0 counter-clockwise.  Exact in
+// doubles: each product is below 2^48 and their difference below 2^49.
+__device__ __forceinline__ double orient(int2 a, int2 b, int2 c) {
+#pragma clang fp contract(off)
+    const double abx = (double)(b.x - a.x), aby = (double)(b.y - a.y);
+    const double acx = (double)(c.x - a.x), acy = (double)(c.y - a.y);
+    return abx * acy - aby * acx;
+}
+
+__device__ __noinline__ int incircle_exact(double al, double bl, double cl, double m_bc, double m_ca,
+                                           double m_ab) {
+    const __int128 d = (__int128)(long long)al * (long long)m_bc +
+                       (__int128)(long long)bl * (long long)m_ca +
+                       (__int128)(long long)cl * (long long)m_ab;
     return (d > 0) - (d < 0);
 }
 
 // Sign of the incircle determinant (> 0: d strictly inside the circle of the
-// counter-clockwise a, b, c).  The three lifts |p - d|^2 and the three 2x2
-// minors are exact integers below 2^49, hence exact doubles; only the three
+// counter-clockwise a, b, c).  The lifts |p - d|^2 and the 2x2 minors are
+// integers below 2^49, computed exactly in doubles; only the three final
 // products and two sums round, so the computed value is within
 // 3u(1 + O(u)) * P of the true one, P the sum of the product magnitudes
 // (u = 2^-53).  A result larger than 4u * P in magnitude has the right sign;
-// otherwise the determinant is recomputed in 128-bit integers.
+// otherwise the determinant is recomputed in 128-bit integers from the same
+// exact lifts and minors.
 __device__ __forceinline__ int incircle(int2 a, int2 b, int2 c, int2 d) {
 #pragma clang fp contract(off)
-    long long adx = a.x - d.x, ady = a.y - d.y;
-    long long bdx = b.x - d.x, bdy = b.y - d.y;
-    long long cdx = c.x - d.x, cdy = c.y - d.y;
-    long long al = adx * adx + ady * ady;
-    long long bl = bdx * bdx + bdy * bdy;
-    long long cl = cdx * cdx + cdy * cdy;
-    long long m_bc = bdx * cdy - bdy * cdx;
-    long long m_ca = cdx * ady - cdy * adx;
-    long long m_ab = adx * bdy - ady * bdx;
-    double p1 = (double)al * (double)m_bc;
-    double p2 = (double)bl * (double)m_ca;
-    double p3 = (double)cl * (double)m_ab;
-    double det = (p1 + p2) + p3;
-    double perm = (fabs(p1) + fabs(p2)) + fabs(p3);
-    double bound = perm * 0x1p-51;
+    const double adx = (double)(a.x - d.x), ady = (double)(a.y - d.y);
+    const double bdx = (double)(b.x - d.x), bdy = (double)(b.y - d.y);
+    const double cdx = (double)(c.x - d.x), cdy = (double)(c.y - d.y);
+    const double al = adx * adx + ady * ady;
+    const double bl = bdx * bdx + bdy * bdy;
+    const double cl = cdx * cdx + cdy * cdy;
+    const double m_bc = bdx * cdy - bdy * cdx;
+    const double m_ca = cdx * ady - cdy * adx;
+    const double m_ab = adx * bdy - ady * bdx;
+    const double p1 = al * m_bc;
+    const double p2 = bl * m_ca;
+    const double p3 = cl * m_ab;
+    const double det = (p1 + p2) + p3;
+    const double perm = (fabs(p1) + fabs(p2)) + fabs(p3);
+    const double bound = perm * 0x1p-51;
     if (det > bound) return 1;
     if (-det > bound) return -1;
     return incircle_exact(al, bl, cl, m_bc, m_ca, m_ab);
 }
 
-__device__ __forceinline__ int sgn(long long v) { return (v > 0) - (v < 0); }
+__device__ __forceinline__ int sgn(double v) { return (v > 0) - (v < 0); }
 
-// Incircle with ties broken by the id lift: when a, b, c, d are exactly
-// cocircular, the point with the largest rank is lifted most and decides
+// Exact ties: the point with the largest rank is lifted most and decides
 // through the cofactor of its height in the lifted 4x4 determinant
 // (rows x, y, x^2+y^2, 1 in the order a, b, c, d).
-__device__ __forceinline__ int incircle_star(int2 a, int ra, int2 b, int rb, int2 c, int rc,
-                                             int2 d, int rd) {
-    int s = incircle(a, b, c, d);
-    if (s != 0) return s;
+__device__ __noinline__ int incircle_tie(int2 a, int ra, int2 b, int rb, int2 c, int rc, int2 d,
+                                         int rd) {
     if (ra > rb && ra > rc && ra > rd) return sgn(orient(b, c, d));
     if (rb > rc && rb > rd) return -sgn(orient(a, c, d));
     if (rc > rd) return sgn(orient(a, b, d));
     return -sgn(orient(a, b, c));
 }
 
+// Incircle with ties on exactly cocircular points broken by the id lift.
+__device__ __forceinline__ int incircle_star(int2 a, int ra, int2 b, int rb, int2 c, int rc,
+                                             int2 d, int rd) {
+    const int s = incircle(a, b, c, d);
+    if (s != 0) return s;
+    return incircle_tie(a, ra, b, rb, c, rc, d, rd);
+}
+
 // Ghost (a, b, inf) covers the open half-plane left of a->b and the open
 // segment ab; a new point there destroys it.
 __device__ __forceinline__ bool ghost_conflict(int2 a, int2 b, int2 q) {
-    long long o = orient(a, b, q);
+    const double o = orient(a, b, q);
     if (o != 0) return o > 0;
-    long long t1 = (long long)(q.x - a.x) * (b.x - a.x) + (long long)(q.y - a.y) * (b.y - a.y);
-    long long t2 = (long long)(q.x - b.x) * (a.x - b.x) + (long long)(q.y - b.y) * (a.y - b.y);
+    const long long t1 = (long long)(q.x - a.x) * (b.x - a.x) + (long long)(q.y - a.y) * (b.y - a.y);
+    const long long t2 = (long long)(q.x - b.x) * (a.x - b.x) + (long long)(q.y - b.y) * (a.y - b.y);
     return t1 > 0 && t2 > 0;
 }
 
 // Does inserting point q (rank rq) destroy triangle t?
-__device__ __forceinline__ bool conflicts(const BlockView& B, const Tri& t, int2 q, int rq) {
-    if (t.v.z == GHOST) return ghost_conflict(B.xy[t.v.x], B.xy[t.v.y], q);
-    return incircle_star(B.xy[t.v.x], t.v.x, B.xy[t.v.y], t.v.y, B.xy[t.v.z], t.v.z, q, rq) > 0;
+__device__ __forceinline__ bool conflicts(const Tri& t, int2 q, int rq) {
+    if (t.v.z == GHOST) return ghost_conflict(cget(t, 0), cget(t, 1), q);
+    return incircle_star(cget(t, 0), t.v.x, cget(t, 1), t.v.y, cget(t, 2), t.v.z, q, rq) > 0;
+}
+
+// ---------------------------------------------------------------- table
+
+__device__ __forceinline__ int thash(int s) { return (int)(((unsigned)s * 0x9E3779B1u) >> 24); }
+
+__device__ __forceinline__ void table_clear(WaveLDS& S) {
+    for (int h = lane_id(); h < HT; h += WAVE) {
+        S.tkey[h] = -1;
+        S.tflag[h] = 0;
+    }
+    wsync();
+}
+
+// Per-kernel setup of the wave's scratch: an empty table.
+__device__ __forceinline__ void scratch_init(WaveLDS& S) { table_clear(S); }
+
+// The t-th triple i < j < l < 16 in colex order (t < 560): l is the number
+// of tetrahedral numbers C(l'+1, 3) <= t, j the number of triangular numbers
+// C(j'+1, 2) <= t - C(l, 3); no loops, no tables.
+__device__ __forceinline__ void triple_of(int t, int* i, int* j, int* l) {
+    int L = 2;
+#pragma unroll
+    for (int x = 3; x < EMK; ++x) L += t >= x * (x - 1) * (x - 2) / 6;
+    const int r = t - L * (L - 1) * (L - 2) / 6;
+    int J = 1;
+#pragma unroll
+    for (int x = 2; x < EMK; ++x) J += r >= x * (x - 1) / 2;
+    *l = L;
+    *j = J;
+    *i = r - J * (J - 1) / 2;
+}
+
+// Entry of slot s, or -1.
+__device__ __forceinline__ int tfind(const WaveLDS& S, int s) {
+    int h = thash(s);
+    for (int i = 0; i < HT; ++i) {
+        const int k = S.tkey[h];
+        if (k == s) return h;
+        if (k == -1) return -1;
+        h = (h + 1) & (HT - 1);
+    }
+    return -1;
+}
+
+// Claim the entry of slot s for every lane with want set: found if present,
+// else created (linear probing, claimed by compare-and-swap).  *mine tells
+// the lane that created it.  -1 if the table is full.
+__device__ __forceinline__ int tclaim(WaveLDS& S, bool want, int s, bool* mine) {
+    *mine = false;
+    if (!want) return -1;
+    int h = thash(s);
+    for (int i = 0; i < HT; ++i) {
+        const int k = S.tkey[h];
+        if (k == s) return h;
+        if (k == -1) {
+            const int old = atomicCAS(&S.tkey[h], -1, s);
+            if (old == -1) { *mine = true; return h; }
+            if (old == s) return h;
+        }
+        h = (h + 1) & (HT - 1);
+    }
+    return -1;
+}
+
+// Table entry of slot s for every lane with want set, reading the record
+// from memory if it is not in the table yet.  Called by the whole wave.
+// *used counts the entries in use (wave-uniform); returns -1 on a full table.
+// Record the entries the lanes with `mine` set just claimed.
+__device__ __forceinline__ void tnote(WaveLDS& S, bool mine, int e, int* used) {
+    const uint64_t m = ballot(mine);
+    if (mine && *used + lanes_below(m) < HT) S.tused[*used + lanes_below(m)] = e;
+    *used += __popcll(m);
+}
+
+__device__ __forceinline__ int tget(const BlockView& B, WaveLDS& S, bool want, int s, int* used) {
+    bool mine;
+    const int e = tclaim(S, want, s, &mine);
+    if (mine) {
+        S.trec[e] = B.tri[s];
+        S.tflag[e] = 0;
+    }
+    tnote(S, mine, e, used);
+    wsync();
+    return e;
+}
+
+// Record of slot s as the move sees it (table first, memory else).
+__device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s) {
+    const int e = tfind(S, s);
+    if (e >= 0) return S.trec[e];
+    return B.tri[s];
 }
 
 // ---------------------------------------------------------------- walk
@@ -187,37 +351,39 @@ __device__ __forceinline__ bool conflicts(const BlockView& B, const Tri& t, int2
 // triangle that q destroys: a real triangle whose closed area holds q, or a
 // ghost whose half-plane holds q.  *hit gets the local index of a vertex
 // sitting exactly at q (-1 if none).  Returns -1 if the step limit is hit.
-__device__ int walk(const BlockView& B, int start, int2 q, int* hit, int* hops) {
+// TABLE: read through the move's write-back table (after changes).
+template <bool TABLE>
+__device__ int walk(const BlockView& B, const WaveLDS& S, int start, int2 q, int* hit, int* hops) {
     int cur = start, entry = -1;
     const int limit = 4 * B.ntri + 16;
     *hit = -1;
     for (int h = 0; h < limit; ++h) {
         if (bad_slot(B, cur)) return -1;
-        Tri t = B.tri[cur];
+        const Tri t = TABLE ? tread(B, S, cur) : B.tri[cur];
         if (bad_tri(B, t.v)) return -1;
+        const int2 p0 = cget(t, 0), p1 = cget(t, 1);
         if (t.v.z == GHOST) {
-            if (ghost_conflict(B.xy[t.v.x], B.xy[t.v.y], q)) {
+            if (ghost_conflict(p0, p1, q)) {
                 *hops += h + 1;
                 return cur;
             }
-            int r = t.n.z;
-            entry = r & 3;
-            cur = r >> 2;
+            entry = t.n.z & 3;
+            cur = t.n.z >> 2;
             continue;
         }
-        int2 p0 = B.xy[t.v.x], p1 = B.xy[t.v.y], p2 = B.xy[t.v.z];
+        const int2 p2 = cget(t, 2);
         int next = -1;
         if (entry != 0 && orient(p1, p2, q) < 0) next = 0;
         else if (entry != 1 && orient(p2, p0, q) < 0) next = 1;
         else if (entry != 2 && orient(p0, p1, q) < 0) next = 2;
         if (next < 0) {
-            if (p0.x == q.x && p0.y == q.y) *hit = t.v.x;
-            else if (p1.x == q.x && p1.y == q.y) *hit = t.v.y;
-            else if (p2.x == q.x && p2.y == q.y) *hit = t.v.z;
+            if (same(p0, q)) *hit = t.v.x;
+            else if (same(p1, q)) *hit = t.v.y;
+            else if (same(p2, q)) *hit = t.v.z;
             *hops += h + 1;
             return cur;
         }
-        int r = vget(t.n, next);
+        const int r = vget(t.n, next);
         entry = r & 3;
         cur = r >> 2;
     }
@@ -235,302 +401,451 @@ __device__ __forceinline__ int3 fan_phys(int a, int b) {
     return make_int3(0, 1, 2);
 }
 
-// Insert point qv at q into the block's DT* (Bowyer-Watson, Sec. IV).
-// `seed` is a triangle q destroys; f0, f1 are two free slots that take the
-// two triangles the insertion adds.  The cavity grows level by level: the
-// lanes test the frontier's neighbours, ballots and prefix counts compact
-// the survivors.  Returns ST_OK or an error code (the block is then
-// no longer valid and must be rebuilt).
-__device__ int insert_vertex(BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int f0, int f1,
-                             BlockStats* st) {
+// Insert point qv at q into the block's DT* (Bowyer-Watson, Sec. IV), in the
+// write-back table.  `seed` is a triangle q destroys; f0, f1 are two free
+// slots that take the two triangles the insertion adds.  The cavity grows
+// level by level: the lanes test the frontier's neighbours, ballots and
+// prefix counts compact the survivors.  *used: table entries in use;
+// *nvt: pending incident-triangle updates.  Returns ST_OK or an error code
+// (the table is then not to be written back).
+__device__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int f0, int f1,
+                             int* used, int* nvt, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, seed) || bad_slot(B, f0) || bad_slot(B, f1)) return ST_INTERNAL;
+    const int fetched0 = *used;
+    const int se = tget(B, S, lane == 0, seed, used);
+    const int se0 = __shfl(se, 0);
+    if (se0 < 0) return ST_CAPACITY;
+    if (bad_tri(B, S.trec[se0].v)) return ST_INTERNAL;
     if (lane == 0) {
-        S.cav_slot[0] = seed;
-        S.cav_rec[0] = B.tri[seed];
-        S.ncav = 1;
-        S.nbnd = 0;
+        S.cav_ent[0] = se0;
+        S.tflag[se0] |= F_CAV;
     }
     wsync();
-    if (bad_tri(B, S.cav_rec[0].v)) return ST_INTERNAL;
     int fs = 0, fe = 1;
-    int err = ST_OK;
-    int loaded = 1;
+    int ncav = 1, nbnd = 0;  // wave-uniform counts of S.cav_ent and S.bnd_*
     while (fs < fe) {
         const int ncand = 3 * (fe - fs);
         for (int base = 0; base < ncand; base += WAVE) {
             const int j = base + lane;
             const bool act = j < ncand;
             const int ci = fs + j / 3, e = j % 3;
-            int nref = 0, ns = -1;
-            bool incav = false, conf = false;
-            Tri nt;
             Tri ct;
+            int nref = 0, ns = 0;
             if (act) {
-                ct = S.cav_rec[ci];
+                ct = S.trec[S.cav_ent[ci]];
                 nref = vget(ct.n, e);
                 ns = nref >> 2;
-                const int nc = S.ncav;
-                for (int m = 0; m < nc; ++m)
-                    if (S.cav_slot[m] == ns) { incav = true; break; }
+            }
+            const bool okslot = act && !bad_slot(B, ns);
+            if (ballot(act && !okslot)) return ST_INTERNAL;
+            const int ne = tget(B, S, okslot, ns, used);
+            if (ballot(okslot && ne < 0) || *used > HT_LIMIT) return ST_CAPACITY;
+            bool incav = false, conf = false, bad = false;
+            if (act) {
+                incav = (S.tflag[ne] & F_CAV) != 0;
                 if (!incav) {
-                    if (bad_slot(B, ns)) {
-                        err = ST_INTERNAL;
-                    } else {
-                        nt = B.tri[ns];
-                        if (bad_tri(B, nt.v)) err = ST_INTERNAL;
-                        else conf = conflicts(B, nt, q, qv);
-                    }
+                    const Tri nt = S.trec[ne];
+                    bad = bad_tri(B, nt.v);
+                    conf = !bad && conflicts(nt, q, qv);
                 }
             }
-            if (ballot(err != ST_OK)) { err = ST_INTERNAL; break; }
-            const bool c1 = act && !incav && conf;
-            const uint64_t mc = ballot(c1);
-            loaded += __popcll(ballot(act && !incav));
-            if (c1) S.cand[lane] = ns;
-            wsync();
-            bool dup = false;
-            if (c1) {
-                uint64_t lower = mc & lanemask_lt();
-                while (lower) {
-                    int i = __ffsll((long long)lower) - 1;
-                    if (S.cand[i] == ns) { dup = true; break; }
-                    lower &= lower - 1;
-                }
-            }
-            const bool acc = c1 && !dup;
+            if (ballot(bad)) return ST_INTERNAL;
+            bool acc = false;
+            if (act && !incav && conf) acc = (atomicOr(&S.tflag[ne], F_CAV) & F_CAV) == 0;
             const bool bnd = act && !incav && !conf;
             const uint64_t macc = ballot(acc), mb = ballot(bnd);
-            const int nc0 = S.ncav, nb0 = S.nbnd;
             const int nacc = __popcll(macc), nbn = __popcll(mb);
-            if (nc0 + nacc > CMAX || nb0 + nbn > BMAX) { err = ST_CAPACITY; break; }
-            if (acc) {
-                int pos = nc0 + lanes_below(macc);
-                S.cav_slot[pos] = ns;
-                S.cav_rec[pos] = nt;
-            }
+            if (ncav + nacc > CMAX || nbnd + nbn > BMAX) return ST_CAPACITY;
+            if (acc) S.cav_ent[ncav + lanes_below(macc)] = ne;
             if (bnd) {
-                int pos = nb0 + lanes_below(mb);
+                const int pos = nbnd + lanes_below(mb);
                 S.bnd_a[pos] = vget(ct.v, (e + 1) % 3);
                 S.bnd_b[pos] = vget(ct.v, (e + 2) % 3);
+                S.bnd_pa[pos] = cget(ct, (e + 1) % 3);
+                S.bnd_pb[pos] = cget(ct, (e + 2) % 3);
                 S.bnd_out[pos] = nref;
             }
             wsync();
-            if (lane == 0) {
-                S.ncav = nc0 + nacc;
-                S.nbnd = nb0 + nbn;
-            }
-            wsync();
+            ncav += nacc;
+            nbnd += nbn;
         }
-        if (err) break;
         fs = fe;
-        fe = S.ncav;
+        fe = ncav;
     }
-    const int c = S.ncav, nb = S.nbnd;
-    if (!err && nb != c + 2) err = ST_INTERNAL;
-    if (err) return err;
+    const int c = ncav, nb = nbnd;
+    if (nb != c + 2) return ST_INTERNAL;
+    const int fetched = *used - fetched0;
 
-    // fan: one triangle (a, b, q) per boundary edge, written into the c
-    // cavity slots and the two free ones
+    // table entries of the two extra slots
+    bool mine;
+    const int fent = tclaim(S, lane < 2, lane == 0 ? f0 : f1, &mine);
+    tnote(S, mine, fent, used);
+    if (ballot(lane < 2 && fent < 0) || *used > HT) return ST_CAPACITY;
+    const int fe0 = __shfl(fent, 0), fe1 = __shfl(fent, 1);
+    wsync();
+
+    // fan: one triangle (a, b, q) per boundary edge, into the c cavity
+    // entries and the two extra ones
+    for (int i = lane; i < nb; i += WAVE) {
+        const int3 ph = fan_phys(S.bnd_a[i], S.bnd_b[i]);
+        S.bnd_slot[i] = i < c ? S.tkey[S.cav_ent[i]] : (i == c ? f0 : f1);
+        S.bnd_ph[i] = ph.x | (ph.y << 2) | (ph.z << 4);
+    }
+    wsync();
+    int err = 0;
     for (int i = lane; i < nb; i += WAVE) {
         const int a = S.bnd_a[i], b = S.bnd_b[i], out = S.bnd_out[i];
-        const int slot = i < c ? S.cav_slot[i] : (i == c ? f0 : f1);
-        const int3 ph = fan_phys(a, b);
+        const int ent = i < c ? S.cav_ent[i] : (i == c ? fe0 : fe1);
+        const int slot = S.bnd_slot[i];
+        const int phi = S.bnd_ph[i];
+        const int pa = phi & 3, pb = (phi >> 2) & 3, pq = phi >> 4;
         int jn = -1, jm = -1;  // fan triangles starting at b / ending at a
+#pragma unroll 8
         for (int m = 0; m < nb; ++m) {
-            if (S.bnd_a[m] == b) jn = m;
-            if (S.bnd_b[m] == a) jm = m;
+            jn = S.bnd_a[m] == b ? m : jn;
+            jm = S.bnd_b[m] == a ? m : jm;
         }
-        if (jn < 0 || jm < 0) { err = ST_INTERNAL; continue; }
-        const int sjn = jn < c ? S.cav_slot[jn] : (jn == c ? f0 : f1);
-        const int sjm = jm < c ? S.cav_slot[jm] : (jm == c ? f0 : f1);
-        const int3 pjn = fan_phys(S.bnd_a[jn], S.bnd_b[jn]);
-        const int3 pjm = fan_phys(S.bnd_a[jm], S.bnd_b[jm]);
+        const int oe = tfind(S, out >> 2);
+        if (jn < 0 || jm < 0 || oe < 0) { err = 1; continue; }
         Tri r;
         r.v = make_int4(0, 0, 0, 0);
         r.n = make_int4(0, 0, 0, 0);
-        vset(r.v, ph.x, a);
-        vset(r.v, ph.y, b);
-        vset(r.v, ph.z, qv);
-        vset(r.n, ph.z, out);                      // across (a, b)
-        vset(r.n, ph.x, sjn * 4 + pjn.y);          // across (b, q): jn's edge (q, b)
-        vset(r.n, ph.y, sjm * 4 + pjm.x);          // across (q, a): jm's edge (a, q)
-        B.tri[slot] = r;
-        reinterpret_cast<int*>(&B.tri[out >> 2].n)[out & 3] = slot * 4 + ph.z;
-        if (a != GHOST) B.vtri[a] = slot;
-        if (i == 0) B.vtri[qv] = slot;
+        r.c01 = make_int4(0, 0, 0, 0);
+        r.c2 = make_int4(0, 0, 0, 0);
+        vset(r.v, pa, a);
+        vset(r.v, pb, b);
+        vset(r.v, pq, qv);
+        if (a != GHOST) cset(r, pa, S.bnd_pa[i]);
+        if (b != GHOST) cset(r, pb, S.bnd_pb[i]);
+        cset(r, pq, q);
+        vset(r.n, pq, out);                                          // across (a, b)
+        vset(r.n, pa, S.bnd_slot[jn] * 4 + ((S.bnd_ph[jn] >> 2) & 3));  // across (b, q): jn's edge (q, b)
+        vset(r.n, pb, S.bnd_slot[jm] * 4 + (S.bnd_ph[jm] & 3));         // across (q, a): jm's edge (a, q)
+        S.trec[ent] = r;
+        S.tflag[ent] = F_DIRTY;
+        reinterpret_cast<int*>(&S.trec[oe].n)[out & 3] = slot * 4 + pq;
+        S.tflag[oe] |= F_DIRTY;
+        const int vi = *nvt + i;
+        S.vt_v[vi] = a;  // GHOST entries are skipped at write-back
+        S.vt_s[vi] = slot;
     }
-    const uint64_t bad = ballot(err != ST_OK);
+    if (ballot(err)) return ST_INTERNAL;
+    if (lane == 0) {
+        S.vt_v[*nvt + nb] = qv;
+        S.vt_s[*nvt + nb] = S.tkey[S.cav_ent[0]];
+    }
+    *nvt += nb + 1;
     wsync();
-    if (bad) return ST_INTERNAL;
     if (lane == 0 && st) {
         st->cavity_sum += c;
-        // records read: cavity + tested neighbours; written: fan; patches c+2;
-        // coordinates of tested vertices; vtri writes c+3
-        st->tri_touched += loaded + nb;
-        st->alg_bytes += 32LL * loaded + 8LL * loaded + 32LL * nb + 4LL * nb + 4LL * (nb + 1);
+        // records read: seed, cavity and tested neighbours not already at
+        // hand; written: the fan and the c + 2 patched neighbours; c + 3
+        // incident-triangle updates
+        st->tri_touched += fetched + 2 * nb;
+        st->alg_bytes += 64LL * fetched + 128LL * nb + 4LL * (nb + 1);
     }
     return ST_OK;
 }
 
-// ---------------------------------------------------------------- delete
-__device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
-
-// Remove point p from the block's DT* (the Delete step of Fig. 4).
-// The hole left by p's star is retriangulated from its link q_0..q_{k-1}
-// (counter-clockwise, with the vertex at infinity last when p is on the
-// hull): the new triangles are the triples q_i, q_j, q_l (i < j < l) that
-// are counter-clockwise and whose (perturbed) circle holds no other link
-// vertex -- for a ghost triple (q_i, q_j, inf), no link vertex beyond the
-// line q_i q_j.  These are the Delaunay triangles of the link vertices that
-// lie in the hole, i.e. exactly DT*(S - p) there.  The k - 2 new triangles
-// take the first k - 2 star slots; the last two star slots become free.
-// Returns k (> 0) or an error code (< 0) with the block unchanged.
-__device__ int remove_vertex(BlockView& B, WaveLDS& S, int p, BlockStats* st) {
+// Write back the move: changed records, then the incident-triangle updates
+// of the deletion, then those of the insertion (no point occurs twice in
+// one list; stores of one wavefront to one address land in program order,
+// so the insertion's value wins), and empty the table.
+__device__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, int nvt) {
     const int lane = lane_id();
-    // 1. star of p, counter-clockwise (every lane walks it identically)
-    int t = B.vtri[p];
-    if (bad_slot(B, t)) return ST_INTERNAL;
-    Tri r = B.tri[t];
-    if (bad_tri(B, r.v)) return ST_INTERNAL;
-    int pi = r.v.x == p ? 0 : (r.v.y == p ? 1 : (r.v.z == p ? 2 : -1));
-    if (pi < 0) return ST_INTERNAL;
-    const int start = t;
-    int k = 0, ghost_at = -1;
-    while (true) {
-        if (k >= KMAX) return ST_CAPACITY;
-        const int a = vget(r.v, (pi + 1) % 3);
-        if (lane == k) {
-            S.star_slot[k] = t;
-            S.link[k] = a;
-            S.outref[k] = vget(r.n, pi);
-        }
-        if (a == GHOST) ghost_at = k;
-        const int nr = vget(r.n, (pi + 1) % 3);
-        if (bad_slot(B, vget(r.n, pi) >> 2)) return ST_INTERNAL;
-        t = nr >> 2;
-        pi = ((nr & 3) + 1) % 3;
-        ++k;
-        if (t == start) break;
-        if (bad_slot(B, t) || pi > 2) return ST_INTERNAL;
-        r = B.tri[t];
-        if (bad_tri(B, r.v) || vget(r.v, pi) != p) return ST_INTERNAL;
+    for (int u = lane; u < used; u += WAVE) {
+        const int h = S.tused[u];
+        if (S.tflag[h] & F_DIRTY) B.tri[S.tkey[h]] = S.trec[h];
+    }
+    for (int i = lane; i < nvt_del; i += WAVE) {
+        const int v = S.vt_v[i];
+        if (v != GHOST) B.vtri[v] = S.vt_s[i];
+    }
+    for (int i = nvt_del + lane; i < nvt; i += WAVE) {
+        const int v = S.vt_v[i];
+        if (v != GHOST) B.vtri[v] = S.vt_s[i];
     }
     wsync();
+    for (int u = lane; u < used; u += WAVE) {
+        const int h = S.tused[u];
+        S.tkey[h] = -1;
+        S.tflag[h] = 0;
+    }
+    wsync();
+}
+
+// ---------------------------------------------------------------- delete
+
+// Gather the star of p counter-clockwise into S: star_slot, link (q_s) and
+// its position lxy, outref (the triangle across link edge q_s q_s+1), with
+// the vertex at infinity, if p is on the hull, rotated to the last place;
+// and the triangles outside the link edges into the table.  Two walkers
+// turn around p in opposite directions and meet halfway.
+// Returns the degree k (>= 3) or an error code.
+__device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int* used, BlockStats* st) {
+    const int lane = lane_id();
+    const int t0 = B.vtri[p];
+    if (bad_slot(B, t0)) return ST_INTERNAL;
+    const Tri r0 = B.tri[t0];
+    if (bad_tri(B, r0.v)) return ST_INTERNAL;
+    const int pi0 = r0.v.x == p ? 0 : (r0.v.y == p ? 1 : (r0.v.z == p ? 2 : -1));
+    if (pi0 < 0) return ST_INTERNAL;
+    // counter-clockwise entries at 0, 1, ...; clockwise ones at KMAX-1,
+    // KMAX-2, ...
+    if (lane == 0) {
+        S.star_slot[0] = t0;
+        S.link[0] = vget(r0.v, (pi0 + 1) % 3);
+        S.lxy[0] = cget(r0, (pi0 + 1) % 3);
+        S.outref[0] = vget(r0.n, pi0);
+    }
+    int na = 1, nc = 0;
+    int ccw_ref = vget(r0.n, (pi0 + 1) % 3), cw_ref = vget(r0.n, (pi0 + 2) % 3);
+    int last_ccw = t0, last_cw = t0;
+    while (true) {
+        if (na + nc + 2 > KMAX) return ST_CAPACITY;
+        const int cs = ccw_ref >> 2, ws = cw_ref >> 2;
+        if (cs == last_cw) break;
+        if (bad_slot(B, cs) || bad_slot(B, ws)) return ST_INTERNAL;
+        const Tri rc = B.tri[cs];
+        const Tri rw = B.tri[ws];
+        const int pc = ((ccw_ref & 3) + 1) % 3, pw = ((cw_ref & 3) + 2) % 3;
+        if (bad_tri(B, rc.v) || bad_tri(B, rw.v) || vget(rc.v, pc) != p || vget(rw.v, pw) != p)
+            return ST_INTERNAL;
+        if (lane == 0) {
+            S.star_slot[na] = cs;
+            S.link[na] = vget(rc.v, (pc + 1) % 3);
+            S.lxy[na] = cget(rc, (pc + 1) % 3);
+            S.outref[na] = vget(rc.n, pc);
+        }
+        ++na;
+        last_ccw = cs;
+        if (ws == cs) break;
+        if (lane == 0) {
+            const int d = KMAX - 1 - nc;
+            S.star_slot[d] = ws;
+            S.link[d] = vget(rw.v, (pw + 1) % 3);
+            S.lxy[d] = cget(rw, (pw + 1) % 3);
+            S.outref[d] = vget(rw.n, pw);
+        }
+        ++nc;
+        last_cw = ws;
+        ccw_ref = vget(rc.n, (pc + 1) % 3);
+        cw_ref = vget(rw.n, (pw + 2) % 3);
+        if ((cw_ref >> 2) == last_ccw) break;
+    }
+    const int k = na + nc;
+    wsync();
+    // move the clockwise entries next to the counter-clockwise ones and, if
+    // p is on the hull, rotate the vertex at infinity to the end
+    int slot = 0, link = 0, outr = 0;
+    int2 lxy = make_int2(0, 0);
+    if (lane < k) {
+        const int src = lane < na ? lane : KMAX - 1 - (k - 1 - lane);
+        slot = S.star_slot[src];
+        link = S.link[src];
+        lxy = S.lxy[src];
+        outr = S.outref[src];
+    }
+    const uint64_t gm = ballot(lane < k && link == GHOST);
+    const int rot = gm ? first_lane(gm) + 1 : 0;  // new index = old - rot (mod k)
+    if (ballot(lane < k && bad_slot(B, outr >> 2))) return ST_INTERNAL;
+    wsync();
+    // the triangles around the star, one per lane, in one round trip
+    const int oe = tget(B, S, lane < k, outr >> 2, used);
+    if (ballot(lane < k && oe < 0)) return ST_CAPACITY;
+    if (lane < k) {
+        const int d = (lane - rot + k) % k;
+        S.star_slot[d] = slot;
+        S.link[d] = link;
+        S.lxy[d] = lxy;
+        S.outref[d] = outr;
+        S.out_ent[d] = oe;
+    }
+    wsync();
+    if (lane == 0 && st) {
+        st->star_sum += k;
+        st->tri_touched += k + *used;
+        st->alg_bytes += 64LL * (k + *used) + 4;  // star and surrounding records, vtri[p]
+    }
+    return k;
+}
+
+// Is q inside the closed region of p's star (p at position pp), and does it
+// sit on a link vertex?  Star triangle s is (p, q_s, q_s+1); a ghost one is
+// tested as the half-plane it stands for.
+__device__ __forceinline__ void locate_in_star(const WaveLDS& S, int k, int2 pp, int2 q,
+                                               bool* in_star, bool* on_vertex) {
+    const int lane = lane_id();
+    bool in = false, on = false;
+    if (lane < k) {
+        const int a = S.link[lane], b = S.link[(lane + 1) % k];
+        const int2 pa = S.lxy[lane], pb = S.lxy[(lane + 1) % k];
+        if (b == GHOST) in = ghost_conflict(pp, pa, q);       // (p, q_s, inf)
+        else if (a == GHOST) in = ghost_conflict(pb, pp, q);  // (q_s+1, p, inf)
+        else in = orient(pp, pa, q) >= 0 && orient(pa, pb, q) >= 0 && orient(pb, pp, q) >= 0;
+        on = a != GHOST && same(pa, q);
+    }
+    *in_star = ballot(in) != 0;
+    *on_vertex = ballot(on) != 0;
+}
+
+__device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
+
+// Delete p from the block's DT* (the Delete step of Fig. 4), its star already
+// gathered by gather_star, in the write-back table.  The hole is
+// retriangulated from the link q_0..q_{k-1} (counter-clockwise, the vertex at
+// infinity last when p is on the hull): the new triangles are the triples
+// q_i, q_j, q_l (i < j < l) that are counter-clockwise and whose (perturbed)
+// circle holds no other link vertex -- for a ghost triple (q_i, q_j, inf),
+// no link vertex beyond the line q_i q_j.  These are the Delaunay triangles
+// of the link vertices that lie in the hole, i.e. exactly DT*(S - p) there.
+// The k - 2 new triangles take the first k - 2 star slots (entries
+// S.hole_ent); the last two star slots become free.  *nvt: pending
+// incident-triangle updates.  Returns ST_OK or an error code.
+__device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* used, int* nvt,
+                                  BlockStats* st) {
+    const int lane = lane_id();
     if (k < 3) return ST_INTERNAL;
     if (k > TRIPLE_KMAX) return ST_CAPACITY;
-    // 2. rotate so that the vertex at infinity, if any, comes last
-    if (ghost_at >= 0 && ghost_at != k - 1) {
-        int s0 = 0, s1 = 0, s2 = 0;
-        const int src = (lane + ghost_at + 1) % k;
-        if (lane < k) { s0 = S.star_slot[src]; s1 = S.link[src]; s2 = S.outref[src]; }
-        wsync();
-        if (lane < k) { S.star_slot[lane] = s0; S.link[lane] = s1; S.outref[lane] = s2; }
-        wsync();
-    }
-    const int lv = lane < k ? S.link[lane] : GHOST;
-    // 3. valid triples; lanes stride over pairs (i, j), each scans l > j
     if (lane == 0) S.nhole = 0;
     if (lane < k) S.edge_tri[lane] = -1;
     wsync();
-    const int npairs = k * (k - 1) / 2;
-    for (int pidx = lane; pidx < npairs; pidx += WAVE) {
-        // decode pidx -> (i, j), i < j, in the order (0,1), (0,2), (1,2), (0,3), ...
-        int j = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)pidx)) * 0.5f);
-        while (j * (j - 1) / 2 > pidx) --j;
-        while ((j + 1) * j / 2 <= pidx) ++j;
-        const int i = pidx - j * (j - 1) / 2;
-        const int vi = S.link[i], vj = S.link[j];
-        if (vi == GHOST || vj == GHOST) continue;
-        const int2 pi2 = B.xy[vi], pj2 = B.xy[vj];
-        for (int l = j + 1; l < k; ++l) {
-            const int vl = S.link[l];
-            bool ok = true;
-            if (vl == GHOST) {
-                for (int m = 0; m < k - 1 && ok; ++m) {
-                    if (m == i || m == j) continue;
-                    if (ghost_conflict(pi2, pj2, B.xy[S.link[m]])) ok = false;
-                }
+    // valid triples: lanes stride over the C(k,3) triples (i < j < l) in
+    // colex order, so each lane gets an equal share.  Link vertex m's id and
+    // position sit in lane m's registers and are broadcast to all lanes.
+    const int lv = lane < k ? S.link[lane] : GHOST;
+    const int2 lp = lane < k ? S.lxy[lane] : make_int2(0, 0);
+    const int ntrip = k * (k - 1) * (k - 2) / 6;
+    for (int t0 = 0; t0 < ntrip; t0 += WAVE) {
+        const int t = t0 + lane;
+        bool ok = t < ntrip;
+        int i = 0, j = 1, l = 2;
+        if (ok) {
+            if (k <= EMK) {
+                triple_of(t, &i, &j, &l);
             } else {
-                const int2 pl2 = B.xy[vl];
-                if (orient(pi2, pj2, pl2) <= 0) continue;
-                for (int m = 0; m < k && ok; ++m) {
-                    if (m == i || m == j || m == l) continue;
-                    const int vm = S.link[m];
-                    if (vm == GHOST) continue;
-                    if (incircle_star(pi2, vi, pj2, vj, pl2, vl, B.xy[vm], vm) >= 0) ok = false;
-                }
+                l = (int)cbrtf(6.0f * (float)t) + 1;
+                while (l * (l - 1) * (l - 2) / 6 > t) --l;
+                while ((l + 1) * l * (l - 1) / 6 <= t) ++l;
+                const int r = t - l * (l - 1) * (l - 2) / 6;
+                j = (int)sqrtf(2.0f * (float)r) + 1;
+                while (j * (j - 1) / 2 > r) --j;
+                while ((j + 1) * j / 2 <= r) ++j;
+                i = r - j * (j - 1) / 2;
             }
-            if (ok) {
-                int pos = atomicAdd(&S.nhole, 1);
-                if (pos < KMAX) S.hole_key[pos] = pack3(i, j, l);
-            }
+        }
+        const int vi = S.link[i], vj = S.link[j], vl = S.link[l];
+        const int2 pi2 = S.lxy[i], pj2 = S.lxy[j], pl2 = S.lxy[l];
+        // only l can be the vertex at infinity (it is last)
+        ok = ok && vi != GHOST && vj != GHOST;
+        const bool ghost = vl == GHOST;
+        ok = ok && (ghost || orient(pi2, pj2, pl2) > 0);
+        for (int m = 0; m < k; ++m) {
+            if (!ballot(ok)) break;
+            const int vm = __builtin_amdgcn_readlane(lv, m);
+            const int2 pm = make_int2(__builtin_amdgcn_readlane(lp.x, m), __builtin_amdgcn_readlane(lp.y, m));
+            if (!ok || vm == GHOST || m == i || m == j || m == l) continue;
+            if (ghost) ok = !ghost_conflict(pi2, pj2, pm);
+            else ok = incircle_star(pi2, vi, pj2, vj, pl2, vl, pm, vm) < 0;
+        }
+        if (ok) {
+            const int pos = atomicAdd(&S.nhole, 1);
+            if (pos < KMAX) S.hole_key[pos] = pack3(i, j, l);
         }
     }
     wsync();
     const int nh = S.nhole;
     if (nh != k - 2) return ST_INTERNAL;
-    // deterministic order: sort hole keys (rank sort, one lane per key)
-    int key = lane < nh ? S.hole_key[lane] : 0x7fffffff;
+    // deterministic order: sort the hole keys (rank sort, one lane per key)
+    const int key = lane < nh ? S.hole_key[lane] : 0x7fffffff;
     int rank = 0;
-    for (int m = 0; m < nh; ++m) {
-        int km = S.hole_key[m];
-        rank += km < key;
-    }
+#pragma unroll 8
+    for (int m = 0; m < nh; ++m) rank += S.hole_key[m] < key;
     wsync();
     if (lane < nh) S.hole_key[rank] = key;
+    const bool small = k <= EMK;
+    if (small)
+        for (int x = lane; x < k * EMK; x += WAVE) S.emat[x] = -1;
     wsync();
-    // 4. adjacency of the hole triangles
+    if (small && lane < nh) {
+        const int hk = S.hole_key[lane];
+        const int d0 = hk >> 16, d1 = (hk >> 8) & 255, d2 = hk & 255;
+        S.emat[d1 * EMK + d2] = lane * 4 + 0;
+        S.emat[d2 * EMK + d0] = lane * 4 + 1;
+        S.emat[d0 * EMK + d1] = lane * 4 + 2;
+    }
+    wsync();
+    // adjacency of the hole triangles
     int herr = 0;
+    Tri h;
     if (lane < nh) {
         const int hk = S.hole_key[lane];
-        const int c0 = hk >> 16, c1 = (hk >> 8) & 255, c2 = hk & 255;
-        const int cs[3] = {c0, c1, c2};
-        Tri h;
-        h.v = make_int4(S.link[c0], S.link[c1], S.link[c2], 0);
+        const int cs[3] = {hk >> 16, (hk >> 8) & 255, hk & 255};
+        h.v = make_int4(S.link[cs[0]], S.link[cs[1]], S.link[cs[2]], 0);
         h.n = make_int4(0, 0, 0, 0);
+        h.c01 = make_int4(S.lxy[cs[0]].x, S.lxy[cs[0]].y, S.lxy[cs[1]].x, S.lxy[cs[1]].y);
+        h.c2 = make_int4(0, 0, 0, 0);
+        if (h.v.z != GHOST) h.c2 = make_int4(S.lxy[cs[2]].x, S.lxy[cs[2]].y, 0, 0);
         for (int e = 0; e < 3; ++e) {
             const int u = cs[(e + 1) % 3], w = cs[(e + 2) % 3];
             int nref;
             if (w == (u + 1) % k) {  // link edge u: the triangle outside it
                 nref = S.outref[u];
                 S.edge_tri[u] = lane * 4 + e;
-            } else {  // diagonal: the hole triangle with edge (w, u)
+            } else if (small) {  // diagonal: the hole triangle with edge (w, u)
+                nref = S.emat[w * EMK + u];
+                if (nref < 0) herr = 1;
+                else nref = S.star_slot[nref >> 2] * 4 + (nref & 3);
+            } else {
                 nref = -1;
-                for (int m = 0; m < nh && nref < 0; ++m) {
-                    if (m == lane) continue;
+#pragma unroll 8
+                for (int m = 0; m < nh; ++m) {
                     const int mk = S.hole_key[m];
-                    const int d[3] = {mk >> 16, (mk >> 8) & 255, mk & 255};
-                    for (int f = 0; f < 3; ++f)
-                        if (d[(f + 1) % 3] == w && d[(f + 2) % 3] == u) nref = S.star_slot[m] * 4 + f;
+                    const int d0 = mk >> 16, d1 = (mk >> 8) & 255, d2 = mk & 255;
+                    // edge f of triangle m is (d[f+1], d[f+2])
+                    const int f = (d1 == w && d2 == u) ? 0 : (d2 == w && d0 == u) ? 1 : (d0 == w && d1 == u) ? 2 : -1;
+                    nref = (m != lane && f >= 0) ? m * 4 + f : nref;
                 }
                 if (nref < 0) herr = 1;
+                else nref = S.star_slot[nref >> 2] * 4 + (nref & 3);
             }
             vset(h.n, e, nref);
         }
-        S.hole_rec[lane] = h;
     }
     if (ballot(herr)) return ST_INTERNAL;
     wsync();
     if (ballot(lane < k && S.edge_tri[lane] < 0)) return ST_INTERNAL;
-    // 5. write the hole triangles, patch the outside neighbours, vtri
-    if (lane < nh) B.tri[S.star_slot[lane]] = S.hole_rec[lane];
+    // the hole triangles into the table, the outside neighbours patched
+    // there, incident triangles of the link vertices queued
+    bool mine;
+    const int he = tclaim(S, lane < nh, S.star_slot[lane < nh ? lane : 0], &mine);
+    tnote(S, mine, he, used);
+    if (ballot(lane < nh && !mine)) return ST_INTERNAL;  // star slots were not in the table
+    if (lane < nh) {
+        S.trec[he] = h;
+        S.tflag[he] = F_DIRTY;
+        S.hole_ent[lane] = he;
+    }
+    wsync();
     if (lane < k) {
         const int et = S.edge_tri[lane];
         const int hs = S.star_slot[et >> 2];
         const int o = S.outref[lane];
-        reinterpret_cast<int*>(&B.tri[o >> 2].n)[o & 3] = hs * 4 + (et & 3);
-        if (lv != GHOST) B.vtri[lv] = hs;
+        const int oe = S.out_ent[lane];
+        reinterpret_cast<int*>(&S.trec[oe].n)[o & 3] = hs * 4 + (et & 3);
+        S.tflag[oe] = F_DIRTY;
+        S.vt_v[*nvt + lane] = S.link[lane];
+        S.vt_s[*nvt + lane] = hs;
     }
+    *nvt += k;
     wsync();
     if (lane == 0 && st) {
-        st->star_sum += k;
-        st->tri_touched += k + nh;
-        // star records + link coordinates read; hole records written;
-        // k back-pointer patches; k vtri writes
-        st->alg_bytes += 32LL * k + 8LL * k + 32LL * nh + 4LL * k + 4LL * k;
+        st->tri_touched += nh;
+        // hole records written, k incident-triangle updates
+        st->alg_bytes += 64LL * nh + 4LL * k;
     }
-    return k;
+    return ST_OK;
 }
 
 }  // namespace kdt

@@ -33,10 +33,13 @@ class KDTError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("applied", "blocked", "star_sum", "cavity_sum", "walk_sum", "tri_touched",
-                 "alg_bytes", "errors")]
+                 "alg_bytes", "errors", "t_star", "t_locate", "t_hole", "t_insert", "clock_khz")] + \
+               [("hist", ctypes.c_int64 * 16)]
 
     def as_dict(self):
-        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+        d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "hist"}
+        d["hist"] = [int(v) for v in self.hist]
+        return d
 
 
 _L = None
