@@ -95,29 +95,71 @@ def main():
     log(f"generating grid1024 with {K + Wu} steps")
     w = W.grid1024(seed=args.seed, steps=K + Wu)
     dev = torch.device("cuda:0")
-    dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev)
     mv = torch.from_numpy(w["mv"]).to(dev)
-    off = torch.from_numpy(w["mv_off"]).to(dev)
-    torch.cuda.synchronize()
-    log("warmup")
-    if Wu:
-        dt.run(mv, off[:Wu].contiguous(), fused=args.fused)
-    dt.sync()
+    off_all = torch.from_numpy(w["mv_off"]).to(dev)
+    off_warm = off_all[:Wu].contiguous()
+    off_timed = off_all[Wu:Wu + K].contiguous()
+
+    def fresh(stream):
+        with torch.cuda.stream(stream):
+            dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev)
+            if Wu:
+                dt.run(mv, off_warm)
+            dt.sync()
+        return dt
+
+    # headline: one plain kernel launch per time step, HIP events around
+    # every launch (kdt_timing) and around the whole timed region
+    stream = torch.cuda.Stream(device=dev)
+    mode = "fused" if args.fused else "step"
+    dt = fresh(stream)
     s0 = dt.stats()
     dt.timing(True)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_host = time.perf_counter()
-    e0.record()
-    dt.run(mv, off[Wu:Wu + K].contiguous(), fused=args.fused)
-    e1.record()
-    torch.cuda.synchronize()
-    t_host = time.perf_counter() - t_host
+    with torch.cuda.stream(stream):
+        t_host = time.perf_counter()
+        e0.record(stream)
+        dt.run(mv, off_timed, mode=mode)
+        e1.record(stream)
+        stream.synchronize()
+        t_host = time.perf_counter() - t_host
     ms = e0.elapsed_time(e1)
     kern_ms, launches = dt.timing_read()
     dt.timing(False)
     dt.sync()
     s1 = dt.stats()
+    dt.close()
+
+    # the other launch forms on fresh contexts, same stream of moves
+    variants = {}
+    for name, vmode, graph, per_cu in [("graph_per_step", "step", True, None),
+                                       ("persistent_lpt", "persistent", False, 4),
+                                       ("graph_persistent_lpt", "persistent", True, 4),
+                                       ("fused", "fused", False, None)]:
+        d2 = fresh(stream)
+        if per_cu:
+            d2.set_launch(per_cu)
+        a0 = d2.stats()["applied"]
+        with torch.cuda.stream(stream):
+            g = d2.graph(mv, off_timed, mode=vmode) if graph else None
+            stream.synchronize()
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(stream)
+            if g is not None:
+                g.launch()
+            else:
+                d2.run(mv, off_timed, mode=vmode)
+            f1.record(stream)
+            stream.synchronize()
+        vms = f0.elapsed_time(f1)
+        d2.sync()
+        napp = d2.stats()["applied"] - a0
+        variants[name] = {"moves_per_s": napp / (vms / 1e3), "ms_per_step": vms / K}
+        log(f"variant {name}: {vms:.2f} ms, {napp / (vms / 1e3):.3e} moves/s")
+        if g is not None:
+            g.close()
+        d2.close()
+
     applied = s1["applied"] - s0["applied"]
     blocked = s1["blocked"] - s0["blocked"]
     alg = s1["alg_bytes"] - s0["alg_bytes"]
@@ -161,6 +203,7 @@ def main():
             "seed": args.seed,
         },
         "applied_moves": applied,
+        "variants": variants,
         "phase_us_per_move": phases,
         "move_time_hist": {f"<{(2 ** (i + 1)) / khz * 1e3:.2f}us": c
                            for i, c in enumerate([a - b for a, b in zip(s1["hist"], s0["hist"])]) if c},

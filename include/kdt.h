@@ -126,8 +126,27 @@ int kdt_step(kdt_ctx* ctx);
  * the result is the same. */
 #define KDT_RUN_PER_STEP 0
 #define KDT_RUN_FUSED 1
+#define KDT_RUN_PERSISTENT 2
+/* KDT_RUN_PERSISTENT launches, per step, a fixed grid of workgroups (a few
+ * per compute unit, see kdt_set_launch) that take blocks from a queue,
+ * largest blocks first, so blocks of uneven size share the machine evenly.
+ * All three forms give identical results. */
 int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
             int32_t n_steps, int8_t* applied, int32_t flags);
+
+/* Workgroups per compute unit of the persistent launch (1..64, default 4). */
+int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
+
+/* The same n_steps steps captured once as a HIP graph and replayed by
+ * kdt_graph_launch (each replay applies the same move stream again, from the
+ * state it finds).  The context's stream must not be the null stream.  The
+ * graph records the given pointers: the move stream and `applied` must stay
+ * valid while the graph lives.  kdt_graph_destroy releases it. */
+typedef struct kdt_graph kdt_graph;
+int kdt_graph_build(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
+                    int32_t n_steps, int8_t* applied, int32_t flags, kdt_graph** out);
+int kdt_graph_launch(kdt_ctx* ctx, kdt_graph* graph);
+void kdt_graph_destroy(kdt_graph* graph);
 
 /* Query the current triangulation (synchronises the stream).
  *   tris      dev int32 [cap][3]: real triangles as global ids,

@@ -262,6 +262,38 @@ __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t
     }
 }
 
+// One time step on a fixed grid of workgroups (a few per compute unit) that
+// take blocks from a queue in the given order -- largest expected cost
+// first -- until it is empty.  The last workgroup to leave resets the queue
+// for the next launch, so consecutive launches (and graph replays) need no
+// reset of their own.
+__global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_move_t* __restrict__ mv,
+                                                       const int* __restrict__ off,
+                                                       const int* __restrict__ order, int* queue,
+                                                       int n_blocks, int8_t* applied) {
+    __shared__ WaveLDS S;
+    __shared__ int next;
+    scratch_init(S);
+    while (true) {
+        if (lane_id() == 0) next = atomicAdd(&queue[0], 1);
+        wsync();
+        const int qi = next;
+        wsync();
+        if (qi >= n_blocks) break;
+        const int b = order[qi];
+        if (s.status[b] != 0) continue;
+        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied);
+        gsync();
+    }
+    if (lane_id() == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&queue[0], 0);
+            atomicExch(&queue[1], 0);
+        }
+    }
+}
+
 // query: number the real triangles of every block
 __global__ void __launch_bounds__(WAVE) k_qcount(DevState s, int* qmap, int* qcount) {
     const int b = blockIdx.x;
@@ -311,7 +343,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, qcount, qoff,
-        qtris, stage_mv, stage_off, sticky, total;
+        qtris, stage_mv, stage_off, sticky, lpt, queue, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -335,6 +367,8 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_mv = take(sizeof(kdt_move_t) * (size_t)std::max(max_staged, 1));
     L.stage_off = take(sizeof(int) * (B + 1));
     L.sticky = take(sizeof(int) * 4);
+    L.lpt = take(sizeof(int) * (B + 1));
+    L.queue = take(sizeof(int) * 4);
     L.total = o;
     return L;
 }
@@ -369,6 +403,8 @@ struct kdt_ctx {
     std::vector<int32_t> staged_block;
     int sticky;
     int device = 0;
+    int cus = 256;
+    int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
     size_t ev_used = 0;
@@ -545,6 +581,20 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.queue, 0, sizeof(int) * 4, s));
+    {
+        // queue order for the persistent launch: largest blocks first
+        std::vector<int> lpt(n_blocks);
+        for (int32_t b = 0; b < n_blocks; ++b) lpt[b] = b;
+        std::stable_sort(lpt.begin(), lpt.end(), [&](int x, int y) {
+            return c->pt_off[x + 1] - c->pt_off[x] > c->pt_off[y + 1] - c->pt_off[y];
+        });
+        rc |= check_hip(c, hipMemcpyAsync(w + L.lpt, lpt.data(), sizeof(int) * n_blocks, hipMemcpyHostToDevice, s));
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        c->cus = cus;
+    }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
     k_build<<<n_blocks, WAVE, 0, s>>>(c->dev, (const int*)(w + L.order));
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
@@ -602,24 +652,104 @@ int kdt_step(kdt_ctx* c) {
     return check_hip(c, hipGetLastError());
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueue n_steps time steps on the context's stream (timing events if on).
+int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_t n_steps,
+                  int8_t* applied, int32_t flags, bool timed) {
+    char* w = c->ws;
+    if (flags == KDT_RUN_FUSED) {
+        hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
+        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied);
+        if (timed) timing_end(c, e0);
+        return check_hip(c, hipGetLastError());
+    }
+    const int grid = std::max(1, std::min(c->B, c->cus * c->persist_per_cu));
+    for (int32_t t = 0; t < n_steps; ++t) {
+        const int32_t* off = step_off + (int64_t)t * (c->B + 1);
+        hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
+        if (flags == KDT_RUN_PERSISTENT)
+            k_step_persist<<<grid, WAVE, 0, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
+                                                         (int*)(w + c->L.queue), c->B, applied);
+        else
+            k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, applied);
+        if (timed) timing_end(c, e0);
+    }
+    return check_hip(c, hipGetLastError());
+}
+
+bool valid_flags(int32_t f) { return f == KDT_RUN_PER_STEP || f == KDT_RUN_FUSED || f == KDT_RUN_PERSISTENT; }
+
+}  // namespace
+
+struct kdt_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    kdt_ctx* ctx;
+};
+
+extern "C" {
+
 int kdt_run(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_t n_steps,
             int8_t* applied, int32_t flags) {
     if (!c || n_steps < 0 || (n_steps > 0 && (!moves || !step_off))) return KDT_E_ARG;
-    if (flags != KDT_RUN_PER_STEP && flags != KDT_RUN_FUSED) return KDT_E_ARG;
+    if (!valid_flags(flags)) return KDT_E_ARG;
     if (c->sticky != KDT_OK) return KDT_E_STATE;
     if (n_steps == 0) return KDT_OK;
-    if (flags == KDT_RUN_FUSED) {
-        hipEvent_t e0 = timing_begin(c);
-        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied);
-        timing_end(c, e0);
-        return check_hip(c, hipGetLastError());
+    return enqueue_steps(c, moves, step_off, n_steps, applied, flags, true);
+}
+
+int kdt_set_launch(kdt_ctx* c, int32_t persist_per_cu) {
+    if (!c || persist_per_cu < 1 || persist_per_cu > 64) return KDT_E_ARG;
+    c->persist_per_cu = persist_per_cu;
+    return KDT_OK;
+}
+
+int kdt_graph_build(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_t n_steps,
+                    int8_t* applied, int32_t flags, kdt_graph** out) {
+    if (!c || !out || n_steps < 1 || !moves || !step_off || !valid_flags(flags)) return KDT_E_ARG;
+    *out = nullptr;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    if (c->stream == nullptr) return KDT_E_STATE;  // the null stream cannot be captured
+    kdt_graph* g = new (std::nothrow) kdt_graph();
+    if (!g) return KDT_E_CAPACITY;
+    g->ctx = c;
+    if (check_hip(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal))) {
+        delete g;
+        return KDT_E_DEVICE;
     }
-    for (int32_t t = 0; t < n_steps; ++t) {
-        hipEvent_t e0 = timing_begin(c);
-        k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off + (int64_t)t * (c->B + 1), applied);
-        timing_end(c, e0);
+    const int rc = enqueue_steps(c, moves, step_off, n_steps, applied, flags, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (rc != KDT_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        c->sticky = KDT_E_DEVICE;
+        return KDT_E_DEVICE;
     }
-    return check_hip(c, hipGetLastError());
+    g->graph = graph;
+    if (check_hip(c, hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0))) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return KDT_E_DEVICE;
+    }
+    *out = g;
+    return KDT_OK;
+}
+
+int kdt_graph_launch(kdt_ctx* c, kdt_graph* g) {
+    if (!c || !g || g->ctx != c) return KDT_E_ARG;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    return check_hip(c, hipGraphLaunch(g->exec, c->stream));
+}
+
+void kdt_graph_destroy(kdt_graph* g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 int kdt_sync(kdt_ctx* c) {

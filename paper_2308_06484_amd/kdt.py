@@ -17,11 +17,12 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkdt.so")
 
 OK, E_ARG, E_RANGE, E_DUP, E_DEGEN, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
-RUN_PER_STEP, RUN_FUSED = 0, 1
+RUN_PER_STEP, RUN_FUSED, RUN_PERSISTENT = 0, 1, 2
 
 EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", "kdt_query",
            "kdt_query_canonical", "kdt_positions", "kdt_stats", "kdt_block_status", "kdt_sync",
-           "kdt_destroy", "kdt_strerror", "kdt_timing", "kdt_timing_read")
+           "kdt_destroy", "kdt_strerror", "kdt_timing", "kdt_timing_read", "kdt_set_launch",
+           "kdt_graph_build", "kdt_graph_launch", "kdt_graph_destroy")
 
 
 class KDTError(RuntimeError):
@@ -67,6 +68,11 @@ def _lib():
         L.kdt_destroy.restype = None
         L.kdt_timing.argtypes = [vp, i32]
         L.kdt_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.kdt_set_launch.argtypes = [vp, i32]
+        L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
+        L.kdt_graph_launch.argtypes = [vp, vp]
+        L.kdt_graph_destroy.argtypes = [vp]
+        L.kdt_graph_destroy.restype = None
         L.kdt_strerror.argtypes = [ctypes.c_int]
         L.kdt_strerror.restype = ctypes.c_char_p
         _L = L
@@ -92,6 +98,27 @@ def workspace_size(n, pt_off, max_staged=0):
     _check(_lib().kdt_workspace_size(int(n), len(pt_off) - 1, _ptr(pt_off), int(max_staged),
                                      ctypes.byref(out)), "kdt_workspace_size")
     return int(out.value)
+
+
+class Graph:
+    """A captured multi-step launch; keeps the tensors it records alive."""
+
+    def __init__(self, dt, handle, keep):
+        self.dt, self.handle, self.keep = dt, handle, keep
+
+    def launch(self):
+        _check(_lib().kdt_graph_launch(self.dt.ctx, self.handle), "kdt_graph_launch")
+
+    def close(self):
+        if self.handle:
+            _lib().kdt_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class KineticDT:
@@ -124,9 +151,20 @@ class KineticDT:
     def step(self):
         _check(_lib().kdt_step(self.ctx), "kdt_step")
 
-    def run(self, moves, step_off, n_steps=None, applied=None, fused=False):
+    def _check_stream(self, moves, step_off, applied):
+        assert moves.dtype == torch.int32 and moves.is_cuda and moves.is_contiguous()
+        assert step_off.dtype == torch.int32 and step_off.is_cuda and step_off.is_contiguous()
+        assert step_off.shape[-1] == self.B + 1
+        if applied is not None:
+            assert applied.dtype == torch.int8 and applied.is_cuda and applied.numel() >= moves.shape[0]
+
+    def run(self, moves, step_off, n_steps=None, applied=None, fused=False, mode=None):
         """moves: int32 device tensor [M, 4]; step_off: int32 device tensor
-        [T, B + 1]; applied: optional int8 device tensor [M]."""
+        [T, B + 1]; applied: optional int8 device tensor [M].
+        mode: "step" (default), "fused" or "persistent"."""
+        if mode is None:
+            mode = "fused" if fused else "step"
+        flags = {"step": RUN_PER_STEP, "fused": RUN_FUSED, "persistent": RUN_PERSISTENT}[mode]
         assert moves.dtype == torch.int32 and moves.is_cuda and moves.is_contiguous()
         assert step_off.dtype == torch.int32 and step_off.is_cuda and step_off.is_contiguous()
         assert step_off.shape[-1] == self.B + 1
@@ -135,9 +173,23 @@ class KineticDT:
         if applied is not None:
             assert applied.dtype == torch.int8 and applied.is_cuda and applied.numel() >= moves.shape[0]
         rc = _lib().kdt_run(self.ctx, ctypes.c_void_p(moves.data_ptr()), ctypes.c_void_p(step_off.data_ptr()),
-                            T, None if applied is None else ctypes.c_void_p(applied.data_ptr()),
-                            RUN_FUSED if fused else RUN_PER_STEP)
+                            T, None if applied is None else ctypes.c_void_p(applied.data_ptr()), flags)
         _check(rc, "kdt_run")
+
+    def set_launch(self, persist_per_cu):
+        _check(_lib().kdt_set_launch(self.ctx, int(persist_per_cu)), "kdt_set_launch")
+
+    def graph(self, moves, step_off, applied=None, mode="step"):
+        """Capture the move stream's steps as a HIP graph (needs a non-null
+        stream); returns a Graph with launch() and close()."""
+        self._check_stream(moves, step_off, applied)
+        flags = {"step": RUN_PER_STEP, "fused": RUN_FUSED, "persistent": RUN_PERSISTENT}[mode]
+        g = ctypes.c_void_p()
+        _check(_lib().kdt_graph_build(self.ctx, ctypes.c_void_p(moves.data_ptr()),
+                                      ctypes.c_void_p(step_off.data_ptr()), step_off.shape[0],
+                                      None if applied is None else ctypes.c_void_p(applied.data_ptr()),
+                                      flags, ctypes.byref(g)), "kdt_graph_build")
+        return Graph(self, g, (moves, step_off, applied))
 
     # ---- results
     def sync(self):
