@@ -175,7 +175,8 @@ def main():
     log("per applied move, us of one wavefront: " + ", ".join(f"{k} {v:.2f}" for k, v in phases.items())
         + f"; mean degree {(s1['star_sum'] - s0['star_sum']) / max(1, applied):.2f}"
         + f", mean cavity {(s1['cavity_sum'] - s0['cavity_sum']) / max(1, applied):.2f}"
-        + f", mean walk {(s1['walk_sum'] - s0['walk_sum']) / max(1, applied + blocked):.2f}")
+        + f", mean walk {(s1['walk_sum'] - s0['walk_sum']) / max(1, applied + blocked):.2f}"
+        + f", star-only path {(s1['fast'] - s0['fast']) / max(1, applied):.3f}")
     hist = [a - b for a, b in zip(s1["hist"], s0["hist"])]
     log("move time histogram (us upper edge: count): " + ", ".join(
         f"{(2 ** (i + 1)) / khz * 1e3:.2f}: {c}" for i, c in enumerate(hist) if c))

@@ -83,6 +83,9 @@ typedef struct kdt_stats_t {
     /* applied moves by the time one move took: bucket b counts moves of
      * [2^b, 2^(b+1)) wall-clock ticks */
     int64_t hist[16];
+    /* applied moves whose target lay inside the moved point's star and
+     * destroyed no triangle around it (the star polygon alone changed) */
+    int64_t fast;
 } kdt_stats_t;
 
 typedef struct kdt_ctx kdt_ctx;

@@ -173,7 +173,31 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
         return ST_OK;
     }
     const long long c2 = wall_clock64();
-    int rc = retriangulate_hole(B, S, k, &used, &nvt, st);
+    // fast path: q inside the star, p not on the hull, and no triangle
+    // around the star destroyed by q -- the star polygon alone changes
+    bool fast = in_star && S.link[k - 1] != GHOST && k + 1 <= EMK;
+    if (fast) fast = !ballot(lane < k && conflicts(S.trec[S.out_ent[lane]], q, p));
+    int rc;
+    if (fast) {
+        rc = fill_star(B, S, k, p, q, true, &used, &nvt, st);
+        if (rc != ST_OK) return rc;
+        commit(B, S, used, nvt, nvt);
+        if (lane == 0) B.xy[p] = q;
+        const long long c4 = wall_clock64();
+        if (lane == 0) {
+            const long long dt = c4 - c0;
+            st->hist[dt <= 1 ? 0 : min(15, 63 - __clzll(dt))] += 1;
+            st->t_star += c1 - c0;
+            st->t_locate += c2 - c1;
+            st->t_hole += c4 - c2;
+            st->applied += 1;
+            st->fast += 1;
+            st->alg_bytes += 16 + 8 + 8;
+        }
+        *applied = 1;
+        return ST_OK;
+    }
+    rc = fill_star(B, S, k, p, q, false, &used, &nvt, st);
     if (rc != ST_OK) return rc;
     const long long c3 = wall_clock64();
     // a triangle of DT*(S - p) that q destroys: the one the walk found
@@ -849,6 +873,7 @@ int kdt_stats(kdt_ctx* c, kdt_stats_t* out) {
         out->t_hole += s.t_hole;
         out->t_insert += s.t_insert;
         for (int i = 0; i < 16; ++i) out->hist[i] += s.hist[i];
+        out->fast += s.fast;
     }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess) out->clock_khz = khz;

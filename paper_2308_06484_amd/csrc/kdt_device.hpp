@@ -83,6 +83,7 @@ struct BlockStats {
     long long t_star, t_locate, t_hole, t_insert;
     // applied moves by wavefront time, bucket b: [2^b, 2^(b+1)) wall-clock ticks
     long long hist[16];
+    long long fast;  // moves done by the star-only path
 };
 
 // per-wavefront scratch in LDS
@@ -692,37 +693,62 @@ __device__ __forceinline__ void locate_in_star(const WaveLDS& S, int k, int2 pp,
 
 __device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
 
-// Delete p from the block's DT* (the Delete step of Fig. 4), its star already
-// gathered by gather_star, in the write-back table.  The hole is
-// retriangulated from the link q_0..q_{k-1} (counter-clockwise, the vertex at
-// infinity last when p is on the hull): the new triangles are the triples
-// q_i, q_j, q_l (i < j < l) that are counter-clockwise and whose (perturbed)
-// circle holds no other link vertex -- for a ghost triple (q_i, q_j, inf),
-// no link vertex beyond the line q_i q_j.  These are the Delaunay triangles
-// of the link vertices that lie in the hole, i.e. exactly DT*(S - p) there.
-// The k - 2 new triangles take the first k - 2 star slots (entries
-// S.hole_ent); the last two star slots become free.  *nvt: pending
-// incident-triangle updates.  Returns ST_OK or an error code.
-__device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* used, int* nvt,
-                                  BlockStats* st) {
+// The u-th pair i < j < 16 in colex order (u < 120), without loops.
+__device__ __forceinline__ void pair_of(int u, int* i, int* j) {
+    int J = 1;
+#pragma unroll
+    for (int x = 2; x < EMK; ++x) J += u >= x * (x - 1) / 2;
+    *j = J;
+    *i = u - J * (J - 1) / 2;
+}
+
+// Retriangulate p's star polygon, its star already gathered by gather_star,
+// in the write-back table.  Vertices: the link q_0..q_{k-1} (counter-
+// clockwise, the vertex at infinity last when p is on the hull) and, when
+// with_q, the new point qv at q as vertex k.
+//
+//  * Without q -- the Delete step of Fig. 4: the new triangles are the link
+//    triples q_i, q_j, q_l (i < j < l) that are counter-clockwise and whose
+//    perturbed circle holds no other link vertex -- for a ghost triple
+//    (q_i, q_j, inf), no link vertex beyond the line q_i q_j.  These are the
+//    Delaunay triangles of the link vertices inside the hole, i.e. exactly
+//    DT*(S - p) there; k - 2 of them take the first k - 2 star slots and the
+//    last two star slots become free.
+//  * With q -- Delete and Insert at once, used when q lies inside the star
+//    and destroys none of the triangles around it: then every link edge stays
+//    Delaunay, nothing outside the star changes, and the star polygon holds
+//    DT*(link + q) restricted to it: the link triples above that also keep q
+//    out of their circle, and the counter-clockwise triangles (q_i, q_j, q)
+//    whose circle holds no link vertex.  There are k of them, one per star
+//    slot.
+//
+// Lanes stride over the candidate triangles, each rejected at its first
+// violating vertex; link vertex m's id and position sit in lane m's
+// registers and are broadcast to all lanes.  *nvt: pending incident-triangle
+// updates.  Returns ST_OK or an error code.
+__device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
+                         int* nvt, BlockStats* st) {
     const int lane = lane_id();
     if (k < 3) return ST_INTERNAL;
-    if (k > TRIPLE_KMAX) return ST_CAPACITY;
+    if (k > TRIPLE_KMAX || (with_q && k + 1 > EMK)) return ST_CAPACITY;
     if (lane == 0) S.nhole = 0;
     if (lane < k) S.edge_tri[lane] = -1;
     wsync();
-    // valid triples: lanes stride over the C(k,3) triples (i < j < l) in
-    // colex order, so each lane gets an equal share.  Link vertex m's id and
-    // position sit in lane m's registers and are broadcast to all lanes.
     const int lv = lane < k ? S.link[lane] : GHOST;
     const int2 lp = lane < k ? S.lxy[lane] : make_int2(0, 0);
     const int ntrip = k * (k - 1) * (k - 2) / 6;
-    for (int t0 = 0; t0 < ntrip; t0 += WAVE) {
+    const int ncand = ntrip + (with_q ? k * (k - 1) / 2 : 0);
+    for (int t0 = 0; t0 < ncand; t0 += WAVE) {
         const int t = t0 + lane;
-        bool ok = t < ntrip;
+        bool ok = t < ncand;
         int i = 0, j = 1, l = 2;
+        bool qtri = false;
         if (ok) {
-            if (k <= EMK) {
+            if (t >= ntrip) {
+                pair_of(t - ntrip, &i, &j);
+                l = k;
+                qtri = true;
+            } else if (k <= EMK) {
                 triple_of(t, &i, &j, &l);
             } else {
                 l = (int)cbrtf(6.0f * (float)t) + 1;
@@ -735,12 +761,26 @@ __device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* us
                 i = r - j * (j - 1) / 2;
             }
         }
-        const int vi = S.link[i], vj = S.link[j], vl = S.link[l];
-        const int2 pi2 = S.lxy[i], pj2 = S.lxy[j], pl2 = S.lxy[l];
+        int vi = S.link[i], vj = S.link[j];
+        int2 pi2 = S.lxy[i], pj2 = S.lxy[j];
+        const int vl = qtri ? qv : S.link[l];
+        const int2 pl2 = qtri ? q : S.lxy[l];
         // only l can be the vertex at infinity (it is last)
         ok = ok && vi != GHOST && vj != GHOST;
-        const bool ghost = vl == GHOST;
-        ok = ok && (ghost || orient(pi2, pj2, pl2) > 0);
+        const bool ghost = !qtri && vl == GHOST;
+        if (qtri && ok) {  // orient (q_i, q_j, q) counter-clockwise
+            const double o = orient(pi2, pj2, q);
+            if (o < 0) {
+                const int ti = i; i = j; j = ti;
+                const int tv = vi; vi = vj; vj = tv;
+                const int2 tp = pi2; pi2 = pj2; pj2 = tp;
+            }
+            ok = o != 0;
+        } else {
+            ok = ok && (ghost || orient(pi2, pj2, pl2) > 0);
+        }
+        // a link triple must also keep q out of its circle
+        if (ok && with_q && !qtri) ok = incircle_star(pi2, vi, pj2, vj, pl2, vl, q, qv) < 0;
         for (int m = 0; m < k; ++m) {
             if (!ballot(ok)) break;
             const int vm = __builtin_amdgcn_readlane(lv, m);
@@ -756,17 +796,18 @@ __device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* us
     }
     wsync();
     const int nh = S.nhole;
-    if (nh != k - 2) return ST_INTERNAL;
-    // deterministic order: sort the hole keys (rank sort, one lane per key)
+    if (nh != (with_q ? k : k - 2)) return ST_INTERNAL;
+    // deterministic order: sort the keys (rank sort, one lane per key)
     const int key = lane < nh ? S.hole_key[lane] : 0x7fffffff;
     int rank = 0;
 #pragma unroll 8
     for (int m = 0; m < nh; ++m) rank += S.hole_key[m] < key;
     wsync();
     if (lane < nh) S.hole_key[rank] = key;
-    const bool small = k <= EMK;
+    const int nv = with_q ? k + 1 : k;  // vertices of the polygon (+ q)
+    const bool small = nv <= EMK;
     if (small)
-        for (int x = lane; x < k * EMK; x += WAVE) S.emat[x] = -1;
+        for (int x = lane; x < nv * EMK; x += WAVE) S.emat[x] = -1;
     wsync();
     if (small && lane < nh) {
         const int hk = S.hole_key[lane];
@@ -776,24 +817,29 @@ __device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* us
         S.emat[d0 * EMK + d1] = lane * 4 + 2;
     }
     wsync();
-    // adjacency of the hole triangles
+    // adjacency of the new triangles
     int herr = 0;
     Tri h;
+    bool has_q = false;
     if (lane < nh) {
         const int hk = S.hole_key[lane];
         const int cs[3] = {hk >> 16, (hk >> 8) & 255, hk & 255};
-        h.v = make_int4(S.link[cs[0]], S.link[cs[1]], S.link[cs[2]], 0);
+        const int2 c0 = S.lxy[cs[0]], c1 = S.lxy[cs[1]];
+        const bool q2 = cs[2] == k;  // only the last vertex can be q (index k)
+        has_q = q2;
+        const int v2 = q2 ? qv : S.link[cs[2]];
+        const int2 c2 = q2 ? q : S.lxy[cs[2]];
+        h.v = make_int4(S.link[cs[0]], S.link[cs[1]], v2, 0);
         h.n = make_int4(0, 0, 0, 0);
-        h.c01 = make_int4(S.lxy[cs[0]].x, S.lxy[cs[0]].y, S.lxy[cs[1]].x, S.lxy[cs[1]].y);
-        h.c2 = make_int4(0, 0, 0, 0);
-        if (h.v.z != GHOST) h.c2 = make_int4(S.lxy[cs[2]].x, S.lxy[cs[2]].y, 0, 0);
+        h.c01 = make_int4(c0.x, c0.y, c1.x, c1.y);
+        h.c2 = v2 != GHOST ? make_int4(c2.x, c2.y, 0, 0) : make_int4(0, 0, 0, 0);
         for (int e = 0; e < 3; ++e) {
             const int u = cs[(e + 1) % 3], w = cs[(e + 2) % 3];
             int nref;
-            if (w == (u + 1) % k) {  // link edge u: the triangle outside it
+            if (u < k && w < k && w == (u + 1) % k) {  // link edge u: the triangle outside it
                 nref = S.outref[u];
                 S.edge_tri[u] = lane * 4 + e;
-            } else if (small) {  // diagonal: the hole triangle with edge (w, u)
+            } else if (small) {  // inner edge: the new triangle with edge (w, u)
                 nref = S.emat[w * EMK + u];
                 if (nref < 0) herr = 1;
                 else nref = S.star_slot[nref >> 2] * 4 + (nref & 3);
@@ -816,8 +862,8 @@ __device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* us
     if (ballot(herr)) return ST_INTERNAL;
     wsync();
     if (ballot(lane < k && S.edge_tri[lane] < 0)) return ST_INTERNAL;
-    // the hole triangles into the table, the outside neighbours patched
-    // there, incident triangles of the link vertices queued
+    // the new triangles into the table, the outside neighbours patched there,
+    // incident triangles of the link vertices (and q) queued
     bool mine;
     const int he = tclaim(S, lane < nh, S.star_slot[lane < nh ? lane : 0], &mine);
     tnote(S, mine, he, used);
@@ -839,11 +885,20 @@ __device__ int retriangulate_hole(const BlockView& B, WaveLDS& S, int k, int* us
         S.vt_s[*nvt + lane] = hs;
     }
     *nvt += k;
+    if (with_q) {
+        const uint64_t mq = ballot(has_q);
+        if (!mq) return ST_INTERNAL;
+        if (lane == 0) {
+            S.vt_v[*nvt] = qv;
+            S.vt_s[*nvt] = S.star_slot[first_lane(mq)];
+        }
+        *nvt += 1;
+    }
     wsync();
     if (lane == 0 && st) {
         st->tri_touched += nh;
-        // hole records written, k incident-triangle updates
-        st->alg_bytes += 64LL * nh + 4LL * k;
+        // new records written, incident-triangle updates
+        st->alg_bytes += 64LL * nh + 4LL * (k + (with_q ? 1 : 0));
     }
     return ST_OK;
 }

@@ -35,7 +35,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("applied", "blocked", "star_sum", "cavity_sum", "walk_sum", "tri_touched",
                  "alg_bytes", "errors", "t_star", "t_locate", "t_hole", "t_insert", "clock_khz")] + \
-               [("hist", ctypes.c_int64 * 16)]
+               [("hist", ctypes.c_int64 * 16), ("fast", ctypes.c_int64)]
 
     def as_dict(self):
         d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "hist"}
