@@ -34,6 +34,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_grid1024_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("kdt.hip", "kdt_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2308_06484_amd", "csrc", f), "rb").read())
+    return d["traffic_bytes_per_launch"] if h.hexdigest()[:16] == d["source_sha256_16"] else None
+
+
 def copy_probe():
     """A plain device copy of known size (256 MiB read + 256 MiB written),
     used to scale the FETCH_SIZE / WRITE_SIZE counters."""
@@ -75,6 +89,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fused", action="store_true", help="time the fused multi-step launch instead")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -132,7 +147,7 @@ def main():
 
     # the other launch forms on fresh contexts, same stream of moves
     variants = {}
-    for name, vmode, graph, per_cu in [("graph_per_step", "step", True, None),
+    for name, vmode, graph, per_cu in [] if args.no_variants else [("graph_per_step", "step", True, None),
                                        ("persistent_lpt", "persistent", False, 4),
                                        ("graph_persistent_lpt", "persistent", True, 4),
                                        ("fused", "fused", False, None)]:
@@ -216,7 +231,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("k_run_fused" if args.fused else "k_step"),
             "kernel": "k_run_fused" if args.fused else "k_step",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg / max(1, launches),
