@@ -86,6 +86,7 @@ typedef struct kdt_stats_t {
     /* applied moves whose target lay inside the moved point's star and
      * destroyed no triangle around it (the star polygon alone changed) */
     int64_t fast;
+    int64_t rebuilt;  /* block steps done by the rebuild branch */
 } kdt_stats_t;
 
 typedef struct kdt_ctx kdt_ctx;
@@ -169,6 +170,15 @@ int kdt_query(kdt_ctx* ctx, int32_t* tris, int32_t* adj, int64_t* blk_off,
  * to a HOST buffer int32 [cap][3]; used to compare with a reference. */
 int kdt_query_canonical(kdt_ctx* ctx, int32_t* host_tris, int64_t cap, int64_t* n_tri);
 
+/* Order-independent 64-bit digest of every block's triangulation (host
+ * uint64 [n_blocks]; synchronises): the wrapping sum over its real triangles,
+ * each rotated to start at its smallest global id (a, b, c), of
+ * M(a ^ M(b ^ M(c))) with M the splitmix64 finaliser
+ * (z += 0x9E3779B97F4A7C15; z = (z ^ z>>30) * 0xBF58476D1CE4E5B9;
+ *  z = (z ^ z>>27) * 0x94D049BB133111EB; z ^ z>>31).  Equal triangulations
+ * give equal digests; used to compare runs cheaply. */
+int kdt_digest(kdt_ctx* ctx, uint64_t* host_per_block);
+
 /* Current positions: host int32 [n][2] (synchronises). */
 int kdt_positions(kdt_ctx* ctx, int32_t* host_xy);
 
@@ -185,6 +195,48 @@ int kdt_block_status(kdt_ctx* ctx, int32_t* host_status);
  * (and the pairs are released) when enable == 0. */
 int kdt_timing(kdt_ctx* ctx, int32_t enable);
 int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
+
+/* Repair or rebuild.  The paper's trade-off (Sec. I): points that move far
+ * are better served by rebuilding the triangulation than by updating it.
+ * Per block and time step the policy picks one branch; both end in the same
+ * DT* (it is unique), so the policy changes only the time taken.
+ *   REPAIR     delete + insert every move (default)
+ *   REBUILD    apply the moves to the positions (same move rule), then
+ *              rebuild the block's DT* from scratch (Bowyer-Watson)
+ *   THRESHOLD  rebuild iff sum over the block's moves of dist / spacing > tau,
+ *              spacing = sqrt(frame area / points)
+ *   MLP        rebuild iff the network's predicted log2 cost of rebuilding is
+ *              below that of repairing; mlp_w: dev float [KDT_MLP_PARAMS],
+ *              must stay valid while used
+ * The network: 16 features -> 32 ReLU -> 32 ReLU -> 2, parameters laid out
+ * as W1[32][16], b1[32], W2[32][32], b2[32], W3[2][32], b3[2]. */
+#define KDT_POLICY_REPAIR 0
+#define KDT_POLICY_REBUILD 1
+#define KDT_POLICY_THRESHOLD 2
+#define KDT_POLICY_MLP 3
+#define KDT_MLP_PARAMS 1666
+int kdt_set_policy(kdt_ctx* ctx, int32_t policy, float tau, const float* mlp_w);
+
+/* Per step and block log (dev float [cap_steps][n_blocks][KDT_LOG_FIELDS],
+ * a ring over the steps launched since this call; NULL / 0 turns it off):
+ * fields 0..15 the block's features for the step (log2 n, k, log2(1+k),
+ * sum d/s, log2(1+sum d/s), max d/s, log2(1+max d/s), mean d/s, #(d>s),
+ * #(d>4s), 100k/n, sum (d/s)^2/k, log2(1+sum d/s)*log2(1+k), log2 s,
+ * log2(1+k)/log2 n, 1), 16 branch taken (0 repair, 1 rebuild), 17 device
+ * clock ticks the branch took, 18 k.  Steps without moves are not logged. */
+#define KDT_LOG_FIELDS 20
+int kdt_set_log(kdt_ctx* ctx, float* log, int64_t cap_steps);
+
+/* MLP kernels (FP32, hand-written; stream = hipStream_t or NULL).
+ *   forward: out[n][2] = f(x[n][16])
+ *   grad:    grad[0..1665] = sum over samples of d/dw 0.5*|f(x)-y|^2,
+ *            grad[1666] = the summed loss (grad: dev float [1667])
+ *   train:   epochs of mini-batch gradient descent on the mean gradient,
+ *            w updated in place; scratch: dev float [1667] */
+int kdt_mlp_forward(const float* w, const float* x, int64_t n, float* out, void* stream);
+int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, float* grad, void* stream);
+int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                  float lr, float* scratch, void* stream);
 
 /* Wait for the stream; return the first sticky error, or KDT_OK. */
 int kdt_sync(kdt_ctx* ctx);

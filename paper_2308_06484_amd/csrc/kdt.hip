@@ -19,6 +19,7 @@
 
 #include "../../include/kdt.h"
 #include "kdt_device.hpp"
+#include "kdt_mlp.hpp"
 
 using namespace kdt;
 
@@ -38,6 +39,14 @@ struct DevState {
     int* status;
     BlockStats* stats;
     int* sticky;
+    const int* order;  // per-block insertion order (Hilbert order at init)
+    // repair-or-rebuild selection
+    int policy;          // KDT_POLICY_*
+    float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
+    const float* mlp_w;  // MLP parameters (policy MLP)
+    float* log;          // per step and block: LOG_FIELDS floats, or null
+    long long log_cap;   // steps the log holds (ring)
+    int n_blocks;
 };
 
 __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
@@ -69,14 +78,13 @@ __device__ __forceinline__ Tri make_tri(int a, int b, int c, int2 pa, int2 pb, i
     return t;
 }
 
-__global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
-    __shared__ WaveLDS S;
-    const int b = blockIdx.x;
+// Build block b's DT* from scratch (Bowyer-Watson insertion in the order
+// given), overwriting its records.  Returns ST_OK or an error code.
+__device__ int build_block(const DevState& s, WaveLDS& S, int b) {
     const int lane = lane_id();
     BlockView B = view_of(s, b);
-    const int* ord = order + s.pt_off[b];
+    const int* ord = s.order + s.pt_off[b];
     const int n = B.n;
-    scratch_init(S);
     // first triangle: the first two points and the first point off their line
     int a = ord[0], c1 = ord[1];
     int2 pa = B.xy[a], pb = B.xy[c1];
@@ -87,7 +95,7 @@ __global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
         const uint64_t m = ballot(off_line);
         if (m) kidx = base + first_lane(m);
     }
-    if (kidx < 0) { fail_block(s, b, ST_DEGEN); return; }
+    if (kidx < 0) return ST_DEGEN;
     const int c = ord[kidx];
     const int2 pc = B.xy[c];
     if (orient(pa, pb, pc) < 0) {
@@ -113,16 +121,25 @@ __global__ void __launch_bounds__(WAVE) k_build(DevState s, const int* order) {
         const int2 q = B.xy[v];
         int hit, hops = 0;
         const int seed = walk<false>(B, S, last, q, &hit, &hops);
-        if (seed < 0 || hit >= 0) { fail_block(s, b, ST_INTERNAL); return; }
+        if (seed < 0 || hit >= 0) return ST_INTERNAL;
         int used = 0, nvt = 0;
         const int rc = insert_vertex(B, S, v, q, seed, nt, nt + 1, &used, &nvt, nullptr);
-        if (rc != ST_OK) { fail_block(s, b, rc); return; }
+        if (rc != ST_OK) return rc;
         last = S.vt_s[nvt - 1];  // a triangle incident to v
         commit(B, S, used, 0, nvt);
         gsync();
         nt += 2;
     }
-    if (nt != B.ntri) { fail_block(s, b, ST_INTERNAL); return; }
+    if (nt != B.ntri) return ST_INTERNAL;
+    return ST_OK;
+}
+
+__global__ void __launch_bounds__(WAVE) k_build(DevState s) {
+    __shared__ WaveLDS S;
+    const int b = blockIdx.x;
+    scratch_init(S);
+    const int rc = build_block(s, S, b);
+    if (rc != ST_OK) fail_block(s, b, rc);
 }
 
 // One move of one block (Fig. 4): Delete p, Insert it at the target.
@@ -238,50 +255,200 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     return ST_OK;
 }
 
-__device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
-                                int m0, int m1, int8_t* applied) {
+// Rebuild branch: the block's moves are first checked against the move rule
+// with the block's current triangulation (left untouched until the rebuild)
+// and the list of points already moved this step; applied moves only change
+// positions.  Then the block's DT* is rebuilt from scratch.
+__device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv, int m0,
+                                   int m1, int8_t* applied, BlockStats* st) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
+    const int lane = lane_id();
+    int nmoved = 0;  // wave-uniform; S.dry_v / S.dry_q: moved points and their new places
+    for (int m = m0; m < m1; ++m) {
+        const kdt_move_t r = mv[m];
+        const int p = r.point, dir = r.dir, dist = r.dist;
+        if (p < 0 || p >= B.n || dir < 0 || dir > 3 || dist < 1) return ST_ARG;
+        const int2 o = B.xy[p];
+        long long qx = o.x, qy = o.y;
+        if (dir == 0) qx += dist;
+        else if (dir == 1) qx -= dist;
+        else if (dir == 2) qy += dist;
+        else qy -= dist;
+        bool ok = qx >= fr.x && qx < fr.z && qy >= fr.y && qy < fr.w;
+        const int2 q = make_int2((int)qx, (int)qy);
+        int prev = -1;  // p's entry in the moved list
+        if (ok) {
+            bool held = false;
+            for (int i = lane; i < nmoved; i += WAVE) {
+                held |= same(S.dry_q[i], q);
+                if (S.dry_v[i] == p) prev = i;
+            }
+            ok = !ballot(held);
+            const uint64_t mp = ballot(prev >= 0);
+            prev = mp ? __shfl(prev, first_lane(mp)) : -1;
+        }
+        if (ok) {
+            // a point of the old triangulation at q that has not moved away
+            int hit, hops = 0;
+            const int tq = walk<false>(B, S, B.vtri[p], q, &hit, &hops);
+            if (tq < 0) return ST_INTERNAL;
+            if (hit >= 0 && same(B.xy[hit], q)) ok = false;
+        }
+        if (ok) {
+            const int slot = prev >= 0 ? prev : nmoved;
+            if (slot >= DRYMAX) return ST_CAPACITY;
+            if (lane == 0) {
+                B.xy[p] = q;
+                S.dry_v[slot] = p;
+                S.dry_q[slot] = q;
+                st->applied += 1;
+            }
+            if (prev < 0) ++nmoved;
+            gsync();
+        } else if (lane == 0) {
+            st->blocked += 1;
+        }
+        if (applied && lane == 0) applied[m] = ok ? 1 : 0;
+    }
+    gsync();
+    table_clear(S);
+    const int rc = build_block(s, S, b);
+    if (lane == 0) {
+        st->rebuilt += 1;
+        st->alg_bytes += 64LL * B.ntri + 12LL * B.n;  // records written, positions read, vtri written
+        st->tri_touched += B.ntri;
+    }
+    return rc;
+}
+
+// The branch the policy takes for this block and step: 0 repair, 1 rebuild.
+__device__ int choose_branch(const DevState& s, const float* f) {
+    if (s.policy == KDT_POLICY_REBUILD) return 1;
+    if (s.policy == KDT_POLICY_THRESHOLD) return f[3] > s.tau ? 1 : 0;
+    if (s.policy != KDT_POLICY_MLP || !s.mlp_w) return 0;
+    // 16 -> 32 -> 32 -> 2: hidden unit j on lane j, inputs broadcast
+    const int lane = lane_id();
+    const float* W = s.mlp_w;
+    float h1 = 0.f;
+    if (lane < MLP_H) {
+        float a = W[MLP_B1 + lane];
+        for (int i = 0; i < MLP_IN; ++i) a += W[MLP_W1 + lane * MLP_IN + i] * f[i];
+        h1 = a > 0.f ? a : 0.f;
+    }
+    float a2 = lane < MLP_H ? W[MLP_B2 + lane] : 0.f;
+    for (int i = 0; i < MLP_H; ++i) {
+        const float hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, h1), i));
+        if (lane < MLP_H) a2 += W[MLP_W2 + lane * MLP_H + i] * hi;
+    }
+    const float h2 = lane < MLP_H && a2 > 0.f ? a2 : 0.f;
+    float o = lane < MLP_OUT ? W[MLP_B3 + lane] : 0.f;
+    for (int i = 0; i < MLP_H; ++i) {
+        const float hi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, h2), i));
+        if (lane < MLP_OUT) o += W[MLP_W3 + lane * MLP_H + i] * hi;
+    }
+    const float o0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), 0));
+    const float o1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), 1));
+    return o1 < o0 ? 1 : 0;
+}
+
+__device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
+                                int m0, int m1, int8_t* applied, long long step) {
+    BlockView B = view_of(s, b);
+    const int4 fr = s.frame[b];
+    const int lane = lane_id();
     // counters start at zero in LDS and are added to the block's totals at
     // the end (no load of the totals on the way in)
     constexpr int NF = sizeof(BlockStats) / sizeof(long long);
-    if (lane_id() < NF) reinterpret_cast<long long*>(&S.st)[lane_id()] = 0;
+    if (lane < NF) reinterpret_cast<long long*>(&S.st)[lane] = 0;
     wsync();
-    int rc = ST_OK;
-    for (int m = m0; m < m1; ++m) {
-        int app = 0;
-        if (m > m0) gsync();  // the previous move's stores are visible
-        rc = apply_move(B, S, mv[m], fr, &S.st, &app);
-        if (applied && lane_id() == 0) applied[m] = (int8_t)app;
-        if (rc != ST_OK) break;
+    const int k = m1 - m0;
+    const bool need_f = k > 0 && (s.policy != KDT_POLICY_REPAIR || s.log);
+    float f[MLP_IN];
+    int branch = 0;
+    if (need_f) {
+        // features from this step's move distances (wave reduction)
+        const float area = (float)(fr.z - fr.x) * (float)(fr.w - fr.y);
+        const float sp = sqrtf(area / (float)B.n);
+        float sum = 0.f, mx = 0.f, sq = 0.f, c1 = 0.f, c4 = 0.f;
+        for (int m = m0 + lane; m < m1; m += WAVE) {
+            const float r = (float)mv[m].dist / sp;
+            sum += r;
+            mx = fmaxf(mx, r);
+            sq += r * r;
+            c1 += r > 1.f ? 1.f : 0.f;
+            c4 += r > 4.f ? 1.f : 0.f;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sum += __shfl_xor(sum, off);
+            mx = fmaxf(mx, __shfl_xor(mx, off));
+            sq += __shfl_xor(sq, off);
+            c1 += __shfl_xor(c1, off);
+            c4 += __shfl_xor(c4, off);
+        }
+        const float ln = log2f((float)B.n), lk = log2f(1.f + (float)k);
+        f[0] = ln; f[1] = (float)k; f[2] = lk; f[3] = sum; f[4] = log2f(1.f + sum);
+        f[5] = mx; f[6] = log2f(1.f + mx); f[7] = sum / (float)k; f[8] = c1; f[9] = c4;
+        f[10] = 100.f * (float)k / (float)B.n; f[11] = sq / (float)k; f[12] = f[4] * lk;
+        f[13] = log2f(sp); f[14] = lk / ln; f[15] = 1.f;
+        branch = choose_branch(s, f);
     }
+    const long long c0 = wall_clock64();
+    int rc = ST_OK;
+    if (branch == 0) {
+        for (int m = m0; m < m1; ++m) {
+            int app = 0;
+            if (m > m0) gsync();  // the previous move's stores are visible
+            rc = apply_move(B, S, mv[m], fr, &S.st, &app);
+            if (applied && lane == 0) applied[m] = (int8_t)app;
+            if (rc != ST_OK) break;
+        }
+    } else {
+        rc = dry_run_and_rebuild(s, S, b, mv, m0, m1, applied, &S.st);
+    }
+    const long long c1 = wall_clock64();
     wsync();
-    if (lane_id() < NF) {
-        const long long v = reinterpret_cast<const long long*>(&S.st)[lane_id()];
-        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b]) + lane_id(), (unsigned long long)v);
+    if (need_f && s.log && s.log_cap > 0 && lane < LOG_FIELDS) {
+        const long long nb = (long long)(s.n_blocks);
+        float* rec = s.log + ((step % s.log_cap) * nb + b) * LOG_FIELDS;
+        float v = 0.f;
+        if (lane < MLP_IN) {
+            for (int i = 0; i < MLP_IN; ++i) v = lane == i ? f[i] : v;
+        } else if (lane == 16) {
+            v = (float)branch;
+        } else if (lane == 17) {
+            v = (float)(c1 - c0);
+        } else if (lane == 18) {
+            v = (float)k;
+        }
+        rec[lane] = v;
+    }
+    if (lane < NF) {
+        const long long v = reinterpret_cast<const long long*>(&S.st)[lane];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b]) + lane, (unsigned long long)v);
     }
     if (rc != ST_OK) fail_block(s, b, rc);
 }
 
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
-                                               const int* __restrict__ off, int8_t* applied) {
+                                               const int* __restrict__ off, int8_t* applied, long long step) {
     __shared__ WaveLDS S;
     const int b = blockIdx.x;
     if (s.status[b] != 0) return;
     scratch_init(S);
-    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied);
+    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step);
 }
 
 __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* __restrict__ mv,
                                                     const int* __restrict__ off, int n_steps, int n_blocks,
-                                                    int8_t* applied) {
+                                                    int8_t* applied, long long step0) {
     __shared__ WaveLDS S;
     const int b = blockIdx.x;
     scratch_init(S);
     for (int t = 0; t < n_steps; ++t) {
         if (s.status[b] != 0) return;
         const int* o = off + (long long)t * (n_blocks + 1);
-        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied);
+        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied, step0 + t);
         gsync();
     }
 }
@@ -294,7 +461,7 @@ __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t
 __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_move_t* __restrict__ mv,
                                                        const int* __restrict__ off,
                                                        const int* __restrict__ order, int* queue,
-                                                       int n_blocks, int8_t* applied) {
+                                                       int n_blocks, int8_t* applied, long long step) {
     __shared__ WaveLDS S;
     __shared__ int next;
     scratch_init(S);
@@ -306,7 +473,7 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
         if (qi >= n_blocks) break;
         const int b = order[qi];
         if (s.status[b] != 0) continue;
-        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied);
+        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step);
         gsync();
     }
     if (lane_id() == 0) {
@@ -316,6 +483,57 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
             atomicExch(&queue[1], 0);
         }
     }
+}
+
+// ------------------------------------------------------------------ MLP
+
+__global__ void k_mlp_forward(const float* __restrict__ W, const float* __restrict__ X, long long n,
+                              float* __restrict__ out) {
+    __shared__ float w[MLP_NPARAM];
+    for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) w[i] = W[i];
+    __syncthreads();
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float x[MLP_IN], h1[MLP_H], h2[MLP_H], o[MLP_OUT];
+    for (int i = 0; i < MLP_IN; ++i) x[i] = X[s * MLP_IN + i];
+    mlp_forward1(w, x, h1, h2, o);
+    for (int i = 0; i < MLP_OUT; ++i) out[s * MLP_OUT + i] = o[i];
+}
+
+// Sum over samples of the gradient of 0.5 * |out - y|^2, and of the loss,
+// added into g[0..MLP_NPARAM) and g[MLP_NPARAM].
+__global__ void k_mlp_grad(const float* __restrict__ W, const float* __restrict__ X,
+                           const float* __restrict__ Y, long long n, float* g) {
+    __shared__ float w[MLP_NPARAM];
+    __shared__ float acc[MLP_NPARAM + 1];
+    for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) {
+        w[i] = W[i];
+        acc[i] = 0.f;
+    }
+    if (threadIdx.x == 0) acc[MLP_NPARAM] = 0.f;
+    __syncthreads();
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        float x[MLP_IN], y[MLP_OUT];
+        for (int i = 0; i < MLP_IN; ++i) x[i] = X[s * MLP_IN + i];
+        for (int i = 0; i < MLP_OUT; ++i) y[i] = Y[s * MLP_OUT + i];
+        const float l = mlp_backward1(w, x, y, acc);
+        atomicAdd(&acc[MLP_NPARAM], l);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= MLP_NPARAM; i += blockDim.x)
+        if (acc[i] != 0.f) atomicAdd(&g[i], acc[i]);
+}
+
+__global__ void k_fill(float* p, long long n, float v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// W -= lr * g / n (mean gradient step)
+__global__ void k_mlp_sgd(float* W, const float* g, float lr, float inv_n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < MLP_NPARAM) W[i] -= lr * g[i] * inv_n;
 }
 
 // query: number the real triangles of every block
@@ -359,6 +577,35 @@ __global__ void __launch_bounds__(WAVE) k_qwrite(DevState s, const int* qmap, co
             }
         }
     }
+}
+
+// Order-independent digest of a block's triangulation: the wrapping sum,
+// over its real triangles rotated to start at their smallest global id
+// (a, b, c), of mix(a ^ mix(b ^ mix(c))), mix = splitmix64's finaliser.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(WAVE) k_digest(DevState s, unsigned long long* out) {
+    const int b = blockIdx.x;
+    BlockView B = view_of(s, b);
+    const unsigned long long g0 = (unsigned long long)s.pt_off[b];
+    unsigned long long acc = 0;
+    for (int i = lane_id(); i < B.ntri; i += WAVE) {
+        const Tri t = B.tri[i];
+        if (t.v.z == GHOST) continue;
+        int r = 0;
+        if (t.v.y < vget(t.v, r)) r = 1;
+        if (t.v.z < vget(t.v, r)) r = 2;
+        const unsigned long long a = g0 + vget(t.v, r), bb = g0 + vget(t.v, (r + 1) % 3),
+                                 c = g0 + vget(t.v, (r + 2) % 3);
+        acc += mix64(a ^ mix64(bb ^ mix64(c)));
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if (lane_id() == 0) out[b] = acc;
 }
 
 // ------------------------------------------------------------------ host
@@ -428,6 +675,7 @@ struct kdt_ctx {
     int sticky;
     int device = 0;
     int cus = 256;
+    long long step_count = 0;  // time steps launched so far (log index)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
@@ -594,6 +842,13 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->dev.status = (int*)(w + L.status);
     c->dev.stats = (BlockStats*)(w + L.stats);
     c->dev.sticky = (int*)(w + L.sticky);
+    c->dev.order = (const int*)(w + L.order);
+    c->dev.policy = KDT_POLICY_REPAIR;
+    c->dev.tau = 0.f;
+    c->dev.mlp_w = nullptr;
+    c->dev.log = nullptr;
+    c->dev.log_cap = 0;
+    c->dev.n_blocks = n_blocks;
     hipStream_t s = c->stream;
     int rc = KDT_OK;
     // The host arrays are pageable: these copies complete before returning.
@@ -620,7 +875,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
         c->cus = cus;
     }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
-    k_build<<<n_blocks, WAVE, 0, s>>>(c->dev, (const int*)(w + L.order));
+    k_build<<<n_blocks, WAVE, 0, s>>>(c->dev);
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
     rc = check_hip(c, hipStreamSynchronize(s));
     if (rc != KDT_OK) { delete c; return rc; }
@@ -671,7 +926,7 @@ int kdt_step(kdt_ctx* c) {
     if (rc != KDT_OK) return KDT_E_DEVICE;
     hipEvent_t e0 = timing_begin(c);
     k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
-                                         (const int*)(w + c->L.stage_off), nullptr);
+                                         (const int*)(w + c->L.stage_off), nullptr, c->step_count++);
     timing_end(c, e0);
     return check_hip(c, hipGetLastError());
 }
@@ -686,7 +941,9 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
     char* w = c->ws;
     if (flags == KDT_RUN_FUSED) {
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
-        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied);
+        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied,
+                                                  c->step_count);
+        c->step_count += n_steps;
         if (timed) timing_end(c, e0);
         return check_hip(c, hipGetLastError());
     }
@@ -696,9 +953,10 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
         if (flags == KDT_RUN_PERSISTENT)
             k_step_persist<<<grid, WAVE, 0, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
-                                                         (int*)(w + c->L.queue), c->B, applied);
+                                                         (int*)(w + c->L.queue), c->B, applied, c->step_count);
         else
-            k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, applied);
+            k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, applied, c->step_count);
+        c->step_count++;
         if (timed) timing_end(c, e0);
     }
     return check_hip(c, hipGetLastError());
@@ -776,6 +1034,54 @@ void kdt_graph_destroy(kdt_graph* g) {
     delete g;
 }
 
+int kdt_set_policy(kdt_ctx* c, int32_t policy, float tau, const float* mlp_w) {
+    if (!c || policy < KDT_POLICY_REPAIR || policy > KDT_POLICY_MLP) return KDT_E_ARG;
+    if (policy == KDT_POLICY_MLP && !mlp_w) return KDT_E_ARG;
+    c->dev.policy = policy;
+    c->dev.tau = tau;
+    c->dev.mlp_w = mlp_w;
+    return KDT_OK;
+}
+
+int kdt_set_log(kdt_ctx* c, float* log, int64_t cap_steps) {
+    if (!c || cap_steps < 0 || (cap_steps > 0 && !log)) return KDT_E_ARG;
+    c->dev.log = cap_steps > 0 ? log : nullptr;
+    c->dev.log_cap = cap_steps;
+    c->step_count = 0;
+    return KDT_OK;
+}
+
+int kdt_mlp_forward(const float* w, const float* x, int64_t n, float* out, void* stream) {
+    if (!w || n < 0 || (n > 0 && (!x || !out))) return KDT_E_ARG;
+    if (n == 0) return KDT_OK;
+    k_mlp_forward<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(w, x, n, out);
+    return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;
+}
+
+int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, float* grad, void* stream) {
+    if (!w || !grad || n < 1 || !x || !y) return KDT_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    k_fill<<<(KDT_MLP_PARAMS + 1 + 255) / 256, 256, 0, s>>>(grad, KDT_MLP_PARAMS + 1, 0.f);
+    k_mlp_grad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, x, y, n, grad);
+    return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;
+}
+
+int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                  float lr, float* scratch, void* stream) {
+    if (!w || !x || !y || !scratch || n < 1 || epochs < 0 || batch < 1) return KDT_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t e = 0; e < epochs; ++e) {
+        for (int64_t b0 = 0; b0 < n; b0 += batch) {
+            const int64_t nb = std::min<int64_t>(batch, n - b0);
+            k_fill<<<(KDT_MLP_PARAMS + 1 + 255) / 256, 256, 0, s>>>(scratch, KDT_MLP_PARAMS + 1, 0.f);
+            k_mlp_grad<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT,
+                                                                   nb, scratch);
+            k_mlp_sgd<<<(KDT_MLP_PARAMS + 255) / 256, 256, 0, s>>>(w, scratch, lr, 1.f / (float)nb);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;
+}
+
 int kdt_sync(kdt_ctx* c) {
     if (!c) return KDT_E_ARG;
     if (c->sticky != KDT_OK) return c->sticky;
@@ -844,6 +1150,19 @@ int kdt_query_canonical(kdt_ctx* c, int32_t* host_tris, int64_t cap, int64_t* n_
     return KDT_OK;
 }
 
+int kdt_digest(kdt_ctx* c, uint64_t* host_per_block) {
+    if (!c || !host_per_block) return KDT_E_ARG;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    unsigned long long* d = (unsigned long long*)(c->ws + c->L.qtris);  // query staging, >= 8 B per block
+    k_digest<<<c->B, WAVE, 0, c->stream>>>(c->dev, d);
+    if (check_hip(c, hipGetLastError())) return KDT_E_DEVICE;
+    if (check_hip(c, hipMemcpyAsync(host_per_block, d, sizeof(uint64_t) * c->B, hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipStreamSynchronize(c->stream)))
+        return KDT_E_DEVICE;
+    return KDT_OK;
+}
+
 int kdt_positions(kdt_ctx* c, int32_t* host_xy) {
     if (!c || !host_xy) return KDT_E_ARG;
     int rc = kdt_sync(c);
@@ -874,6 +1193,7 @@ int kdt_stats(kdt_ctx* c, kdt_stats_t* out) {
         out->t_insert += s.t_insert;
         for (int i = 0; i < 16; ++i) out->hist[i] += s.hist[i];
         out->fast += s.fast;
+        out->rebuilt += s.rebuilt;
     }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess) out->clock_khz = khz;

@@ -49,6 +49,7 @@ constexpr int HT_LIMIT = 200;    // entries a move may use (keeps probe chains s
 constexpr int CMAX = 160;        // largest Bowyer-Watson cavity
 constexpr int BMAX = CMAX + 2;   // cavity boundary
 constexpr int VTMAX = KMAX + BMAX + 1;  // pending incident-triangle updates
+constexpr int DRYMAX = 256;     // moves of one block in one step on the rebuild branch
 constexpr int EMK = 16;          // links up to this size use the closed-form triple decode and edge matrix
 
 constexpr int F_DIRTY = 1;  // table entry changed: write back
@@ -83,7 +84,8 @@ struct BlockStats {
     long long t_star, t_locate, t_hole, t_insert;
     // applied moves by wavefront time, bucket b: [2^b, 2^(b+1)) wall-clock ticks
     long long hist[16];
-    long long fast;  // moves done by the star-only path
+    long long fast;     // moves done by the star-only path
+    long long rebuilt;  // block steps done by the rebuild branch
 };
 
 // per-wavefront scratch in LDS
@@ -117,6 +119,9 @@ struct WaveLDS {
     int bnd_ph[BMAX];    // its stored index of a (bits 0-1), b (2-3), q (4-5)
     int nhole, pad[3];
     BlockStats st;  // the block's counters while its wavefront works on it
+    // rebuild branch: points moved this step and their new places
+    int dry_v[DRYMAX];
+    int2 dry_q[DRYMAX];
 };
 
 // ---------------------------------------------------------------- wave ops

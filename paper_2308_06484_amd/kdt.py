@@ -18,11 +18,15 @@ LIB_PATH = os.path.join(_PKG, "libkdt.so")
 
 OK, E_ARG, E_RANGE, E_DUP, E_DEGEN, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 RUN_PER_STEP, RUN_FUSED, RUN_PERSISTENT = 0, 1, 2
+POLICY = {"repair": 0, "rebuild": 1, "threshold": 2, "mlp": 3}
+MLP_PARAMS = 1666
+LOG_FIELDS = 20
 
 EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", "kdt_query",
            "kdt_query_canonical", "kdt_positions", "kdt_stats", "kdt_block_status", "kdt_sync",
            "kdt_destroy", "kdt_strerror", "kdt_timing", "kdt_timing_read", "kdt_set_launch",
-           "kdt_graph_build", "kdt_graph_launch", "kdt_graph_destroy")
+           "kdt_graph_build", "kdt_graph_launch", "kdt_graph_destroy", "kdt_digest",
+           "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train")
 
 
 class KDTError(RuntimeError):
@@ -35,7 +39,7 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("applied", "blocked", "star_sum", "cavity_sum", "walk_sum", "tri_touched",
                  "alg_bytes", "errors", "t_star", "t_locate", "t_hole", "t_insert", "clock_khz")] + \
-               [("hist", ctypes.c_int64 * 16), ("fast", ctypes.c_int64)]
+               [("hist", ctypes.c_int64 * 16), ("fast", ctypes.c_int64), ("rebuilt", ctypes.c_int64)]
 
     def as_dict(self):
         d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "hist"}
@@ -61,6 +65,12 @@ def _lib():
         L.kdt_query.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.kdt_query_canonical.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
         L.kdt_positions.argtypes = [vp, vp]
+        L.kdt_digest.argtypes = [vp, vp]
+        L.kdt_set_policy.argtypes = [vp, i32, ctypes.c_float, vp]
+        L.kdt_set_log.argtypes = [vp, vp, i64]
+        L.kdt_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.kdt_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.kdt_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, vp, vp]
         L.kdt_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.kdt_block_status.argtypes = [vp, vp]
         L.kdt_sync.argtypes = [vp]
@@ -98,6 +108,39 @@ def workspace_size(n, pt_off, max_staged=0):
     _check(_lib().kdt_workspace_size(int(n), len(pt_off) - 1, _ptr(pt_off), int(max_staged),
                                      ctypes.byref(out)), "kdt_workspace_size")
     return int(out.value)
+
+
+def _stream_arg(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mlp_forward(w, x, stream=None):
+    """Device tensors: w [MLP_PARAMS], x [n, 16] -> out [n, 2] (float32)."""
+    n = x.shape[0]
+    out = torch.empty((n, 2), dtype=torch.float32, device=x.device)
+    _check(_lib().kdt_mlp_forward(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()), n,
+                                  ctypes.c_void_p(out.data_ptr()), _stream_arg(stream)), "kdt_mlp_forward")
+    return out
+
+
+def mlp_grad(w, x, y, stream=None):
+    """Summed gradient [MLP_PARAMS] and summed loss of 0.5 |f(x) - y|^2."""
+    g = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=x.device)
+    _check(_lib().kdt_mlp_grad(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(y.data_ptr()), x.shape[0], ctypes.c_void_p(g.data_ptr()),
+                               _stream_arg(stream)), "kdt_mlp_grad")
+    return g[:MLP_PARAMS], g[MLP_PARAMS]
+
+
+def mlp_train(w, x, y, epochs, batch, lr, stream=None):
+    """Mini-batch gradient descent on the device; w updated in place."""
+    scratch = torch.empty(MLP_PARAMS + 1, dtype=torch.float32, device=x.device)
+    _check(_lib().kdt_mlp_train(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(y.data_ptr()), x.shape[0], int(epochs), int(batch),
+                                float(lr), ctypes.c_void_p(scratch.data_ptr()), _stream_arg(stream)),
+           "kdt_mlp_train")
+    return w
 
 
 class Graph:
@@ -176,6 +219,27 @@ class KineticDT:
                             T, None if applied is None else ctypes.c_void_p(applied.data_ptr()), flags)
         _check(rc, "kdt_run")
 
+    def set_policy(self, policy, tau=0.0, mlp_w=None):
+        """policy: "repair", "rebuild", "threshold" (tau) or "mlp" (mlp_w: a
+        float32 device tensor of MLP_PARAMS, kept alive by this object)."""
+        if mlp_w is not None:
+            assert mlp_w.dtype == torch.float32 and mlp_w.is_cuda and mlp_w.numel() == MLP_PARAMS
+        self._mlp_w = mlp_w
+        _check(_lib().kdt_set_policy(self.ctx, POLICY[policy], float(tau),
+                                     None if mlp_w is None else ctypes.c_void_p(mlp_w.data_ptr())),
+               "kdt_set_policy")
+
+    def set_log(self, cap_steps):
+        """Log features, branch and cost per step and block into a device
+        tensor [cap_steps, B, LOG_FIELDS] (returned; None turns it off)."""
+        if not cap_steps:
+            _check(_lib().kdt_set_log(self.ctx, None, 0), "kdt_set_log")
+            self._log = None
+            return None
+        self._log = torch.zeros((cap_steps, self.B, LOG_FIELDS), dtype=torch.float32, device=self.device)
+        _check(_lib().kdt_set_log(self.ctx, ctypes.c_void_p(self._log.data_ptr()), cap_steps), "kdt_set_log")
+        return self._log
+
     def set_launch(self, persist_per_cu):
         _check(_lib().kdt_set_launch(self.ctx, int(persist_per_cu)), "kdt_set_launch")
 
@@ -214,6 +278,12 @@ class KineticDT:
         nt = ctypes.c_int64(0)
         _check(_lib().kdt_query_canonical(self.ctx, _ptr(out), cap, ctypes.byref(nt)), "kdt_query_canonical")
         return out[:int(nt.value)].copy()
+
+    def digest(self):
+        """uint64 [B]: order-independent digest of each block's triangulation."""
+        out = np.zeros(self.B, dtype=np.uint64)
+        _check(_lib().kdt_digest(self.ctx, _ptr(out)), "kdt_digest")
+        return out
 
     def positions(self):
         out = np.empty((self.n, 2), dtype=np.int32)

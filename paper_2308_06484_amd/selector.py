@@ -1,0 +1,147 @@
+"""Training and evaluation driver of the repair-or-rebuild selector.
+
+The paper weighs updating the triangulation against rebuilding it when
+points move far (Sec. I, abstract).  Here that choice is made per block and
+time step by a small network (16 -> 32 -> 32 -> 2) that predicts the log2
+device-clock cost of each branch from the block's features; a threshold on
+the summed move distance (in units of the block's point spacing) is the
+fallback.  Features, costs and branch choices are produced by the library's
+kernels (the per-step log), and the network is trained by the library's own
+forward/backward/SGD kernels; this module only arranges the runs, the
+feature normalisation (folded into the first layer afterwards) and the
+bookkeeping of the regret.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .kdt import LOG_FIELDS, MLP_PARAMS, KineticDT, mlp_train
+
+H, IN = 32, 16
+
+
+def run_policy(w, steps, policy, device="cuda:0", tau=0.0, mlp_w=None, log=True):
+    """Run the workload's first `steps` steps under one policy from its
+    initial state.  Returns (log [steps, B, LOG_FIELDS] numpy or None,
+    seconds, stats)."""
+    dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=device)
+    dt.set_policy(policy, tau, mlp_w)
+    lg = dt.set_log(steps) if log else None
+    mv = torch.from_numpy(w["mv"]).to(device)
+    off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:steps])).to(device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt.run(mv, off)
+    dt.sync()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = dt.stats()
+    out = lg.cpu().numpy() if lg is not None else None
+    dt.close()
+    return out, secs, st
+
+
+def collect(w, steps, device="cuda:0"):
+    """Training samples: features and the log2 cost of both branches for
+    every (step, block) with moves, from a forced-repair and a forced-rebuild
+    run of the same workload (identical states: DT* is unique)."""
+    lr_, _, _ = run_policy(w, steps, "repair", device)
+    lb_, _, _ = run_policy(w, steps, "rebuild", device)
+    valid = lr_[..., 18] > 0
+    X = lr_[..., :IN][valid].astype(np.float32)
+    Y = np.stack([np.log2(np.maximum(lr_[..., 17][valid], 1.0)),
+                  np.log2(np.maximum(lb_[..., 17][valid], 1.0))], axis=1).astype(np.float32)
+    return X, Y
+
+
+def init_weights(seed=0):
+    """He-uniform initialisation, zero biases (float32 [MLP_PARAMS])."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros(MLP_PARAMS, dtype=np.float32)
+    o = 0
+    for fan_in, fan_out in ((IN, H), (H, H), (H, 2)):
+        lim = np.sqrt(6.0 / fan_in)
+        w[o:o + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+        o += fan_in * fan_out + fan_out
+    return w
+
+
+def fold_normalisation(w, mu, sd):
+    """Weights for raw features from weights trained on (x - mu) / sd."""
+    w = w.astype(np.float64).copy()
+    W1 = w[:H * IN].reshape(H, IN)
+    b1 = w[H * IN:H * IN + H]
+    W1n = W1 / sd[None, :]
+    b1n = b1 - W1n @ mu
+    w[:H * IN] = W1n.reshape(-1)
+    w[H * IN:H * IN + H] = b1n
+    return w.astype(np.float32)
+
+
+def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0"):
+    """Train on the device (the library's kernels) and return float32
+    weights for raw features, plus the final mean loss."""
+    mu = X.mean(axis=0).astype(np.float64)
+    sd = X.std(axis=0).astype(np.float64)
+    sd[sd < 1e-6] = 1.0  # constant features: centred to zero, left unscaled
+    Xn = ((X - mu) / sd).astype(np.float32)
+    ym = Y.mean(axis=0)
+    Yc = (Y - ym).astype(np.float32)
+    w0 = init_weights(seed)
+    w0[-2:] = 0.0
+    wt = torch.from_numpy(w0).to(device)
+    xt = torch.from_numpy(Xn).to(device)
+    yt = torch.from_numpy(Yc).to(device)
+    mlp_train(wt, xt, yt, epochs, batch, lr)
+    torch.cuda.synchronize()
+    w = wt.cpu().numpy()
+    w[-2:] += ym.astype(np.float32)  # output bias back to the label scale
+    return fold_normalisation(w, mu, sd)
+
+
+def calibrate_threshold(X, Y):
+    """tau for the rule "rebuild iff sum d/s > tau" that minimises the
+    summed cost on the samples (candidates: the observed values)."""
+    f = X[:, 3].astype(np.float64)
+    cr, cb = np.exp2(Y[:, 0].astype(np.float64)), np.exp2(Y[:, 1].astype(np.float64))
+    order = np.argsort(f)
+    fs, crs, cbs = f[order], cr[order], cb[order]
+    # choose the split index i: repair for the first i samples, rebuild after
+    cum_r = np.concatenate([[0.0], np.cumsum(crs)])
+    cum_b = np.concatenate([[0.0], np.cumsum(cbs[::-1])])[::-1]
+    total = cum_r + cum_b
+    i = int(np.argmin(total))
+    if i >= len(fs):
+        return float(fs[-1] + 1.0) if len(fs) else 0.0
+    return float(fs[i - 1] if i > 0 else fs[0] - 1.0)
+
+
+def regret(branch_log, cost_repair, cost_rebuild, valid):
+    """Sum over (step, block) of the chosen branch's cost minus the cheaper
+    one's (device ticks), and the total cost of the choices."""
+    cr, cb = cost_repair[valid], cost_rebuild[valid]
+    ch = branch_log[valid]
+    chosen = np.where(ch > 0.5, cb, cr)
+    best = np.minimum(cr, cb)
+    return float((chosen - best).sum()), float(chosen.sum()), float(best.sum())
+
+
+def evaluate(w, steps, mlp_w, tau, device="cuda:0"):
+    """Wall time and regret of every policy on the workload."""
+    res = {}
+    logs = {}
+    for pol in ("repair", "rebuild", "threshold", "mlp"):
+        lg, secs, st = run_policy(w, steps, pol, device, tau=tau, mlp_w=mlp_w)
+        logs[pol] = lg
+        res[pol] = {"seconds": secs, "applied": st["applied"], "rebuilt_block_steps": st["rebuilt"],
+                    "moves_per_s": st["applied"] / secs}
+    valid = logs["repair"][..., 18] > 0
+    cr, cb = logs["repair"][..., 17], logs["rebuild"][..., 17]
+    for pol in res:
+        r, tot, best = regret(logs[pol][..., 16], cr, cb, valid)
+        res[pol].update(regret_ticks=r, chosen_ticks=tot, best_ticks=best,
+                        rebuild_fraction=float(logs[pol][..., 16][valid].mean()))
+    return res

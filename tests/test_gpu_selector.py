@@ -1,0 +1,113 @@
+"""Repair-or-rebuild selector on the GPU: the MLP kernels against the FP64
+reference, the rebuild branch and every policy bit-exact against the oracle,
+the per-step log, and the training/evaluation driver end to end."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.kinetic import Kinetic
+from paper_2308_06484_amd import workloads as W
+from tests import mlp_ref as R
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def test_mlp_forward_and_gradient_match_fp64_reference():
+    from paper_2308_06484_amd.kdt import mlp_forward, mlp_grad
+    rng = np.random.default_rng(0)
+    w = (rng.normal(0, 0.25, R.NPARAM)).astype(np.float32)
+    X = rng.normal(0, 1, (3000, R.IN)).astype(np.float32)
+    Y = rng.normal(0, 1, (3000, R.OUT)).astype(np.float32)
+    wt, xt, yt = (torch.from_numpy(a).to(DEV) for a in (w, X, Y))
+    out = mlp_forward(wt, xt).cpu().numpy()
+    ref, _ = R.forward(w, X)
+    # float32 sums of at most 33 terms of O(1): relative error well below 1e-4
+    assert np.allclose(out, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+    g, l = mlp_grad(wt, xt, yt)
+    gref = R.grad(w, X, Y)
+    lref = R.loss(w, X, Y)
+    # sums over 3000 samples in float32 atomics (any order): relative 1e-4 of the scale
+    scale = np.abs(gref).max()
+    assert np.allclose(g.cpu().numpy(), gref, rtol=1e-3, atol=1e-4 * scale)
+    assert abs(float(l) - lref) <= 1e-4 * lref
+
+
+def test_training_kernels_fit_a_smooth_target():
+    from paper_2308_06484_amd.kdt import mlp_grad, mlp_train
+    from paper_2308_06484_amd.selector import init_weights
+    rng = np.random.default_rng(1)
+    X = rng.normal(0, 1, (8192, R.IN)).astype(np.float32)
+    Y = np.stack([np.tanh(X[:, 0] + 0.5 * X[:, 1]), X[:, 2] * 0.3 - X[:, 3] * 0.2], 1).astype(np.float32)
+    w = torch.from_numpy(init_weights(5) * 0.5).to(DEV)
+    xt, yt = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    l0 = float(mlp_grad(w, xt, yt)[1])
+    mlp_train(w, xt, yt, epochs=60, batch=512, lr=0.05)
+    l1 = float(mlp_grad(w, xt, yt)[1])
+    assert l1 < 0.1 * l0, (l0, l1)
+    # the device-trained weights agree with the FP64 reference loss
+    assert abs(l1 - R.loss(w.cpu().numpy(), X, Y)) <= 1e-3 * max(l1, 1e-3)
+
+
+def _policy_run(w, policy, tau=0.0, mlp_w=None, steps=None):
+    from paper_2308_06484_amd.kdt import KineticDT
+    T = w["mv_off"].shape[0] if steps is None else steps
+    dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+    dt.set_policy(policy, tau, mlp_w)
+    log = dt.set_log(T)
+    mv = torch.from_numpy(w["mv"]).to(DEV)
+    off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:T])).to(DEV)
+    ap = torch.zeros(w["mv"].shape[0], dtype=torch.int8, device=DEV)
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    for t in range(T):
+        dt.run(mv, off[t:t + 1].contiguous(), applied=ap)
+        a = ref.apply_step(w["mv"], w["mv_off"][t])
+        lo, hi = int(w["mv_off"][t, 0]), int(w["mv_off"][t, -1])
+        assert np.array_equal(ap[lo:hi].cpu().numpy().astype(bool), a), (policy, t)
+        assert np.array_equal(dt.query_canonical(), ref.all_dt(8)), (policy, t)
+    assert np.array_equal(dt.positions(), ref.xy)
+    st = dt.stats()
+    return st, log.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def heavy():
+    return W.multi2048(seed=7, steps=6, blocks=8, per_block=300, side=2048, dcap=1024)
+
+
+def test_rebuild_branch_bit_exact(heavy):
+    st, log = _policy_run(heavy, "rebuild")
+    assert st["errors"] == 0 and st["rebuilt"] == 6 * 8
+    assert (log[..., 16] == 1).all() and (log[..., 17] > 0).all()
+    k = np.diff(heavy["mv_off"], axis=1)
+    assert np.array_equal(log[..., 18], k) and np.array_equal(log[..., 1], k)
+
+
+def test_threshold_and_mlp_policies_bit_exact(heavy):
+    st, log = _policy_run(heavy, "threshold", tau=float(np.median(heavy["mv"][:, 2])) / 50)
+    assert st["errors"] == 0 and 0 < st["rebuilt"] < 48
+    assert np.array_equal(log[..., 16] == 1, log[..., 3] > float(np.median(heavy["mv"][:, 2])) / 50)
+    rng = np.random.default_rng(3)
+    w = torch.from_numpy(rng.normal(0, 0.3, R.NPARAM).astype(np.float32)).to(DEV)
+    st, log = _policy_run(heavy, "mlp", mlp_w=w)
+    assert st["errors"] == 0
+    # the device's choice is the FP64 reference's wherever the margin is clear
+    out, _ = R.forward(w.cpu().numpy(), log[..., :16].reshape(-1, 16))
+    margin = np.abs(out[:, 1] - out[:, 0])
+    pick = (out[:, 1] < out[:, 0]).astype(np.float32)
+    clear = margin > 1e-3 * (1 + np.abs(out).max(1))
+    assert np.array_equal(log[..., 16].reshape(-1)[clear], pick[clear])
+
+
+def test_selector_train_and_evaluate_end_to_end():
+    from paper_2308_06484_amd import selector as S
+    calib = W.multi2048(seed=105, steps=4, blocks=16, per_block=400, side=4096, dcap=2048)
+    X, Y = S.collect(calib, 4)
+    assert X.shape[0] == 64 and np.isfinite(Y).all()
+    wts = S.train(X, Y, epochs=50, batch=64, lr=0.02)
+    tau = S.calibrate_threshold(X, Y)
+    evalw = W.multi2048(seed=5, steps=4, blocks=16, per_block=400, side=4096, dcap=2048)
+    res = S.evaluate(evalw, 4, torch.from_numpy(wts).to(DEV), tau)
+    for pol in ("repair", "rebuild", "threshold", "mlp"):
+        assert res[pol]["applied"] == res["repair"]["applied"]
+        assert res[pol]["regret_ticks"] >= 0
