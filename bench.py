@@ -80,6 +80,93 @@ def cpu_baseline(w, threads, budget_s=12.0, max_steps=16):
                        f"{threads} host threads over blocks")
 
 
+def time_form(w, steps, mode, graph, per_cu, dev):
+    """Seconds and applied moves of `steps` steps of w from its initial
+    state under one launch form (fresh context, own stream)."""
+    import numpy as np
+    import torch
+
+    from paper_2308_06484_amd.kdt import KineticDT
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev)
+        if per_cu:
+            dt.set_launch(per_cu)
+        mv = torch.from_numpy(w["mv"]).to(dev)
+        off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:steps])).to(dev)
+        g = dt.graph(mv, off, mode=mode) if graph else None
+        stream.synchronize()
+        a0 = dt.stats()["applied"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if g is not None:
+            g.launch()
+        else:
+            dt.run(mv, off, mode=mode)
+        e1.record(stream)
+        stream.synchronize()
+        dt.sync()
+        st = dt.stats()
+        if g is not None:
+            g.close()
+        dt.close()
+    return e0.elapsed_time(e1) / 1e3, st["applied"] - a0, st
+
+
+def other_workload(args):
+    """Secondary reports: launch forms on lattice256 / uneven4096 (with the
+    autotuner's pick), the repair-or-rebuild selector on multi2048."""
+    import numpy as np
+    import torch
+
+    from paper_2308_06484_amd import autotune as A
+    from paper_2308_06484_amd import selector as S
+    from paper_2308_06484_amd import workloads as W
+    dev = "cuda:0"
+    name = args.workload
+    if name == "multi2048":
+        cal_steps = 8
+        ev_steps = args.other_steps or 10
+        log(f"multi2048: calibration workload (seed {100 + args.seed})")
+        calib = W.multi2048(seed=100 + args.seed, steps=cal_steps)
+        X, Y = S.collect(calib, cal_steps, dev)
+        del calib
+        wts = S.train(X, Y, epochs=300, batch=2048, lr=0.02, device=dev)
+        tau = S.calibrate_threshold(X, Y)
+        log(f"trained on {len(X)} samples, tau = {tau:.3f}; evaluation workload (seed {args.seed})")
+        evalw = W.multi2048(seed=args.seed, steps=ev_steps)
+        res = S.evaluate(evalw, ev_steps, torch.from_numpy(wts).to(dev), tau, dev)
+        out = {"workload": "multi2048: 2048 blocks x 4096 uniform points on [0,16384)^2, "
+                           "k ~ clip(Poisson(lambda_b),1,64) moves per block per step, Pareto(1.2) "
+                           "distances capped at 4096", "steps": ev_steps, "train_samples": int(len(X)),
+               "tau": tau, "policies": res}
+        print(json.dumps(out), flush=True)
+        return
+    if name == "lattice256":
+        w = W.lattice256(seed=args.seed, steps=args.other_steps or 100)
+    else:
+        w = W.uneven4096(seed=args.seed, steps=args.other_steps or 500)
+    T = w["mv_off"].shape[0]
+    forms = [("per_step", "step", False, None), ("graph_per_step", "step", True, None),
+             ("persistent_lpt", "persistent", False, 4), ("graph_persistent_lpt", "persistent", True, 4),
+             ("fused", "fused", False, None)]
+    res = {}
+    if name == "uneven4096":
+        cal = W.uneven4096(seed=100 + args.seed, steps=60)
+        best = A.autotune(cal, steps=50, use_cache=False)
+        log("autotuner: " + json.dumps({k: v for k, v in best.items() if k != "table"}))
+        forms.append(("autotuned", best["mode"], best["graph"], best.get("per_cu")))
+        res["autotune_table"] = best["table"]
+    for fname, mode, graph, per_cu in forms:
+        secs, napp, st = time_form(w, T, mode, graph, per_cu, dev)
+        res[fname] = {"moves_per_s": napp / secs, "ms_per_step": secs * 1e3 / T, "mode": mode,
+                      "graph": graph, "per_cu": per_cu, "errors": st["errors"]}
+        log(f"{name} {fname}: {napp / secs:.3e} moves/s, {secs * 1e3 / T:.3f} ms/step")
+    sizes = np.diff(w["pt_off"])
+    print(json.dumps({"workload": name, "blocks": int(len(sizes)), "points": int(sizes.sum()),
+                      "steps": T, "forms": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +177,10 @@ def main():
     ap.add_argument("--fused", action="store_true", help="time the fused multi-step launch instead")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms")
+    ap.add_argument("--workload", default="grid1024",
+                    choices=["grid1024", "lattice256", "uneven4096", "multi2048"],
+                    help="grid1024 is the measured configuration; the others print a secondary report")
+    ap.add_argument("--other-steps", type=int, default=0, help="steps for --workload other than grid1024")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -98,6 +189,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload != "grid1024":
+        other_workload(args)
         return
 
     import numpy as np
