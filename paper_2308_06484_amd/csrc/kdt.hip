@@ -1,8 +1,8 @@
 // libkdt: kinetic Delaunay triangulation of moving lattice points on MI355X.
 //
 // Kernels (one 64-lane wavefront per block of the partition, Sec. IV):
-//   k_build      every block's DT* from scratch (Bowyer-Watson insertion in
-//                Hilbert order); the starting state of Fig. 4
+//   k_pbuild     every block's DT* from scratch, the threads of a workgroup
+//                inserting in parallel (kdt_pbuild.hpp); the starting state of Fig. 4
 //   k_step       one time step: for each block, its moves in order, each a
 //                walk to the target, Delete, Insert (Fig. 4)
 //   k_run_fused  all steps of a move stream; blocks are independent, so each
@@ -20,6 +20,7 @@
 #include "../../include/kdt.h"
 #include "kdt_device.hpp"
 #include "kdt_mlp.hpp"
+#include "kdt_pbuild.hpp"
 
 using namespace kdt;
 
@@ -40,6 +41,7 @@ struct DevState {
     BlockStats* stats;
     int* sticky;
     const int* order;  // per-block insertion order (Hilbert order at init)
+    int* owner;        // one int per triangle slot: claims of the parallel build
     // repair-or-rebuild selection
     int policy;          // KDT_POLICY_*
     float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
@@ -61,7 +63,7 @@ __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
 }
 
 __device__ void fail_block(const DevState& s, int b, int code) {
-    if (lane_id() == 0) {
+    if (threadIdx.x == 0) {
         s.status[b] = code;
         atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b].errors), 1ull);
         atomicMin(s.sticky, code);
@@ -78,67 +80,13 @@ __device__ __forceinline__ Tri make_tri(int a, int b, int c, int2 pa, int2 pb, i
     return t;
 }
 
-// Build block b's DT* from scratch (Bowyer-Watson insertion in the order
-// given), overwriting its records.  Returns ST_OK or an error code.
-__device__ int build_block(const DevState& s, WaveLDS& S, int b) {
-    const int lane = lane_id();
-    BlockView B = view_of(s, b);
-    const int* ord = s.order + s.pt_off[b];
-    const int n = B.n;
-    // first triangle: the first two points and the first point off their line
-    int a = ord[0], c1 = ord[1];
-    int2 pa = B.xy[a], pb = B.xy[c1];
-    int kidx = -1;
-    for (int base = 2; base < n && kidx < 0; base += WAVE) {
-        const int i = base + lane;
-        const bool off_line = i < n && orient(pa, pb, B.xy[ord[i]]) != 0;
-        const uint64_t m = ballot(off_line);
-        if (m) kidx = base + first_lane(m);
-    }
-    if (kidx < 0) return ST_DEGEN;
-    const int c = ord[kidx];
-    const int2 pc = B.xy[c];
-    if (orient(pa, pb, pc) < 0) {
-        const int t = a; a = c1; c1 = t;
-        const int2 tp = pa; pa = pb; pb = tp;
-    }
-    if (lane == 0) {
-        // slot 0: (a, c1, c); ghosts 1: (c1, a, inf), 2: (c, c1, inf), 3: (a, c, inf)
-        const int2 z = make_int2(0, 0);
-        B.tri[0] = make_tri(a, c1, c, pa, pb, pc, 2 * 4 + 2, 3 * 4 + 2, 1 * 4 + 2);
-        B.tri[1] = make_tri(c1, a, GHOST, pb, pa, z, 3 * 4 + 1, 2 * 4 + 0, 0 * 4 + 2);
-        B.tri[2] = make_tri(c, c1, GHOST, pc, pb, z, 1 * 4 + 1, 3 * 4 + 0, 0 * 4 + 0);
-        B.tri[3] = make_tri(a, c, GHOST, pa, pc, z, 2 * 4 + 1, 1 * 4 + 0, 0 * 4 + 1);
-        B.vtri[a] = 0;
-        B.vtri[c1] = 0;
-        B.vtri[c] = 0;
-    }
-    gsync();
-    int nt = 4, last = 0;
-    for (int idx = 2; idx < n; ++idx) {
-        if (idx == kidx) continue;
-        const int v = ord[idx];
-        const int2 q = B.xy[v];
-        int hit, hops = 0;
-        const int seed = walk<false>(B, S, last, q, &hit, &hops);
-        if (seed < 0 || hit >= 0) return ST_INTERNAL;
-        int used = 0, nvt = 0;
-        const int rc = insert_vertex(B, S, v, q, seed, nt, nt + 1, &used, &nvt, nullptr);
-        if (rc != ST_OK) return rc;
-        last = S.vt_s[nvt - 1];  // a triangle incident to v
-        commit(B, S, used, 0, nvt);
-        gsync();
-        nt += 2;
-    }
-    if (nt != B.ntri) return ST_INTERNAL;
-    return ST_OK;
-}
-
-__global__ void __launch_bounds__(WAVE) k_build(DevState s) {
-    __shared__ WaveLDS S;
+// Every block's DT* from scratch, all threads of a workgroup inserting in
+// parallel (kdt_pbuild.hpp); `owner`: one int per triangle slot (scratch).
+__global__ void __launch_bounds__(256) k_pbuild(DevState s, int* owner) {
+    __shared__ int lds[4 + PB_DEFER];
     const int b = blockIdx.x;
-    scratch_init(S);
-    const int rc = build_block(s, S, b);
+    BlockView B = view_of(s, b);
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], owner + s.tri_off[b], lds);
     if (rc != ST_OK) fail_block(s, b, rc);
 }
 
@@ -177,7 +125,7 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     int hops = 0, tq = -1;
     if (!in_star) {
         int hit;
-        tq = walk<false>(B, S, S.star_slot[0], q, &hit, &hops);
+        tq = walk<false>(B, &S, S.star_slot[0], q, &hit, &hops);
         if (tq < 0) return ST_INTERNAL;
         on_vertex = hit >= 0;
     }
@@ -228,7 +176,7 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
             seed = S.star_slot[first_lane(m)];
         } else {
             int hit2;
-            seed = walk<true>(B, S, S.star_slot[0], q, &hit2, &hops);
+            seed = walk<true>(B, &S, S.star_slot[0], q, &hit2, &hops);
             if (seed < 0 || hit2 >= 0) return ST_INTERNAL;
         }
     }
@@ -291,7 +239,7 @@ __device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const k
         if (ok) {
             // a point of the old triangulation at q that has not moved away
             int hit, hops = 0;
-            const int tq = walk<false>(B, S, B.vtri[p], q, &hit, &hops);
+            const int tq = walk<false>(B, &S, B.vtri[p], q, &hit, &hops);
             if (tq < 0) return ST_INTERNAL;
             if (hit >= 0 && same(B.xy[hit], q)) ok = false;
         }
@@ -312,8 +260,8 @@ __device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const k
         if (applied && lane == 0) applied[m] = ok ? 1 : 0;
     }
     gsync();
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], s.owner + s.tri_off[b], S.pb_lds);
     table_clear(S);
-    const int rc = build_block(s, S, b);
     if (lane == 0) {
         st->rebuilt += 1;
         st->alg_bytes += 64LL * B.ntri + 12LL * B.n;  // records written, positions read, vtri written
@@ -843,6 +791,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->dev.stats = (BlockStats*)(w + L.stats);
     c->dev.sticky = (int*)(w + L.sticky);
     c->dev.order = (const int*)(w + L.order);
+    c->dev.owner = (int*)(w + L.qmap);
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.tau = 0.f;
     c->dev.mlp_w = nullptr;
@@ -875,10 +824,17 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
         c->cus = cus;
     }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
-    k_build<<<n_blocks, WAVE, 0, s>>>(c->dev);
+    k_pbuild<<<n_blocks, 256, 0, s>>>(c->dev, c->dev.owner);
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
     rc = check_hip(c, hipStreamSynchronize(s));
     if (rc != KDT_OK) { delete c; return rc; }
+    // a block whose build failed (a local limit, an invariant) fails the init
+    int built = 0;
+    if (check_hip(c, hipMemcpy(&built, c->dev.sticky, sizeof(int), hipMemcpyDeviceToHost)) != KDT_OK) {
+        delete c;
+        return KDT_E_DEVICE;
+    }
+    if (built != 0) { delete c; return built; }
     *out = c;
     return KDT_OK;
 }

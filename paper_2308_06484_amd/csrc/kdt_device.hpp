@@ -119,9 +119,11 @@ struct WaveLDS {
     int bnd_ph[BMAX];    // its stored index of a (bits 0-1), b (2-3), q (4-5)
     int nhole, pad[3];
     BlockStats st;  // the block's counters while its wavefront works on it
-    // rebuild branch: points moved this step and their new places
+    // rebuild branch: points moved this step and their new places, and the
+    // parallel build's counters and deferred points
     int dry_v[DRYMAX];
     int2 dry_q[DRYMAX];
+    int pb_lds[4 + 256];
 };
 
 // ---------------------------------------------------------------- wave ops
@@ -359,13 +361,13 @@ __device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s
 // sitting exactly at q (-1 if none).  Returns -1 if the step limit is hit.
 // TABLE: read through the move's write-back table (after changes).
 template <bool TABLE>
-__device__ int walk(const BlockView& B, const WaveLDS& S, int start, int2 q, int* hit, int* hops) {
+__device__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops) {
     int cur = start, entry = -1;
     const int limit = 4 * B.ntri + 16;
     *hit = -1;
     for (int h = 0; h < limit; ++h) {
         if (bad_slot(B, cur)) return -1;
-        const Tri t = TABLE ? tread(B, S, cur) : B.tri[cur];
+        const Tri t = TABLE ? tread(B, *S, cur) : B.tri[cur];
         if (bad_tri(B, t.v)) return -1;
         const int2 p0 = cget(t, 0), p1 = cget(t, 1);
         if (t.v.z == GHOST) {
