@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -82,11 +83,13 @@ __device__ __forceinline__ Tri make_tri(int a, int b, int c, int2 pa, int2 pb, i
 
 // Every block's DT* from scratch, all threads of a workgroup inserting in
 // parallel (kdt_pbuild.hpp); `owner`: one int per triangle slot (scratch).
-__global__ void __launch_bounds__(256) k_pbuild(DevState s, int* owner) {
+constexpr int PB_THREADS = 128;
+__global__ void __launch_bounds__(PB_THREADS) k_pbuild(DevState s, int* owner) {
     __shared__ int lds[4 + PB_DEFER];
+    __shared__ int att[PB_THREADS * ATT_INTS];
     const int b = blockIdx.x;
     BlockView B = view_of(s, b);
-    const int rc = pbuild_block(B, s.order + s.pt_off[b], owner + s.tri_off[b], lds);
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], owner + s.tri_off[b], lds, att);
     if (rc != ST_OK) fail_block(s, b, rc);
 }
 
@@ -260,7 +263,10 @@ __device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const k
         if (applied && lane == 0) applied[m] = ok ? 1 : 0;
     }
     gsync();
-    const int rc = pbuild_block(B, s.order + s.pt_off[b], s.owner + s.tri_off[b], S.pb_lds);
+    // the attempts overlay the wavefront's repair scratch, unused here
+    static_assert(offsetof(WaveLDS, st) >= sizeof(int) * WAVE * ATT_INTS, "attempts overlap the counters");
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], s.owner + s.tri_off[b], S.pb_lds,
+                                reinterpret_cast<int*>(&S));
     table_clear(S);
     if (lane == 0) {
         st->rebuilt += 1;
@@ -824,7 +830,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
         c->cus = cus;
     }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
-    k_pbuild<<<n_blocks, 256, 0, s>>>(c->dev, c->dev.owner);
+    k_pbuild<<<n_blocks, PB_THREADS, 0, s>>>(c->dev, c->dev.owner);
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
     rc = check_hip(c, hipStreamSynchronize(s));
     if (rc != KDT_OK) { delete c; return rc; }
