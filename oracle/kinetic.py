@@ -77,3 +77,93 @@ class Kinetic:
         order (ids are global, so this is the sorted union)."""
         parts = self.blocks_dt(None, threads)
         return np.concatenate(parts) if parts else np.zeros((0, 3), np.int64)
+
+
+def kd_splits(xy, depth):
+    """The kd partition of a point set into 2^depth cells, by definition:
+    the root holds every point; a node at level l orders its points by the
+    key (x, y) if l is even, (y, x) if l is odd, keeps the first half (n // 2
+    points) on the left and the rest on the right, and its split key is the
+    key of the first right point.  Nodes are numbered as a heap (root 1,
+    children 2k and 2k + 1).  Returns int64 [2^depth, 2]: the split key of
+    node k in row k (row 0 unused)."""
+    xy = np.asarray(xy, dtype=np.int64)
+    splits = np.zeros((1 << depth, 2), dtype=np.int64)
+    if depth == 0:
+        return splits
+
+    def node(k, idx, level):
+        a = xy[idx, level % 2]
+        b = xy[idx, 1 - level % 2]
+        idx = idx[np.lexsort((b, a))]
+        h = len(idx) // 2
+        splits[k] = (xy[idx[h], level % 2], xy[idx[h], 1 - level % 2])
+        if level + 1 < depth:
+            node(2 * k, idx[:h], level + 1)
+            node(2 * k + 1, idx[h:], level + 1)
+
+    node(1, np.arange(len(xy)), 0)
+    return splits
+
+
+def kd_cell(xy, splits, depth):
+    """Cell (0 .. 2^depth - 1) of each position: from the root, go right iff
+    the position's key is >= the node's split key (lexicographically)."""
+    xy = np.asarray(xy, dtype=np.int64).reshape(-1, 2)
+    k = np.ones(len(xy), dtype=np.int64)
+    for level in range(depth):
+        a = xy[:, level % 2]
+        b = xy[:, 1 - level % 2]
+        sa, sb = splits[k, 0], splits[k, 1]
+        right = (a > sa) | ((a == sa) & (b >= sb))
+        k = 2 * k + right
+    return k - (1 << depth)
+
+
+class KineticGlobal:
+    """Global mode: one DT* over every point of the domain [0, side)^2.
+
+    Move rule (this project's reading, as in the per-block mode but with one
+    domain): the moves of a step are applied one after the other in list
+    order; a move of point p by `dist` units in direction `dir` jumps p to
+    its target cell and is blocked when that cell lies outside the domain or
+    is held by any point at that moment.  Points belong to the kd cell that
+    holds their current position (cells fixed by the initial points)."""
+
+    def __init__(self, xy, side, depth):
+        self.xy = np.array(xy, dtype=np.int32).reshape(-1, 2)
+        self.side = int(side)
+        self.depth = int(depth)
+        self.occ = set((self.xy[:, 0].astype(np.int64) << 24 | self.xy[:, 1]).tolist())
+        self.splits = kd_splits(self.xy, self.depth)
+
+    def apply_step(self, mv_rows):
+        """Apply one step's moves (rows (point, dir, dist, _)) in order;
+        returns a bool array: applied."""
+        out = np.zeros(len(mv_rows), dtype=bool)
+        for r, (p, d, dist) in enumerate(np.asarray(mv_rows)[:, :3].tolist()):
+            px, py = int(self.xy[p, 0]), int(self.xy[p, 1])
+            qx, qy = px + dist * _DIR[d][0], py + dist * _DIR[d][1]
+            key = qx << 24 | qy
+            if not (0 <= qx < self.side and 0 <= qy < self.side) or key in self.occ:
+                continue
+            self.occ.discard(px << 24 | py)
+            self.occ.add(key)
+            self.xy[p] = (qx, qy)
+            out[r] = True
+        return out
+
+    def owner(self):
+        return kd_cell(self.xy, self.splits, self.depth)
+
+    def dt(self):
+        """Canonical DT* of all points (global ids = rows).  The points are
+        handed to the builder in strips of 64 columns, alternately upward and
+        downward, so that consecutive insertions are close; the order never
+        changes DT*."""
+        x = self.xy[:, 0].astype(np.int64)
+        y = self.xy[:, 1].astype(np.int64)
+        strip = x >> 6
+        yy = np.where(strip % 2 == 0, y, (1 << 24) - 1 - y)
+        order = np.lexsort((x, yy, strip))
+        return dt_star(self.xy[order], order.astype(np.int64))

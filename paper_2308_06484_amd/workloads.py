@@ -22,6 +22,11 @@ measured on:
                k ~ clip(Poisson(lambda_b), 1, 64) distinct movers per block
                with Pareto(1.2) distances capped at 4096.
 
+  global4m     one triangulation of 4,194,304 uniform points on
+               [0,65536)^2; the points are grouped into 4096 cells of 1024
+               by alternating median splits (x first), and every step moves
+               one point drawn from each cell by 1..16 units (200 steps).
+
 A workload is a dict of numpy arrays:
   xy      int32 [N, 2]   point coordinates, grouped by block
   pt_off  int64 [B + 1]  block b owns points pt_off[b] .. pt_off[b+1]-1;
@@ -31,6 +36,14 @@ A workload is a dict of numpy arrays:
   mv_off  int32 [T, B+1] moves of step t for block b are rows
                          mv_off[t, b] .. mv_off[t, b+1]-1 of mv
 Directions: 0 = +x (right), 1 = -x (left), 2 = +y (up), 3 = -y (down).
+
+The global-mode workload (global4m) is a dict of:
+  xy        int32 [N, 2]  points, ordered cell by cell (cell c holds rows
+                          c * N / C .. (c + 1) * N / C - 1)
+  side      int           the domain is [0, side)^2
+  depth     int           C = 2^depth cells
+  mv        int32 [M, 4]  (global point id, direction, distance, 0)
+  step_off  int64 [T + 1] moves of step t are rows step_off[t] .. step_off[t+1]-1
 """
 from __future__ import annotations
 
@@ -176,3 +189,50 @@ def subset_blocks(w, blocks, steps=None):
     return dict(name=w["name"] + "_subset", xy=xy, pt_off=pt_off,
                 frame=w["frame"][blocks].copy(), mv=mv.astype(np.int32),
                 mv_off=offs.astype(np.int32))
+
+
+def _median_groups(xy, depth):
+    """Row order that groups the points into 2^depth cells of equal size by
+    alternating median splits: at level l every group is sorted by
+    (x, y) (l even) or (y, x) (l odd) and cut in half.  Used to pick one
+    mover per cell; requires N divisible by 2^depth."""
+    n = len(xy)
+    if n % (1 << depth):
+        raise ValueError("point count must be divisible by the cell count")
+    order = np.arange(n, dtype=np.int64)
+    x = xy[:, 0].astype(np.int64)
+    y = xy[:, 1].astype(np.int64)
+    for level in range(depth):
+        group = np.arange(n, dtype=np.int64) // (n >> level)
+        a, b = (x, y) if level % 2 == 0 else (y, x)
+        key = (group << 48) | (a[order] << 24) | b[order]
+        order = order[np.argsort(key, kind="stable")]
+    return order
+
+
+def global_mode(seed=1, steps=200, n=1 << 22, depth=12, side=65536, dmax=16, name="global4m"):
+    """One triangulation over all points (see the module notes)."""
+    rng = np.random.default_rng(seed)
+    xy = _distinct_uniform(rng, n, 0, 0, side, side)
+    xy = xy[_median_groups(xy, depth)]
+    cells = 1 << depth
+    per = n // cells
+    pt = (np.arange(cells, dtype=np.int64)[None, :] * per
+          + rng.integers(0, per, size=(steps, cells)))
+    mv = np.zeros((steps * cells, 4), dtype=np.int32)
+    mv[:, 0] = pt.reshape(-1)
+    mv[:, 1] = rng.integers(0, 4, size=steps * cells)
+    mv[:, 2] = rng.integers(1, dmax + 1, size=steps * cells)
+    step_off = np.arange(steps + 1, dtype=np.int64) * cells
+    return dict(name=name, xy=xy, side=side, depth=depth, mv=mv, step_off=step_off)
+
+
+def global4m(seed=1, steps=200):
+    return global_mode(seed=seed, steps=steps)
+
+
+def global_small(seed=1, steps=20, n=16384, depth=4, side=4096, dmax=16):
+    """The global mode at the density of global4m (one point per 1024
+    lattice cells), small enough for the oracle at every step."""
+    return global_mode(seed=seed, steps=steps, n=n, depth=depth, side=side, dmax=dmax,
+                       name="global_small")
