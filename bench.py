@@ -13,6 +13,7 @@ counted) per second of the timed region.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
     python bench.py --copy-probe     # plain copy kernel for counter scaling
+    python bench.py --workload global4m   # global mode vs full rebuild (report)
 """
 from __future__ import annotations
 
@@ -124,6 +125,9 @@ def other_workload(args):
     from paper_2308_06484_amd import workloads as W
     dev = "cuda:0"
     name = args.workload
+    if name == "global4m":
+        global_report(args)
+        return
     if name == "multi2048":
         cal_steps = 8
         ev_steps = args.other_steps or 10
@@ -167,6 +171,60 @@ def other_workload(args):
                       "steps": T, "forms": res}), flush=True)
 
 
+def global_report(args):
+    """Global mode on 4,194,304 points in 4096 kd cells: moves/s of the
+    reservation-round repair, against rebuilding the whole DT* with the
+    device builder (one rebuild per step would be the alternative)."""
+    import numpy as np
+    import torch
+
+    from paper_2308_06484_amd import workloads as W
+    from paper_2308_06484_amd.kdt import GlobalDT
+    dev = "cuda:0"
+    steps = args.other_steps or 200
+    warm = min(10, steps - 1)
+    t0 = time.perf_counter()
+    w = W.global4m(seed=args.seed, steps=steps)
+    log(f"global4m: generated in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        G = GlobalDT(w["xy"], [0, 0, w["side"], w["side"]], w["depth"], 1 << w["depth"], device=dev)
+        init_s = time.perf_counter() - t0
+        mv = torch.from_numpy(np.ascontiguousarray(w["mv"])).to(dev)
+        G.run(mv, w["step_off"][:warm + 1])
+        stream.synchronize()
+        st0 = G.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        G.run(mv, w["step_off"][warm:])
+        e1.record(stream)
+        stream.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        st = G.stats()
+        gs = G.gstats()
+        applied = st["applied"] - st0["applied"]
+        timed = steps - warm
+        rb = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            G.rebuild()
+            rb.append(time.perf_counter() - t0)
+        G.close()
+    moves_per_step = int(w["step_off"][1] - w["step_off"][0])
+    out = {"workload": "global4m: one DT* of 4,194,304 uniform points on [0,65536)^2, 4096 kd cells "
+                       "(median splits), one move per cell per step of 1..16 units",
+           "steps_timed": timed, "warmup": warm, "moves_per_s": applied / secs,
+           "ms_per_step": secs * 1e3 / timed, "applied": int(applied),
+           "blocked": int(st["blocked"] - st0["blocked"]), "init_build_s": init_s,
+           "full_rebuild_s": min(rb), "full_rebuild_moves_per_s": moves_per_step / min(rb),
+           "speedup_vs_rebuild_per_step": (applied / secs) / (moves_per_step / min(rb)),
+           "global_counters": gs}
+    log(f"global4m: {applied / secs:.3e} moves/s ({secs * 1e3 / timed:.3f} ms/step); full rebuild "
+        f"{min(rb) * 1e3:.1f} ms; init {init_s:.2f} s; counters {gs}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,13 +236,13 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms")
     ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "lattice256", "uneven4096", "multi2048"],
+                    choices=["grid1024", "lattice256", "uneven4096", "multi2048", "global4m"],
                     help="grid1024 is the measured configuration; the others print a secondary report")
     ap.add_argument("--other-steps", type=int, default=0, help="steps for --workload other than grid1024")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(blocks are independent: sharding them over GPUs needs no exchange, see DESIGN.md)",
+              f"(blocks are independent: sharding them over GPUs needs no exchange)",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:

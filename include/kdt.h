@@ -238,6 +238,65 @@ int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, floa
 int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
                   float lr, float* scratch, void* stream);
 
+/* ---- Global mode: one DT* over every point ------------------------------
+ * The paper lets a moved point leave its block and be sent to the
+ * neighbouring block that now holds it (Sec. IV, Fig. 4), with at most one
+ * such hand-over per block and step (Theorem 1, Sec. V).  Here the blocks
+ * are the 2^depth cells of a kd partition of the initial points (median
+ * splits, x first: a node's first half by (x, y) at even levels, (y, x) at
+ * odd levels goes left, and a position goes right iff its key is not below
+ * the key of the first right point), and every point belongs to the cell
+ * that holds its current position.  The triangulation is one DT* of all
+ * points in the domain, with ghosts on the global hull.
+ *
+ * Move rule: the moves of a step apply one after the other in list order; a
+ * move is blocked when its target lies outside the domain or on a cell held
+ * by any point at that moment.  Moves with no cell in common with another
+ * move of the step run concurrently (reservation rounds on the triangles
+ * their plans read); the others, and moves still contended after the
+ * rounds, run afterwards in list order.  The triangulation after each step
+ * is DT* of the positions the sequential rule gives.
+ *
+ * Query, digest, positions, stats and sync work as for one block holding
+ * every point (kdt_stats: n_blocks = 1); the per-block move calls return
+ * KDT_E_STATE on a global context. */
+
+/* Workspace of a global context: n points (4 .. 2^22), 2^depth kd cells
+ * (0 <= depth <= 20, 2^depth <= n), at most max_moves moves per step. */
+int kdt_workspace_size_global(int64_t n, int32_t depth, int32_t max_moves, size_t* dev_bytes);
+
+/* Build the global DT* on the device (all threads of the GPU insert points
+ * at once; Sec. IV, "Insertion").  xy: host int32 [n][2], distinct, not all
+ * collinear, inside domain = host int32 [4] (x0, y0, x1, y1), a half-open
+ * rectangle in [0, 2^24).  Errors as for kdt_init. */
+int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, const int32_t* domain,
+                    int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream);
+
+/* Run n_steps steps.  moves: dev kdt_move_t [*] with point = global id;
+ * step_off: HOST int64 [n_steps + 1], step t = moves step_off[t] ..
+ * step_off[t+1]-1 (at most max_moves).  applied: dev int8 indexed like
+ * moves (1 applied, 0 blocked) or NULL.  Asynchronous. */
+int kdt_run_global(kdt_ctx* ctx, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                   int8_t* applied);
+
+/* Rebuild the whole DT* from scratch from the current positions with the
+ * device builder (the full-rebuild alternative the paper weighs against
+ * updating, Sec. I).  Synchronises. */
+int kdt_rebuild_global(kdt_ctx* ctx);
+
+/* kd cell of every point's current position: host int32 [n]. */
+int kdt_owner(kdt_ctx* ctx, int32_t* host_owner);
+
+/* Counters of the global mode: host uint64 [KDT_GSTAT_N]. */
+#define KDT_GSTAT_INTERACTING 0  /* moves sharing a cell with another move of their step */
+#define KDT_GSTAT_SERIAL 1       /* moves run by the ordered pass */
+#define KDT_GSTAT_LOST 2         /* plans that lost a claim (retried or passed on) */
+#define KDT_GSTAT_TRANSFERS 3    /* applied moves that changed the point's kd cell */
+#define KDT_GSTAT_OVERFLOW 4     /* plans too large for a reservation (ordered pass) */
+#define KDT_GSTAT_BUILD_ROUNDS 5 /* reservation rounds of the builds so far */
+#define KDT_GSTAT_N 8
+int kdt_global_stats(kdt_ctx* ctx, uint64_t* host_counters);
+
 /* Wait for the stream; return the first sticky error, or KDT_OK. */
 int kdt_sync(kdt_ctx* ctx);
 

@@ -71,16 +71,6 @@ __device__ void fail_block(const DevState& s, int b, int code) {
     }
 }
 
-__device__ __forceinline__ Tri make_tri(int a, int b, int c, int2 pa, int2 pb, int2 pc, int na, int nb,
-                                        int nc) {
-    Tri t;
-    t.v = make_int4(a, b, c, 0);
-    t.n = make_int4(na, nb, nc, 0);
-    t.c01 = make_int4(pa.x, pa.y, pb.x, pb.y);
-    t.c2 = c == GHOST ? make_int4(0, 0, 0, 0) : make_int4(pc.x, pc.y, 0, 0);
-    return t;
-}
-
 // Every block's DT* from scratch, all threads of a workgroup inserting in
 // parallel (kdt_pbuild.hpp); `owner`: one int per triangle slot (scratch).
 constexpr int PB_THREADS = 128;
@@ -101,8 +91,18 @@ __global__ void __launch_bounds__(PB_THREADS) k_pbuild(DevState s, int* owner) {
 //  4. write the changes back.
 // Returns ST_OK (applied or blocked; *applied tells which) or an error, in
 // which case memory is unchanged.
+// In MV_PLAN mode nothing is written back: the move's records stay in the
+// table, *applied is 2 and *plan tells what the move read (the k star slots,
+// the table's used entries, the walk path in S.wpath); the caller empties
+// the table.  Counters are kept only when st is given.
+constexpr int MV_APPLY = 0;
+constexpr int MV_PLAN = 1;
+struct MovePlan {
+    int k, used, npath;
+};
+
 __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
-                          BlockStats* st, int* applied) {
+                          BlockStats* st, int* applied, int mode = MV_APPLY, MovePlan* plan = nullptr) {
     const int lane = lane_id();
     *applied = 0;
     const int p = mv.point, dir = mv.dir, dist = mv.dist;
@@ -114,11 +114,13 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     else if (dir == 2) qy += dist;
     else qy -= dist;
     if (qx < fr.x || qx >= fr.z || qy < fr.y || qy >= fr.w) {
-        if (lane == 0) st->blocked += 1;
+        if (lane == 0 && st) st->blocked += 1;
         return ST_OK;
     }
     const int2 q = make_int2((int)qx, (int)qy);
     const long long c0 = wall_clock64();
+    int npath = 0;
+    int* path = mode == MV_PLAN ? S.wpath : nullptr;
     int used = 0, nvt = 0;
     const int k = gather_star(B, S, p, &used, st);
     if (k < 0) return k;
@@ -128,13 +130,13 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     int hops = 0, tq = -1;
     if (!in_star) {
         int hit;
-        tq = walk<false>(B, &S, S.star_slot[0], q, &hit, &hops);
+        tq = walk<false>(B, &S, S.star_slot[0], q, &hit, &hops, path, &npath);
         if (tq < 0) return ST_INTERNAL;
         on_vertex = hit >= 0;
     }
     if (on_vertex) {
         table_clear(S);
-        if (lane == 0) {
+        if (lane == 0 && st) {
             st->blocked += 1;
             st->walk_sum += hops;
         }
@@ -149,10 +151,15 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     if (fast) {
         rc = fill_star(B, S, k, p, q, true, &used, &nvt, st);
         if (rc != ST_OK) return rc;
+        if (mode == MV_PLAN) {
+            *plan = MovePlan{k, used, npath};
+            *applied = 2;
+            return ST_OK;
+        }
         commit(B, S, used, nvt, nvt);
         if (lane == 0) B.xy[p] = q;
         const long long c4 = wall_clock64();
-        if (lane == 0) {
+        if (lane == 0 && st) {
             const long long dt = c4 - c0;
             st->hist[dt <= 1 ? 0 : min(15, 63 - __clzll(dt))] += 1;
             st->t_star += c1 - c0;
@@ -179,17 +186,22 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
             seed = S.star_slot[first_lane(m)];
         } else {
             int hit2;
-            seed = walk<true>(B, &S, S.star_slot[0], q, &hit2, &hops);
+            seed = walk<true>(B, &S, S.star_slot[0], q, &hit2, &hops, path, &npath);
             if (seed < 0 || hit2 >= 0) return ST_INTERNAL;
         }
     }
     const int nvt_del = nvt;
     rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], &used, &nvt, st);
     if (rc != ST_OK) return rc;
+    if (mode == MV_PLAN) {
+        *plan = MovePlan{k, used, npath};
+        *applied = 2;
+        return ST_OK;
+    }
     commit(B, S, used, nvt_del, nvt);
     if (lane == 0) B.xy[p] = q;
     const long long c4 = wall_clock64();
-    if (lane == 0) {
+    if (lane == 0 && st) {
         const long long dt = c4 - c0;
         st->hist[dt <= 1 ? 0 : min(15, 63 - __clzll(dt))] += 1;
         st->t_star += c1 - c0;
@@ -439,6 +451,492 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
     }
 }
 
+// ------------------------------------------------------------------ global mode
+// One triangulation over every point (the whole set is block 0 of the
+// state), changed by many wavefronts at once.  A time step:
+//   1. k_g_prep, k_g_classify: every move's source and target cell go into a
+//      hash of the step's cells.  A move whose cells are named by no other
+//      move of the step commutes with all of them: its target is held at its
+//      turn in list order exactly when it is held at the start of the step.
+//      The other ("interacting") moves wait for the ordered pass;
+//   2. rounds of k_g_plan / k_g_commit (deterministic reservations): a
+//      wavefront plans its move without writing (apply_move, MV_PLAN) and
+//      claims every triangle slot the plan read with an atomic maximum of
+//      its stamp (round, priority).  After the kernel boundary a wavefront
+//      that holds all its claims plans again -- nothing it read has changed,
+//      since every writer holds the claims of all it reads and writes -- and
+//      commits; the others try again in the next round;
+//   3. k_g_serial: the interacting moves and those still pending after the
+//      last round, in list order, by one wavefront.
+// The result is the sequential rule of the oracle: moves in list order,
+// each blocked when its target cell is outside the domain or held.
+
+constexpr int G_ROUNDS = 3;           // reservation rounds per step
+constexpr int RSMAX = 384;            // slots a planned move may read
+constexpr int G_SERIAL_LDS = 2048;    // ordered-pass entries sorted in LDS
+constexpr int MS_PEND = 0, MS_DONE = 1, MS_SERIAL = 2;
+constexpr int GB_CHUNK = 1 << 17;     // points the grid-wide builder plans at once
+constexpr int GB_BIG = 1 << 14;       // cavity capacity of a deferred point's attempt
+constexpr int GB_DEFER = 1 << 16;     // deferred points of one build
+constexpr int GB_ROUNDS = 64;         // rounds of one chunk before its points are deferred
+// g.ctr entries
+constexpr int GC_STAMP = 0, GC_DONE = 1, GC_SERIAL = 2, GC_USED = 3, GC_PEND = 4, GC_DEFER = 5,
+              GC_KIDX = 6, GC_N = 16;
+
+struct GlobalDev {
+    unsigned long long* claim;  // per triangle slot: stamp of the highest claim so far
+    int* mstate;                // per move of the step: MS_*
+    int* rs;                    // per move: the RSMAX slots its plan read
+    int* rsn;                   // per move: slots in rs (0: no plan this round)
+    unsigned long long* hkey;   // cell hash: cell key + 1, or 0 when empty
+    int* hcnt;                  // moves naming the cell
+    int hmask;
+    int* ctr;                   // GC_* counters
+    int* serial;                // ordered-pass list (move indices, any order)
+    const int2* split;          // kd split keys in heap order (root 1)
+    int depth;
+    int* powner;                // kd cell holding each point
+    unsigned long long* gstats; // KDT_GSTAT_* counters
+};
+
+struct GBuild {
+    const int* ord;  // every point, Hilbert order
+    int* att;        // GB_CHUNK interleaved attempts
+    int* pend;       // per chunk entry: still to insert
+    int2* plan;      // per chunk entry: (cavity, boundary) sizes of this round's plan
+    int* deferred;   // deferred indices into ord
+    int* big;        // the attempt of a deferred point
+};
+
+__device__ void fail_global(const DevState& s, int code) {
+    s.status[0] = code;
+    atomicMin(s.sticky, code);
+}
+
+__device__ __forceinline__ void claim_max(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long claim_get(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Later rounds stamp higher; within a round the smaller priority wins.
+__device__ __forceinline__ unsigned long long stamp_of(int round, int prio) {
+    return ((unsigned long long)(unsigned)round << 32) | (0xffffffffu - (unsigned)prio);
+}
+
+__device__ __forceinline__ unsigned long long cell_key(int2 p) {
+    return (((unsigned long long)(unsigned)p.x << 24) | (unsigned)p.y) + 1ull;
+}
+__device__ __forceinline__ int cell_slot(unsigned long long k, int mask) {
+    return (int)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask;
+}
+// The table holds at least 8 entries per move, so a free entry is found.
+__device__ void cell_add(const GlobalDev& g, unsigned long long k) {
+    int h = cell_slot(k, g.hmask);
+    for (int i = 0; i <= g.hmask; ++i) {
+        const unsigned long long prev = atomicCAS(&g.hkey[h], 0ull, k);
+        if (prev == 0ull || prev == k) {
+            atomicAdd(&g.hcnt[h], 1);
+            return;
+        }
+        h = (h + 1) & g.hmask;
+    }
+}
+__device__ int cell_count(const GlobalDev& g, unsigned long long k) {
+    int h = cell_slot(k, g.hmask);
+    for (int i = 0; i <= g.hmask; ++i) {
+        const unsigned long long cur = g.hkey[h];
+        if (cur == k) return g.hcnt[h];
+        if (cur == 0ull) return 0;
+        h = (h + 1) & g.hmask;
+    }
+    return 0;
+}
+
+__device__ __forceinline__ bool move_target(int2 o, int dir, int dist, int4 fr, int2* q) {
+    long long qx = o.x, qy = o.y;
+    if (dir == 0) qx += dist;
+    else if (dir == 1) qx -= dist;
+    else if (dir == 2) qy += dist;
+    else qy -= dist;
+    const bool in = qx >= fr.x && qx < fr.z && qy >= fr.y && qy < fr.w;
+    *q = in ? make_int2((int)qx, (int)qy) : o;
+    return in;
+}
+
+// kd cell of a position: from the root, right iff its key -- (x, y) at even
+// levels, (y, x) at odd ones -- is not below the node's split key.
+__device__ int kd_cell_of(const int2* split, int depth, int2 p) {
+    int k = 1;
+    for (int l = 0; l < depth; ++l) {
+        const int2 sk = split[k];
+        const int a = (l & 1) ? p.y : p.x, b = (l & 1) ? p.x : p.y;
+        k = 2 * k + ((a > sk.x || (a == sk.x && b >= sk.y)) ? 1 : 0);
+    }
+    return k - (1 << depth);
+}
+
+// After an applied move of p (by this lane): the point's kd cell.
+__device__ void update_owner(const DevState& s, const GlobalDev& g, int p) {
+    const int cell = kd_cell_of(g.split, g.depth, s.xy[p]);
+    if (cell != g.powner[p]) {
+        g.powner[p] = cell;
+        atomicAdd(&g.gstats[KDT_GSTAT_TRANSFERS], 1ull);
+    }
+}
+
+__device__ __forceinline__ void stats_zero(WaveLDS& S) {
+    constexpr int NF = sizeof(BlockStats) / sizeof(long long);
+    if (lane_id() < NF) reinterpret_cast<long long*>(&S.st)[lane_id()] = 0;
+    wsync();
+}
+__device__ __forceinline__ void stats_flush(const DevState& s, WaveLDS& S) {
+    constexpr int NF = sizeof(BlockStats) / sizeof(long long);
+    wsync();
+    if (lane_id() < NF) {
+        const long long v = reinterpret_cast<const long long*>(&S.st)[lane_id()];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[0]) + lane_id(), (unsigned long long)v);
+    }
+}
+
+// The last workgroup of a kernel to get here advances the round stamp.
+__device__ void round_done(const GlobalDev& g) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&g.ctr[GC_DONE], 1) == (int)gridDim.x - 1) {
+            atomicExch(&g.ctr[GC_DONE], 0);
+            atomicAdd(&g.ctr[GC_STAMP], 1);
+        }
+    }
+}
+
+__global__ void k_set(int* p, int v) { *p = v; }
+
+__global__ void k_zero(int* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_g_prep(DevState s, GlobalDev g, const kdt_move_t* __restrict__ mv, int M,
+                         int8_t* applied) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const kdt_move_t r = mv[m];
+    g.rsn[m] = 0;
+    if (applied) applied[m] = 0;
+    if (r.point < 0 || r.point >= (int)s.pt_off[1] || r.dir < 0 || r.dir > 3 || r.dist < 1) {
+        g.mstate[m] = MS_DONE;
+        fail_global(s, ST_ARG);
+        return;
+    }
+    g.mstate[m] = MS_PEND;
+    const int2 o = s.xy[r.point];
+    int2 q;
+    cell_add(g, cell_key(o));
+    if (move_target(o, r.dir, r.dist, s.frame[0], &q)) cell_add(g, cell_key(q));
+}
+
+__global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restrict__ mv, int M) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || g.mstate[m] != MS_PEND) return;
+    const kdt_move_t r = mv[m];
+    const int2 o = s.xy[r.point];
+    int2 q;
+    if (!move_target(o, r.dir, r.dist, s.frame[0], &q)) {  // outside the domain: blocked
+        g.mstate[m] = MS_DONE;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[0].blocked), 1ull);
+        return;
+    }
+    if (cell_count(g, cell_key(o)) > 1 || cell_count(g, cell_key(q)) > 1) {
+        g.mstate[m] = MS_SERIAL;
+        g.serial[atomicAdd(&g.ctr[GC_SERIAL], 1)] = m;
+        atomicAdd(&g.gstats[KDT_GSTAT_INTERACTING], 1ull);
+    }
+}
+
+__global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
+                                                 const kdt_move_t* __restrict__ mv, int M) {
+    __shared__ WaveLDS S;
+    const int m = blockIdx.x;
+    if (m >= M || g.mstate[m] != MS_PEND || s.status[0] != 0) return;
+    const int lane = lane_id();
+    scratch_init(S);
+    BlockView B = view_of(s, 0);
+    MovePlan pl{0, 0, 0};
+    int app = 0;
+    const int rc = apply_move(B, S, mv[m], s.frame[0], nullptr, &app, MV_PLAN, &pl);
+    if (rc != ST_OK) {
+        if (lane == 0) {
+            g.mstate[m] = MS_DONE;
+            fail_global(s, rc);
+        }
+        return;
+    }
+    if (app == 0) {  // target held by a point that stays put this step
+        if (lane == 0) {
+            g.mstate[m] = MS_DONE;
+            atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[0].blocked), 1ull);
+        }
+        return;
+    }
+    const int total = pl.k + pl.used + pl.npath;
+    if (pl.npath > WPMAX || total > RSMAX) {
+        if (lane == 0) {
+            g.mstate[m] = MS_SERIAL;
+            g.serial[atomicAdd(&g.ctr[GC_SERIAL], 1)] = m;
+            atomicAdd(&g.gstats[KDT_GSTAT_OVERFLOW], 1ull);
+        }
+        return;
+    }
+    const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
+    int* out = g.rs + (long long)m * RSMAX;
+    for (int i = lane; i < total; i += WAVE) {
+        const int slot = i < pl.k ? S.star_slot[i]
+                                  : (i < pl.k + pl.used ? S.tkey[S.tused[i - pl.k]] : S.wpath[i - pl.k - pl.used]);
+        out[i] = slot;
+        claim_max(&g.claim[slot], stamp);
+    }
+    if (lane == 0) g.rsn[m] = total;
+}
+
+__global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
+                                                   const kdt_move_t* __restrict__ mv, int M, int last,
+                                                   int8_t* applied) {
+    __shared__ WaveLDS S;
+    const int m = blockIdx.x;
+    const int lane = lane_id();
+    if (m < M && g.mstate[m] == MS_PEND && s.status[0] == 0) {
+        const int nrs = g.rsn[m];
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
+        const int* in = g.rs + (long long)m * RSMAX;
+        bool held = nrs > 0;
+        for (int i = lane; i < nrs; i += WAVE) held &= claim_get(&g.claim[in[i]]) == stamp;
+        const bool won = nrs > 0 && !ballot(!held && lane < nrs);
+        if (won) {
+            scratch_init(S);
+            stats_zero(S);
+            BlockView B = view_of(s, 0);
+            int app = 0;
+            const int rc = apply_move(B, S, mv[m], s.frame[0], &S.st, &app);
+            if (lane == 0) {
+                if (rc != ST_OK) {
+                    fail_global(s, rc);
+                } else if (app) {
+                    update_owner(s, g, mv[m].point);
+                    if (applied) applied[m] = 1;
+                }
+                g.mstate[m] = MS_DONE;
+            }
+            stats_flush(s, S);
+        } else if (lane == 0) {
+            g.rsn[m] = 0;
+            atomicAdd(&g.gstats[KDT_GSTAT_LOST], 1ull);
+            if (last) {
+                g.mstate[m] = MS_SERIAL;
+                g.serial[atomicAdd(&g.ctr[GC_SERIAL], 1)] = m;
+            }
+        }
+    }
+    round_done(g);
+}
+
+__global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
+                                                   const kdt_move_t* __restrict__ mv, int M,
+                                                   int8_t* applied) {
+    __shared__ WaveLDS S;
+    __shared__ int tmp[G_SERIAL_LDS], list[G_SERIAL_LDS];
+    const int lane = lane_id();
+    const int cnt = g.ctr[GC_SERIAL];
+    scratch_init(S);
+    stats_zero(S);
+    BlockView B = view_of(s, 0);
+    const int4 fr = s.frame[0];
+    auto one = [&](int m) {
+        int app = 0;
+        const int rc = apply_move(B, S, mv[m], fr, &S.st, &app);
+        if (lane == 0) {
+            if (rc != ST_OK) fail_global(s, rc);
+            else if (app) update_owner(s, g, mv[m].point);
+            if (applied) applied[m] = (int8_t)app;
+            g.mstate[m] = MS_DONE;
+        }
+        gsync();  // this move's stores are visible to the next
+        return rc;
+    };
+    if (s.status[0] == 0 && cnt > 0) {
+        if (cnt <= G_SERIAL_LDS) {
+            // list order: an entry's rank is the number of smaller entries
+            for (int i = lane; i < cnt; i += WAVE) tmp[i] = g.serial[i];
+            wsync();
+            for (int i = lane; i < cnt; i += WAVE) {
+                const int v = tmp[i];
+                int r = 0;
+                for (int j = 0; j < cnt; ++j) r += tmp[j] < v ? 1 : 0;
+                list[r] = v;
+            }
+            wsync();
+            for (int i = 0; i < cnt; ++i) {
+                const int m = list[i];
+                if (m < 0 || m >= M) {  // the list names each move at most once
+                    if (lane == 0) fail_global(s, ST_INTERNAL);
+                    break;
+                }
+                if (one(m) != ST_OK) break;
+            }
+        } else {
+            bool ok = true;
+            for (int base = 0; base < M && ok; base += WAVE) {
+                uint64_t mask = ballot(base + lane < M && g.mstate[base + lane] == MS_SERIAL);
+                while (mask && ok) {
+                    const int j = first_lane(mask);
+                    mask &= mask - 1;
+                    ok = one(base + j) == ST_OK;
+                }
+            }
+        }
+        if (lane == 0) atomicAdd(&g.gstats[KDT_GSTAT_SERIAL], (unsigned long long)cnt);
+    }
+    stats_flush(s, S);
+    if (lane == 0) g.ctr[GC_SERIAL] = 0;
+}
+
+// ---- grid-wide builder: the rounds of the block builder with every chunk
+// of a level planned by one thread per point, claims stamped per round
+
+__global__ void k_gb_kidx(DevState s, GlobalDev g, GBuild gb) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x + 2;
+    const int n = (int)s.pt_off[1];
+    if (i >= n) return;
+    const int2 a = s.xy[gb.ord[0]], b = s.xy[gb.ord[1]];
+    if (orient(a, b, s.xy[gb.ord[i]]) != 0) atomicMin(&g.ctr[GC_KIDX], (int)i);
+}
+
+__global__ void k_gb_seed(DevState s, GlobalDev g, GBuild gb) {
+    const int kidx = g.ctr[GC_KIDX];
+    if (kidx >= (int)s.pt_off[1]) {
+        fail_global(s, ST_DEGEN);
+        return;
+    }
+    BlockView B = view_of(s, 0);
+    seed_triangle(B, gb.ord[0], gb.ord[1], gb.ord[kidx]);
+    g.ctr[GC_USED] = 4;
+    g.ctr[GC_DEFER] = 0;
+}
+
+__global__ void k_gb_chunk(GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const long long i = lvl + 2LL * lvl * (j0 + t);
+    gb.pend[t] = (i != 1 && i != g.ctr[GC_KIDX]) ? 1 : 0;
+    gb.plan[t] = make_int2(0, 0);
+}
+
+__global__ void k_gb_plan(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt || !gb.pend[t] || s.status[0] != 0) return;
+    BlockView B = view_of(s, 0);
+    const int i = (int)(lvl + 2LL * lvl * (j0 + t));
+    const int v = gb.ord[i];
+    const int used = g.ctr[GC_USED];
+    const int hs = B.vtri[gb.ord[i - lvl]];
+    const int hint = hs >= 0 && hs < used ? hs : 0;
+    const AttView A{gb.att + t, GB_CHUNK, TCM};
+    int nc = 0, nb = 0;
+    const int rc = tplan(B, v, B.xy[v], hint, A, &nc, &nb);
+    if (rc == 0) {
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(i));
+        for (int m = 0; m < nc; ++m) claim_max(&g.claim[A.cav(m)], stamp);
+        for (int e = 0; e < nb; ++e) claim_max(&g.claim[A.bout(e) >> 2], stamp);
+        gb.plan[t] = make_int2(nc, nb);
+    } else {
+        gb.pend[t] = 0;
+        if (rc == 1) {  // cavity too large for one thread's attempt: at the end, alone
+            const int d = atomicAdd(&g.ctr[GC_DEFER], 1);
+            if (d < GB_DEFER) gb.deferred[d] = i;
+            else fail_global(s, ST_CAPACITY);
+        } else {
+            fail_global(s, rc);
+        }
+    }
+}
+
+__global__ void k_gb_commit(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    BlockView B = view_of(s, 0);
+    int i = 0;
+    int2 pl = make_int2(0, 0);
+    bool won = false, pend = false;
+    const AttView A{gb.att + t, GB_CHUNK, TCM};
+    if (t < cnt && gb.pend[t] && s.status[0] == 0) {
+        pend = true;
+        pl = gb.plan[t];
+        i = (int)(lvl + 2LL * lvl * (j0 + t));
+        if (pl.x > 0) {
+            const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(i));
+            won = true;
+            for (int m = 0; m < pl.x; ++m) won &= claim_get(&g.claim[A.cav(m)]) == stamp;
+            for (int e = 0; e < pl.y; ++e) won &= claim_get(&g.claim[A.bout(e) >> 2]) == stamp;
+            gb.plan[t] = make_int2(0, 0);
+        }
+    }
+    // two fresh slots per winner, one atomic per wavefront (this kernel's
+    // workgroups hold several wavefronts: lanes are counted within the wave)
+    const int wl = (int)(threadIdx.x & (WAVE - 1));
+    const uint64_t wm = ballot(won);
+    int base = 0;
+    if (wm) {
+        const int leader = first_lane(wm);
+        if (wl == leader) base = atomicAdd(&g.ctr[GC_USED], 2 * __popcll(wm));
+        base = __shfl(base, leader);
+    }
+    if (won) {
+        const int f = base + 2 * __popcll(wm & ((1ull << wl) - 1ull));
+        const int v = gb.ord[i];
+        const int rc = f + 1 < B.ntri ? tcommit(B, A, pl.x, pl.y, v, B.xy[v], f, f + 1) : ST_INTERNAL;
+        if (rc != ST_OK) fail_global(s, rc);
+        gb.pend[t] = 0;
+        pend = false;
+    }
+    const uint64_t pm = ballot(pend);
+    if (pm && wl == first_lane(pm)) atomicAdd(&g.ctr[GC_PEND], __popcll(pm));
+    round_done(g);
+}
+
+__global__ void k_gb_defer_rest(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt || !gb.pend[t]) return;
+    gb.pend[t] = 0;
+    const int d = atomicAdd(&g.ctr[GC_DEFER], 1);
+    if (d < GB_DEFER) gb.deferred[d] = (int)(lvl + 2LL * lvl * (j0 + t));
+    else fail_global(s, ST_CAPACITY);
+}
+
+// Deferred points one by one (one thread), then the slot count check.
+__global__ void k_gb_serial(DevState s, GlobalDev g, GBuild gb) {
+    BlockView B = view_of(s, 0);
+    const int nd = min(g.ctr[GC_DEFER], GB_DEFER);
+    const AttView A{gb.big, 1, GB_BIG};
+    for (int d = 0; d < nd && s.status[0] == 0; ++d) {
+        const int i = gb.deferred[d];
+        const int v = gb.ord[i];
+        const int used = g.ctr[GC_USED];
+        const int hs = B.vtri[gb.ord[i - 1]];
+        int nc = 0, nb = 0;
+        const int rc = tplan(B, v, B.xy[v], hs >= 0 && hs < used ? hs : 0, A, &nc, &nb);
+        if (rc != 0) {
+            fail_global(s, rc == 1 ? ST_CAPACITY : rc);
+            return;
+        }
+        g.ctr[GC_USED] = used + 2;
+        const int rc2 = used + 1 < B.ntri ? tcommit(B, A, nc, nb, v, B.xy[v], used, used + 1) : ST_INTERNAL;
+        if (rc2 != ST_OK) {
+            fail_global(s, rc2);
+            return;
+        }
+    }
+    if (s.status[0] == 0 && g.ctr[GC_USED] != B.ntri) fail_global(s, ST_INTERNAL);
+}
+
 // ------------------------------------------------------------------ MLP
 
 __global__ void k_mlp_forward(const float* __restrict__ W, const float* __restrict__ X, long long n,
@@ -598,6 +1096,61 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     return L;
 }
 
+// Global mode: the extra regions after the per-block layout of one block.
+struct GLayout {
+    size_t claim, mstate, rs, rsn, hkey, hcnt, ctr, serial, split, powner, gstats, att, pend, plan,
+        deferred, big, total;
+    int hsize;
+};
+
+GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves) {
+    GLayout G;
+    size_t o = align_up(base);
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    const int64_t ntri = 2 * n - 2;
+    int hs = 1024;
+    while (hs < 8 * (int64_t)max_moves) hs *= 2;
+    G.hsize = hs;
+    G.claim = take(sizeof(unsigned long long) * ntri);
+    G.mstate = take(sizeof(int) * max_moves);
+    G.rs = take(sizeof(int) * (size_t)RSMAX * max_moves);
+    G.rsn = take(sizeof(int) * max_moves);
+    G.hkey = take(sizeof(unsigned long long) * hs);
+    G.hcnt = take(sizeof(int) * hs);
+    G.ctr = take(sizeof(int) * GC_N);
+    G.serial = take(sizeof(int) * max_moves);
+    G.split = take(sizeof(int2) * ((size_t)1 << depth));
+    G.powner = take(sizeof(int) * n);
+    G.gstats = take(sizeof(unsigned long long) * KDT_GSTAT_N);
+    G.att = take(sizeof(int) * (size_t)ATT_INTS * GB_CHUNK);
+    G.pend = take(sizeof(int) * GB_CHUNK);
+    G.plan = take(sizeof(int2) * GB_CHUNK);
+    G.deferred = take(sizeof(int) * GB_DEFER);
+    G.big = take(sizeof(int) * (4 * (size_t)GB_BIG + 6));
+    G.total = o;
+    return G;
+}
+
+// kd partition of the initial points: node `node` at `level` keeps the
+// first half (by (x, y) at even levels, (y, x) at odd ones) on the left and
+// records the key of the first right point; leaves give each point its cell.
+void kd_build(const int32_t* xy, std::vector<int>& idx, size_t lo, size_t hi, int node, int level,
+              int depth, std::vector<int2>& split, std::vector<int>& cell) {
+    if (level == depth) {
+        for (size_t i = lo; i < hi; ++i) cell[idx[i]] = node - (1 << depth);
+        return;
+    }
+    const int d = level & 1;
+    auto key = [&](int a) { return std::make_pair(xy[2 * (size_t)a + d], xy[2 * (size_t)a + 1 - d]); };
+    const size_t h = lo + (hi - lo) / 2;
+    std::nth_element(idx.begin() + lo, idx.begin() + h, idx.begin() + hi,
+                     [&](int a, int b) { return key(a) < key(b); });
+    const auto k = key(idx[h]);
+    split[node] = make_int2(k.first, k.second);
+    kd_build(xy, idx, lo, h, 2 * node, level + 1, depth, split, cell);
+    kd_build(xy, idx, h, hi, 2 * node + 1, level + 1, depth, split, cell);
+}
+
 // Hilbert index of (x, y) on a 2^16 x 2^16 grid (classic rotate-and-flip
 // construction); used only to order insertions for short walks.
 uint64_t hilbert16(uint32_t x, uint32_t y) {
@@ -634,6 +1187,14 @@ struct kdt_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
     size_t ev_used = 0;
+    // global mode: one triangulation over all points (block 0)
+    bool global = false;
+    int32_t depth = 0;
+    int32_t max_moves = 0;
+    int hsize = 0;
+    GlobalDev g{};
+    GBuild gb{};
+    long long build_rounds = 0;
 };
 
 namespace {
@@ -673,6 +1234,48 @@ void release_events(kdt_ctx* c) {
 
 int64_t orient_h(const int32_t* a, const int32_t* b, const int32_t* c) {
     return (int64_t)(b[0] - a[0]) * (c[1] - a[1]) - (int64_t)(b[1] - a[1]) * (c[0] - a[0]);
+}
+
+// Build the global DT* from the current positions with the grid-wide
+// builder: Hilbert-order levels, chunks of GB_CHUNK points, reservation
+// rounds until a chunk is done (the host reads the pending count after each
+// round), then the deferred points one by one.
+int gbuild(kdt_ctx* c) {
+    hipStream_t st = c->stream;
+    const int n = (int)c->n;
+    k_set<<<1, 1, 0, st>>>(c->g.ctr + GC_KIDX, 0x7fffffff);
+    k_gb_kidx<<<(n - 2 + 255) / 256, 256, 0, st>>>(c->dev, c->g, c->gb);
+    k_gb_seed<<<1, 1, 0, st>>>(c->dev, c->g, c->gb);
+    if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
+    int top = 1;
+    while (top * 2 < n) top *= 2;
+    for (int lvl = top; lvl >= 1; lvl >>= 1) {
+        const long long count = (n - 1 - lvl) / (2LL * lvl) + 1;
+        for (long long j0 = 0; j0 < count; j0 += GB_CHUNK) {
+            const int cnt = (int)std::min<long long>(GB_CHUNK, count - j0);
+            const int grid = (cnt + 255) / 256;
+            k_gb_chunk<<<grid, 256, 0, st>>>(c->g, c->gb, lvl, j0, cnt);
+            int r = 0;
+            for (; r < GB_ROUNDS; ++r) {
+                k_set<<<1, 1, 0, st>>>(c->g.ctr + GC_PEND, 0);
+                k_gb_plan<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
+                k_gb_commit<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
+                int pend = 0;
+                if (check_hip(c, hipGetLastError()) ||
+                    check_hip(c, hipMemcpyAsync(&pend, c->g.ctr + GC_PEND, sizeof(int), hipMemcpyDeviceToHost, st)) ||
+                    check_hip(c, hipStreamSynchronize(st)))
+                    return KDT_E_DEVICE;
+                ++c->build_rounds;
+                if (pend == 0) break;
+            }
+            if (r == GB_ROUNDS) k_gb_defer_rest<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
+        }
+    }
+    k_gb_serial<<<1, 1, 0, st>>>(c->dev, c->g, c->gb);
+    if (check_hip(c, hipGetLastError()) || check_hip(c, hipStreamSynchronize(st))) return KDT_E_DEVICE;
+    int sticky = 0;
+    if (check_hip(c, hipMemcpy(&sticky, c->dev.sticky, sizeof(int), hipMemcpyDeviceToHost))) return KDT_E_DEVICE;
+    return sticky;
 }
 
 }  // namespace
@@ -847,6 +1450,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
 
 int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist) {
     if (!c) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
     if (block < 0 || block >= c->B) return KDT_E_ARG;
     if (point < c->pt_off[block] || point >= c->pt_off[block + 1]) return KDT_E_ARG;
     if (dir < 0 || dir > 3 || dist < 1) return KDT_E_ARG;
@@ -863,6 +1467,7 @@ int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist
 
 int kdt_step(kdt_ctx* c) {
     if (!c) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
     if (c->sticky != KDT_OK) return KDT_E_STATE;
     // group the staged moves by block, keeping their order within a block
     std::vector<int> idx(c->staged.size());
@@ -940,7 +1545,7 @@ int kdt_run(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_
             int8_t* applied, int32_t flags) {
     if (!c || n_steps < 0 || (n_steps > 0 && (!moves || !step_off))) return KDT_E_ARG;
     if (!valid_flags(flags)) return KDT_E_ARG;
-    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    if (c->sticky != KDT_OK || c->global) return KDT_E_STATE;
     if (n_steps == 0) return KDT_OK;
     return enqueue_steps(c, moves, step_off, n_steps, applied, flags, true);
 }
@@ -955,7 +1560,7 @@ int kdt_graph_build(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off
                     int8_t* applied, int32_t flags, kdt_graph** out) {
     if (!c || !out || n_steps < 1 || !moves || !step_off || !valid_flags(flags)) return KDT_E_ARG;
     *out = nullptr;
-    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    if (c->sticky != KDT_OK || c->global) return KDT_E_STATE;
     if (c->stream == nullptr) return KDT_E_STATE;  // the null stream cannot be captured
     kdt_graph* g = new (std::nothrow) kdt_graph();
     if (!g) return KDT_E_CAPACITY;
@@ -1190,6 +1795,201 @@ int kdt_timing_read(kdt_ctx* c, double* total_ms, int64_t* launches) {
     }
     *total_ms = tot;
     *launches = (int64_t)c->ev_used;
+    return KDT_OK;
+}
+
+int kdt_workspace_size_global(int64_t n, int32_t depth, int32_t max_moves, size_t* dev_bytes) {
+    if (!dev_bytes || n < 1 || depth < 0 || depth > 20 || max_moves < 1 || max_moves > (1 << 22))
+        return KDT_E_ARG;
+    if (n > (1 << 22)) return KDT_E_CAPACITY;
+    const Layout L = make_layout(n, 1, 0);
+    *dev_bytes = make_glayout(L.total, n, depth, max_moves).total;
+    return KDT_OK;
+}
+
+int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, const int32_t* domain,
+                    int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream) {
+    if (!out) return KDT_E_ARG;
+    *out = nullptr;
+    if (!xy || !domain || n < 1 || depth < 0 || depth > 20 || max_moves < 1 || max_moves > (1 << 22))
+        return KDT_E_ARG;
+    if (n < 4) return KDT_E_DEGEN;
+    if (n > (1 << 22)) return KDT_E_CAPACITY;
+    if (n < ((int64_t)1 << depth)) return KDT_E_ARG;
+    const int32_t* f = domain;
+    if (f[0] < 0 || f[1] < 0 || f[2] > KDT_COORD_LIMIT || f[3] > KDT_COORD_LIMIT || f[0] >= f[2] || f[1] >= f[3])
+        return KDT_E_RANGE;
+    const int4 fr = make_int4(f[0], f[1], f[2], f[3]);
+    int32_t mnx = INT32_MAX, mny = INT32_MAX, mxx = 0, mxy = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < fr.x || x >= fr.z || y < fr.y || y >= fr.w) return KDT_E_RANGE;
+        mnx = std::min(mnx, x); mny = std::min(mny, y);
+        mxx = std::max(mxx, x); mxy = std::max(mxy, y);
+    }
+    std::vector<std::pair<uint64_t, int>> key(n);
+    for (int64_t i = 0; i < n; ++i)
+        key[i] = {((uint64_t)(uint32_t)xy[2 * i] << 32) | (uint32_t)xy[2 * i + 1], (int)i};
+    std::sort(key.begin(), key.end());
+    for (int64_t i = 1; i < n; ++i)
+        if (key[i].first == key[i - 1].first) return KDT_E_DUP;
+    bool off_line = false;
+    for (int64_t i = 2; i < n && !off_line; ++i) off_line = orient_h(xy, xy + 2, xy + 2 * i) != 0;
+    if (!off_line) return KDT_E_DEGEN;
+    // insertion order: Hilbert order over the bounding box
+    const double sx = 65535.0 / std::max(1, mxx - mnx), sy = 65535.0 / std::max(1, mxy - mny);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t hx = (uint32_t)((xy[2 * i] - mnx) * sx), hy = (uint32_t)((xy[2 * i + 1] - mny) * sy);
+        key[i] = {hilbert16(hx, hy), (int)i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> order(n);
+    for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+    // kd cells of the initial points
+    std::vector<int2> split((size_t)1 << depth, make_int2(0, 0));
+    std::vector<int> cell(n), idx(n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+    kd_build(xy, idx, 0, (size_t)n, 1, 0, depth, split, cell);
+
+    const Layout L = make_layout(n, 1, 0);
+    const GLayout G = make_glayout(L.total, n, depth, max_moves);
+    if (!dev_ws || ws_bytes < G.total) return KDT_E_CAPACITY;
+    if (((uintptr_t)dev_ws & 255) != 0) return KDT_E_ARG;
+    kdt_ctx* c = new (std::nothrow) kdt_ctx();
+    if (!c) return KDT_E_CAPACITY;
+    c->stream = (hipStream_t)stream;
+    c->B = 1;
+    c->n = n;
+    c->max_staged = 0;
+    c->ws = (char*)dev_ws;
+    c->L = L;
+    c->sticky = KDT_OK;
+    c->global = true;
+    c->depth = depth;
+    c->max_moves = max_moves;
+    c->hsize = G.hsize;
+    (void)hipGetDevice(&c->device);
+    c->pt_off = {0, (long long)n};
+    c->tri_off = {0, 2 * (long long)n - 2};
+    char* w = c->ws;
+    c->dev.tri = (Tri*)(w + L.tri);
+    c->dev.xy = (int2*)(w + L.xy);
+    c->dev.vtri = (int*)(w + L.vtri);
+    c->dev.pt_off = (const long long*)(w + L.pt_off);
+    c->dev.tri_off = (const long long*)(w + L.tri_off);
+    c->dev.frame = (const int4*)(w + L.frame);
+    c->dev.status = (int*)(w + L.status);
+    c->dev.stats = (BlockStats*)(w + L.stats);
+    c->dev.sticky = (int*)(w + L.sticky);
+    c->dev.order = (const int*)(w + L.order);
+    c->dev.owner = (int*)(w + L.qmap);
+    c->dev.policy = KDT_POLICY_REPAIR;
+    c->dev.n_blocks = 1;
+    c->g.claim = (unsigned long long*)(w + G.claim);
+    c->g.mstate = (int*)(w + G.mstate);
+    c->g.rs = (int*)(w + G.rs);
+    c->g.rsn = (int*)(w + G.rsn);
+    c->g.hkey = (unsigned long long*)(w + G.hkey);
+    c->g.hcnt = (int*)(w + G.hcnt);
+    c->g.hmask = G.hsize - 1;
+    c->g.ctr = (int*)(w + G.ctr);
+    c->g.serial = (int*)(w + G.serial);
+    c->g.split = (const int2*)(w + G.split);
+    c->g.depth = depth;
+    c->g.powner = (int*)(w + G.powner);
+    c->g.gstats = (unsigned long long*)(w + G.gstats);
+    c->gb.ord = (const int*)(w + L.order);
+    c->gb.att = (int*)(w + G.att);
+    c->gb.pend = (int*)(w + G.pend);
+    c->gb.plan = (int2*)(w + G.plan);
+    c->gb.deferred = (int*)(w + G.deferred);
+    c->gb.big = (int*)(w + G.big);
+    hipStream_t s = c->stream;
+    int rc = KDT_OK;
+    int ctr[GC_N] = {0};
+    ctr[GC_STAMP] = 1;
+    // The host arrays are pageable: these copies complete before returning.
+    rc |= check_hip(c, hipMemcpyAsync(w + L.xy, xy, sizeof(int2) * n, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.pt_off, c->pt_off.data(), sizeof(long long) * 2, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.tri_off, c->tri_off.data(), sizeof(long long) * 2, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + L.frame, &fr, sizeof(int4), hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + G.split, split.data(), sizeof(int2) * split.size(), hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + G.powner, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemcpyAsync(w + G.ctr, ctr, sizeof(ctr), hipMemcpyHostToDevice, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int), s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats), s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
+    rc |= check_hip(c, hipMemsetAsync(w + G.claim, 0, sizeof(unsigned long long) * (2 * n - 2), s));
+    rc |= check_hip(c, hipMemsetAsync(w + G.gstats, 0, sizeof(unsigned long long) * KDT_GSTAT_N, s));
+    rc |= check_hip(c, hipMemsetAsync(w + G.hkey, 0, sizeof(unsigned long long) * G.hsize, s));
+    rc |= check_hip(c, hipMemsetAsync(w + G.hcnt, 0, sizeof(int) * G.hsize, s));
+    if (rc == KDT_OK) rc = check_hip(c, hipStreamSynchronize(s));
+    if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
+    rc = gbuild(c);
+    if (rc != KDT_OK) { delete c; return rc; }
+    *out = c;
+    return KDT_OK;
+}
+
+int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                   int8_t* applied) {
+    if (!c || n_steps < 0 || (n_steps > 0 && (!moves || !step_off))) return KDT_E_ARG;
+    if (!c->global || c->sticky != KDT_OK) return KDT_E_STATE;
+    for (int32_t t = 0; t < n_steps; ++t) {
+        const int64_t M = step_off[t + 1] - step_off[t];
+        if (step_off[t] < 0 || M < 0) return KDT_E_ARG;
+        if (M > c->max_moves) return KDT_E_CAPACITY;
+    }
+    hipStream_t st = c->stream;
+    for (int32_t t = 0; t < n_steps; ++t) {
+        const int M = (int)(step_off[t + 1] - step_off[t]);
+        if (M == 0) continue;
+        const kdt_move_t* mv = moves + step_off[t];
+        int8_t* ap = applied ? applied + step_off[t] : nullptr;
+        hipEvent_t e0 = timing_begin(c);
+        k_zero<<<(2 * c->hsize + 255) / 256, 256, 0, st>>>((int*)c->g.hkey, 2LL * c->hsize);
+        k_zero<<<(c->hsize + 255) / 256, 256, 0, st>>>(c->g.hcnt, c->hsize);
+        k_g_prep<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M, ap);
+        k_g_classify<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M);
+        for (int r = 0; r < G_ROUNDS; ++r) {
+            k_g_plan<<<M, WAVE, 0, st>>>(c->dev, c->g, mv, M);
+            k_g_commit<<<M, WAVE, 0, st>>>(c->dev, c->g, mv, M, r == G_ROUNDS - 1 ? 1 : 0, ap);
+        }
+        k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap);
+        timing_end(c, e0);
+        if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
+        c->step_count++;
+    }
+    return KDT_OK;
+}
+
+int kdt_rebuild_global(kdt_ctx* c) {
+    if (!c) return KDT_E_ARG;
+    if (!c->global || c->sticky != KDT_OK) return KDT_E_STATE;
+    const int rc = gbuild(c);
+    if (rc != KDT_OK) c->sticky = rc;
+    return rc;
+}
+
+int kdt_owner(kdt_ctx* c, int32_t* host_owner) {
+    if (!c || !host_owner) return KDT_E_ARG;
+    if (!c->global) return KDT_E_STATE;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    if (check_hip(c, hipMemcpy(host_owner, c->g.powner, sizeof(int32_t) * c->n, hipMemcpyDeviceToHost)))
+        return KDT_E_DEVICE;
+    return KDT_OK;
+}
+
+int kdt_global_stats(kdt_ctx* c, uint64_t* host_counters) {
+    if (!c || !host_counters) return KDT_E_ARG;
+    if (!c->global) return KDT_E_STATE;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    if (check_hip(c, hipMemcpy(host_counters, c->g.gstats, sizeof(uint64_t) * KDT_GSTAT_N, hipMemcpyDeviceToHost)))
+        return KDT_E_DEVICE;
+    host_counters[KDT_GSTAT_BUILD_ROUNDS] = (uint64_t)c->build_rounds;
     return KDT_OK;
 }
 

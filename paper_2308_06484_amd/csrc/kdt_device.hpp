@@ -51,6 +51,7 @@ constexpr int BMAX = CMAX + 2;   // cavity boundary
 constexpr int VTMAX = KMAX + BMAX + 1;  // pending incident-triangle updates
 constexpr int DRYMAX = 256;     // moves of one block in one step on the rebuild branch
 constexpr int EMK = 16;          // links up to this size use the closed-form triple decode and edge matrix
+constexpr int WPMAX = 64;        // walk hops a planned move can record
 
 constexpr int F_DIRTY = 1;  // table entry changed: write back
 constexpr int F_CAV = 2;    // table entry is in the current cavity
@@ -118,6 +119,7 @@ struct WaveLDS {
     int bnd_slot[BMAX];  // slot of the fan triangle on boundary edge i
     int bnd_ph[BMAX];    // its stored index of a (bits 0-1), b (2-3), q (4-5)
     int nhole, pad[3];
+    int wpath[WPMAX];  // slots a planned move's walks read (global mode)
     BlockStats st;  // the block's counters while its wavefront works on it
     // rebuild branch: points moved this step and their new places, and the
     // parallel build's counters and deferred points
@@ -361,12 +363,17 @@ __device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s
 // sitting exactly at q (-1 if none).  Returns -1 if the step limit is hit.
 // TABLE: read through the move's write-back table (after changes).
 template <bool TABLE>
-__device__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops) {
+__device__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops,
+                    int* path = nullptr, int* npath = nullptr) {
     int cur = start, entry = -1;
     const int limit = 4 * B.ntri + 16;
     *hit = -1;
     for (int h = 0; h < limit; ++h) {
         if (bad_slot(B, cur)) return -1;
+        if (path) {  // record the slots read (wave-uniform; lane 0 writes)
+            if (*npath < WPMAX && lane_id() == 0) path[*npath] = cur;
+            ++*npath;
+        }
         const Tri t = TABLE ? tread(B, *S, cur) : B.tri[cur];
         if (bad_tri(B, t.v)) return -1;
         const int2 p0 = cget(t, 0), p1 = cget(t, 1);
@@ -576,6 +583,18 @@ __device__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, in
     }
     wsync();
     for (int u = lane; u < used; u += WAVE) {
+        const int h = S.tused[u];
+        S.tkey[h] = -1;
+        S.tflag[h] = 0;
+    }
+    wsync();
+}
+
+// Empty the table entries of the tused list without writing anything back
+// (a planned move that is not committed).
+__device__ void table_drop(WaveLDS& S, int used) {
+    wsync();
+    for (int u = lane_id(); u < used; u += WAVE) {
         const int h = S.tused[u];
         S.tkey[h] = -1;
         S.tflag[h] = 0;

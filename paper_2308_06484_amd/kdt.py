@@ -26,7 +26,13 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_query_canonical", "kdt_positions", "kdt_stats", "kdt_block_status", "kdt_sync",
            "kdt_destroy", "kdt_strerror", "kdt_timing", "kdt_timing_read", "kdt_set_launch",
            "kdt_graph_build", "kdt_graph_launch", "kdt_graph_destroy", "kdt_digest",
-           "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train")
+           "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
+           "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
+           "kdt_owner", "kdt_global_stats")
+
+# kdt_global_stats counters, in order
+GSTATS = ("interacting", "serial", "lost", "transfers", "overflow", "build_rounds")
+GSTAT_N = 8
 
 
 class KDTError(RuntimeError):
@@ -83,6 +89,12 @@ def _lib():
         L.kdt_graph_launch.argtypes = [vp, vp]
         L.kdt_graph_destroy.argtypes = [vp]
         L.kdt_graph_destroy.restype = None
+        L.kdt_workspace_size_global.argtypes = [i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.kdt_init_global.argtypes = [ctypes.POINTER(vp), vp, i64, i32, vp, i32, vp, ctypes.c_size_t, vp]
+        L.kdt_run_global.argtypes = [vp, vp, vp, i32, vp]
+        L.kdt_rebuild_global.argtypes = [vp]
+        L.kdt_owner.argtypes = [vp, vp]
+        L.kdt_global_stats.argtypes = [vp, vp]
         L.kdt_strerror.argtypes = [ctypes.c_int]
         L.kdt_strerror.restype = ctypes.c_char_p
         _L = L
@@ -320,3 +332,61 @@ class KineticDT:
             self.close()
         except Exception:
             pass
+
+
+def workspace_size_global(n, depth, max_moves):
+    out = ctypes.c_size_t(0)
+    _check(_lib().kdt_workspace_size_global(int(n), int(depth), int(max_moves), ctypes.byref(out)),
+           "kdt_workspace_size_global")
+    return int(out.value)
+
+
+class GlobalDT(KineticDT):
+    """A global-mode context: one DT* over every point of the domain
+    (x0, y0, x1, y1), kd cells of depth `depth`, at most `max_moves` moves
+    per step.  Query, digest, positions and stats as for one block."""
+
+    def __init__(self, xy, domain, depth, max_moves, device="cuda:0", stream=None):
+        L = _lib()
+        self.xy0 = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+        self.domain = np.ascontiguousarray(domain, dtype=np.int32).reshape(4)
+        self.depth = int(depth)
+        self.max_moves = int(max_moves)
+        self.n = self.xy0.shape[0]
+        self.B = 1
+        self.pt_off = np.array([0, self.n], dtype=np.int64)
+        self.device = torch.device(device)
+        ws = workspace_size_global(self.n, self.depth, self.max_moves)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        rc = L.kdt_init_global(ctypes.byref(ctx), _ptr(self.xy0), self.n, self.depth, _ptr(self.domain),
+                               self.max_moves, ctypes.c_void_p(self.ws.data_ptr()), ws,
+                               ctypes.c_void_p(self.stream.cuda_stream))
+        _check(rc, "kdt_init_global")
+        self.ctx = ctx
+
+    def run(self, moves, step_off, applied=None):
+        """moves: device int32 [M, 4] (global point id, dir, dist, 0);
+        step_off: host int64 [T + 1]; applied: device int8 [M] or None."""
+        assert moves.dtype == torch.int32 and moves.is_cuda and moves.is_contiguous()
+        step_off = np.ascontiguousarray(step_off, dtype=np.int64)
+        if applied is not None:
+            assert applied.dtype == torch.int8 and applied.is_cuda
+        _check(_lib().kdt_run_global(self.ctx, ctypes.c_void_p(moves.data_ptr()), _ptr(step_off),
+                                     len(step_off) - 1,
+                                     ctypes.c_void_p(applied.data_ptr()) if applied is not None else None),
+               "kdt_run_global")
+
+    def rebuild(self):
+        _check(_lib().kdt_rebuild_global(self.ctx), "kdt_rebuild_global")
+
+    def owner(self):
+        out = np.empty(self.n, dtype=np.int32)
+        _check(_lib().kdt_owner(self.ctx, _ptr(out)), "kdt_owner")
+        return out
+
+    def gstats(self):
+        out = np.zeros(GSTAT_N, dtype=np.uint64)
+        _check(_lib().kdt_global_stats(self.ctx, _ptr(out)), "kdt_global_stats")
+        return {k: int(out[i]) for i, k in enumerate(GSTATS)}

@@ -1,0 +1,139 @@
+"""Global mode on the device against the global oracle (bit-exact).
+
+After every step the applied flags, the positions, the kd cell of every
+point and the canonical triangle list must equal the oracle's (which
+rebuilds DT* of all points from scratch); at the full size of the global
+workload (4,194,304 points) the comparison is made after the last step.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.kinetic import KineticGlobal
+from paper_2308_06484_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _gdt(w, max_moves=None):
+    from paper_2308_06484_amd.kdt import GlobalDT
+    M = max_moves or max(1, int(np.diff(w["step_off"]).max()))
+    return GlobalDT(w["xy"], [0, 0, w["side"], w["side"]], w["depth"], M, device=DEV)
+
+
+def run_compare(w, steps, check_every=1):
+    G = _gdt(w)
+    K = KineticGlobal(w["xy"], w["side"], w["depth"])
+    assert np.array_equal(G.query_canonical(), K.dt())
+    assert np.array_equal(G.owner(), K.owner())
+    mv = torch.from_numpy(np.ascontiguousarray(w["mv"])).to(DEV)
+    ap = torch.full((len(w["mv"]),), -1, dtype=torch.int8, device=DEV)
+    for t in range(steps):
+        lo, hi = int(w["step_off"][t]), int(w["step_off"][t + 1])
+        G.run(mv, np.array([lo, hi], dtype=np.int64), ap)
+        want = K.apply_step(w["mv"][lo:hi])
+        got = ap[lo:hi].cpu().numpy()
+        assert np.array_equal(got.astype(bool), want) and got.min() >= 0, t
+        if (t + 1) % check_every == 0 or t == steps - 1:
+            assert np.array_equal(G.positions(), K.xy), t
+            assert np.array_equal(G.query_canonical(), K.dt()), t
+            assert np.array_equal(G.owner(), K.owner()), t
+    return G, K
+
+
+def test_global_build():
+    _say("global build: small workloads and a full lattice")
+    for seed in (1, 2):
+        w = W.global_small(seed=seed, steps=1)
+        G = _gdt(w)
+        K = KineticGlobal(w["xy"], w["side"], w["depth"])
+        assert np.array_equal(G.query_canonical(), K.dt())
+        assert np.array_equal(G.owner(), K.owner())
+        G.close()
+    # every cell of a 64 x 64 lattice: cocircular everywhere, ties decided by ids
+    xy = np.array([(x, y) for y in range(64) for x in range(64)], np.int32)
+    xy = xy[np.random.default_rng(0).permutation(len(xy))]
+    from paper_2308_06484_amd.kdt import GlobalDT
+    G = GlobalDT(xy, [0, 0, 64, 64], 3, 8, device=DEV)
+    K = KineticGlobal(xy, 64, 3)
+    assert np.array_equal(G.query_canonical(), K.dt())
+    assert np.array_equal(G.owner(), K.owner())
+
+
+def test_global_small_every_step():
+    _say("global_small: 20 steps")
+    run_compare(W.global_small(seed=1, steps=20), 20)
+
+
+def _dense(seed, steps, n=4096, side=128, depth=4, per_step=96, dmax=3):
+    """Density 1/4 and short moves: many moves share cells (chains, swaps
+    of places, the same point twice in a step, moves off the domain)."""
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(side * side, size=n, replace=False)
+    xy = np.stack([cells % side, cells // side], 1).astype(np.int32)
+    mv = np.zeros((steps * per_step, 4), np.int32)
+    mv[:, 0] = rng.integers(0, n, size=len(mv))
+    mv[:, 1] = rng.integers(0, 4, size=len(mv))
+    mv[:, 2] = rng.integers(1, dmax + 1, size=len(mv))
+    return dict(xy=xy, side=side, depth=depth, mv=mv,
+                step_off=np.arange(steps + 1, dtype=np.int64) * per_step)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_global_dense_interacting(seed):
+    _say(f"global dense: seed {seed}")
+    G, K = run_compare(_dense(seed, 15), 15)
+    gs = G.gstats()
+    assert gs["interacting"] > 0 and gs["serial"] >= gs["interacting"]
+
+
+def test_global_rebuild_matches():
+    _say("global rebuild after steps")
+    w = W.global_small(seed=5, steps=10)
+    G, K = run_compare(w, 10, check_every=10)
+    G.rebuild()
+    assert np.array_equal(G.query_canonical(), K.dt())
+    # and the mode keeps working on the rebuilt triangulation
+    w2 = dict(w, mv=W.global_small(seed=6, steps=5)["mv"], step_off=np.arange(6, dtype=np.int64) * 16)
+    mv = torch.from_numpy(np.ascontiguousarray(w2["mv"])).to(DEV)
+    G.run(mv, w2["step_off"])
+    for t in range(5):
+        K.apply_step(w2["mv"][t * 16:(t + 1) * 16])
+    assert np.array_equal(G.positions(), K.xy)
+    assert np.array_equal(G.query_canonical(), K.dt())
+
+
+def test_global_rejects_block_calls_and_bad_moves():
+    from paper_2308_06484_amd.kdt import KDTError
+    w = W.global_small(seed=7, steps=2)
+    G = _gdt(w)
+    with pytest.raises(KDTError):
+        G.step()
+    too_many = torch.zeros((w["mv"].shape[0] * 2, 4), dtype=torch.int32, device=DEV)
+    with pytest.raises(KDTError):
+        G.run(too_many, np.array([0, len(too_many)], dtype=np.int64))
+
+
+@pytest.mark.timeout(900)
+def test_global4m_full_size():
+    _say("global4m: 4,194,304 points, 3 steps (oracle rebuilds the full DT*)")
+    w = W.global4m(seed=1, steps=3)
+    G = _gdt(w)
+    K = KineticGlobal(w["xy"], w["side"], w["depth"])
+    assert np.array_equal(G.owner(), K.owner())
+    mv = torch.from_numpy(np.ascontiguousarray(w["mv"])).to(DEV)
+    ap = torch.full((len(w["mv"]),), -1, dtype=torch.int8, device=DEV)
+    G.run(mv, w["step_off"], ap)
+    got = ap.cpu().numpy()
+    for t in range(3):
+        lo, hi = int(w["step_off"][t]), int(w["step_off"][t + 1])
+        assert np.array_equal(got[lo:hi].astype(bool), K.apply_step(w["mv"][lo:hi])), t
+    _say("global4m: comparing positions, cells and the canonical DT*")
+    assert np.array_equal(G.positions(), K.xy)
+    assert np.array_equal(G.owner(), K.owner())
+    assert np.array_equal(G.query_canonical(), K.dt())
