@@ -44,7 +44,7 @@ def measured_traffic(kernel):
         return None
     d = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("kdt.hip", "kdt_device.hpp"):
+    for f in ("kdt.hip", "kdt_device.hpp", "kdt_pbuild.hpp", "kdt_mlp.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2308_06484_amd", "csrc", f), "rb").read())
     return d["traffic_bytes_per_launch"] if h.hexdigest()[:16] == d["source_sha256_16"] else None
 
@@ -128,22 +128,29 @@ def other_workload(args):
     if name == "global4m":
         global_report(args)
         return
-    if name == "multi2048":
+    if name in ("multi2048", "selector_mix"):
+        gen = W.multi2048 if name == "multi2048" else W.selector_mix
         cal_steps = 8
         ev_steps = args.other_steps or 10
-        log(f"multi2048: calibration workload (seed {100 + args.seed})")
-        calib = W.multi2048(seed=100 + args.seed, steps=cal_steps)
+        log(f"{name}: calibration workload (seed {100 + args.seed})")
+        calib = gen(seed=100 + args.seed, steps=cal_steps)
         X, Y = S.collect(calib, cal_steps, dev)
         del calib
         wts = S.train(X, Y, epochs=300, batch=2048, lr=0.02, device=dev)
         tau = S.calibrate_threshold(X, Y)
         log(f"trained on {len(X)} samples, tau = {tau:.3f}; evaluation workload (seed {args.seed})")
-        evalw = W.multi2048(seed=args.seed, steps=ev_steps)
+        evalw = gen(seed=args.seed, steps=ev_steps)
         res = S.evaluate(evalw, ev_steps, torch.from_numpy(wts).to(dev), tau, dev)
-        out = {"workload": "multi2048: 2048 blocks x 4096 uniform points on [0,16384)^2, "
-                           "k ~ clip(Poisson(lambda_b),1,64) moves per block per step, Pareto(1.2) "
-                           "distances capped at 4096", "steps": ev_steps, "train_samples": int(len(X)),
-               "tau": tau, "policies": res}
+        desc = {"multi2048": "multi2048: 2048 blocks x 4096 uniform points on [0,16384)^2, "
+                             "k ~ clip(Poisson(lambda_b),1,64) moves per block per step, Pareto(1.2) "
+                             "distances capped at 4096",
+                "selector_mix": "selector_mix: 256 blocks of 256 points on 1024^2 with n/2..n moves of "
+                                "side/8..side/2 units per step, 256 blocks of 4096 points on 16384^2 with "
+                                "1..8 moves of 1..8 units"}[name]
+        out = {"workload": desc, "steps": ev_steps, "train_samples": int(len(X)), "tau": tau, "policies": res}
+        for pol, r in res.items():
+            log(f"{name} {pol}: {r['seconds'] * 1e3:.2f} ms, rebuilt fraction {r['rebuild_fraction']:.3f}, "
+                f"chosen/best ticks {r['chosen_ticks'] / max(r['best_ticks'], 1):.3f}")
         print(json.dumps(out), flush=True)
         return
     if name == "lattice256":
@@ -236,7 +243,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms")
     ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "lattice256", "uneven4096", "multi2048", "global4m"],
+                    choices=["grid1024", "lattice256", "uneven4096", "multi2048", "selector_mix", "global4m"],
                     help="grid1024 is the measured configuration; the others print a secondary report")
     ap.add_argument("--other-steps", type=int, default=0, help="steps for --workload other than grid1024")
     args = ap.parse_args()

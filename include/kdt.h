@@ -208,6 +208,8 @@ int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
  *   MLP        rebuild iff the network's predicted log2 cost of rebuilding is
  *              below that of repairing; mlp_w: dev float [KDT_MLP_PARAMS],
  *              must stay valid while used
+ * A block with more than 256 moves in one step is repaired whatever the
+ * policy (the rebuild branch checks at most 256 moves per block and step).
  * The network: 16 features -> 32 ReLU -> 32 ReLU -> 2, parameters laid out
  * as W1[32][16], b1[32], W2[32][32], b2[32], W3[2][32], b3[2]. */
 #define KDT_POLICY_REPAIR 0

@@ -1,8 +1,9 @@
 // libkdt: kinetic Delaunay triangulation of moving lattice points on MI355X.
 //
 // Kernels (one 64-lane wavefront per block of the partition, Sec. IV):
-//   k_pbuild     every block's DT* from scratch, the threads of a workgroup
-//                inserting in parallel (kdt_pbuild.hpp); the starting state of Fig. 4
+//   k_build_blocks  every block's DT* from scratch (or the blocks flagged
+//                for the rebuild branch), the threads of a workgroup inserting
+//                in parallel (kdt_pbuild.hpp); the starting state of Fig. 4
 //   k_step       one time step: for each block, its moves in order, each a
 //                walk to the target, Delete, Insert (Fig. 4)
 //   k_run_fused  all steps of a move stream; blocks are independent, so each
@@ -42,7 +43,10 @@ struct DevState {
     BlockStats* stats;
     int* sticky;
     const int* order;  // per-block insertion order (Hilbert order at init)
-    int* owner;        // one int per triangle slot: claims of the parallel build
+    int* owner;        // one int per triangle slot: cavity claims of the parallel build
+    int* own2;         // one int per triangle slot: boundary claims of the parallel build
+    int* rb_flag;      // per block: rebuild after this step (set by the dry run)
+    int step_lds;      // dynamic LDS the step kernels run with: blocks whose build fits it are rebuilt there
     // repair-or-rebuild selection
     int policy;          // KDT_POLICY_*
     float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
@@ -71,16 +75,50 @@ __device__ void fail_block(const DevState& s, int b, int code) {
     }
 }
 
-// Every block's DT* from scratch, all threads of a workgroup inserting in
-// parallel (kdt_pbuild.hpp); `owner`: one int per triangle slot (scratch).
 constexpr int PB_THREADS = 128;
-__global__ void __launch_bounds__(PB_THREADS) k_pbuild(DevState s, int* owner) {
-    __shared__ int lds[4 + PB_DEFER];
-    __shared__ int att[PB_THREADS * ATT_INTS];
+constexpr int PB_LDS_BYTES = 128 * 1024;  // dynamic LDS asked for by the block build
+__host__ __device__ constexpr size_t pb_fixed_lds() {
+    return (sizeof(int) * (4 + PB_DEFER + (size_t)PB_THREADS * ATT_B_INTS) + 15) & ~(size_t)15;
+}
+// LDS a block of n points needs to be built in LDS: records, both claim
+// arrays and incident triangles (after the fixed part).
+__host__ __device__ constexpr size_t pb_block_lds(long long n) {
+    return (size_t)(2 * n - 2) * (sizeof(Tri) + 2 * sizeof(int)) + sizeof(int) * (size_t)n;
+}
+
+// Build every block's DT* (only_flagged = 0: the starting state) or those
+// the rebuild branch flagged in this step (only_flagged = 1), one workgroup
+// per block.  A block whose working state fits in `lds_bytes` of dynamic
+// LDS is built there and written back; a larger one is built in place.
+__global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int only_flagged, long long step,
+                                                             int lds_bytes) {
+    extern __shared__ __align__(16) char dyn[];
     const int b = blockIdx.x;
-    BlockView B = view_of(s, b);
-    const int rc = pbuild_block(B, s.order + s.pt_off[b], owner + s.tri_off[b], lds, att);
+    if (only_flagged && s.rb_flag[b] == 0) return;
+    const long long c0 = wall_clock64();
+    BlockView G = view_of(s, b);
+    int* lds = reinterpret_cast<int*>(dyn);
+    PBMem M;
+    M.att = lds + 4 + PB_DEFER;
+    if (pb_fixed_lds() + pb_block_lds(G.n) <= (size_t)lds_bytes) {
+        M.tri = reinterpret_cast<Tri*>(dyn + pb_fixed_lds());
+        M.cown = reinterpret_cast<int*>(M.tri + G.ntri);
+        M.bown = M.cown + G.ntri;
+        M.vtri = M.bown + G.ntri;
+    } else {
+        M.tri = G.tri;
+        M.vtri = G.vtri;
+        M.cown = s.owner + s.tri_off[b];
+        M.bown = s.own2 + s.tri_off[b];
+    }
+    const int rc = pbuild_block(G, s.order + s.pt_off[b], M, lds);
     if (rc != ST_OK) fail_block(s, b, rc);
+    if (only_flagged && threadIdx.x == 0) {
+        s.rb_flag[b] = 0;
+        // the branch's cost in the step log includes the build
+        if (s.log && s.log_cap > 0)
+            s.log[((step % s.log_cap) * (long long)s.n_blocks + b) * LOG_FIELDS + 17] += (float)(wall_clock64() - c0);
+    }
 }
 
 // One move of one block (Fig. 4): Delete p, Insert it at the target.
@@ -218,73 +256,178 @@ __device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const i
     return ST_OK;
 }
 
+// Position hash of the rebuild branch's dry run, in the wavefront's repair
+// scratch (unused on that branch): open addressing on 64-bit cell keys, with
+// 0 an empty entry and 1 a vacated cell.  Probes go 64 entries at a time.
+constexpr int PH_CAP = 2048;
+constexpr unsigned long long PH_EMPTY = 0ull, PH_GONE = 1ull;
+__device__ __forceinline__ unsigned long long ph_key(int2 p) {
+    return ((((unsigned long long)(unsigned)p.x) << 24) | (unsigned)p.y) + 2ull;
+}
+__device__ __forceinline__ int ph_home(unsigned long long k) {
+    return (int)((k * 0x9E3779B97F4A7C15ull) >> 53) & (PH_CAP - 1);
+}
+// Entry that holds key k, or -1.  Whole wavefront.
+__device__ int ph_find(const unsigned long long* T, unsigned long long k) {
+    const int h0 = ph_home(k);
+    for (int base = 0; base < PH_CAP; base += WAVE) {
+        const int h = (h0 + base + lane_id()) & (PH_CAP - 1);
+        const unsigned long long v = T[h];
+        const uint64_t hit = ballot(v == k);
+        if (hit) return __shfl(h, first_lane(hit));
+        if (ballot(v == PH_EMPTY)) return -1;  // entries never become empty again
+    }
+    return -1;
+}
+// Insert key k (not present).  Whole wavefront.
+__device__ void ph_insert(unsigned long long* T, unsigned long long k) {
+    const int h0 = ph_home(k);
+    for (int base = 0; base < PH_CAP; base += WAVE) {
+        const int h = (h0 + base + lane_id()) & (PH_CAP - 1);
+        const unsigned long long v = T[h];
+        const uint64_t fr = ballot(v == PH_EMPTY || v == PH_GONE);
+        if (fr) {
+            if (lane_id() == first_lane(fr)) T[h] = k;
+            wsync();
+            return;
+        }
+    }
+}
+// The n distinct positions, inserted by all lanes at once.
+__device__ void ph_build(unsigned long long* T, const int2* xy, int n) {
+    for (int h = lane_id(); h < PH_CAP; h += WAVE) T[h] = PH_EMPTY;
+    wsync();
+    for (int i = lane_id(); i < n; i += WAVE) {
+        const unsigned long long k = ph_key(xy[i]);
+        int h = ph_home(k);
+        for (int t = 0; t < PH_CAP; ++t) {
+            if (atomicCAS(&T[h], PH_EMPTY, k) == PH_EMPTY) break;
+            h = (h + 1) & (PH_CAP - 1);
+        }
+    }
+    wsync();
+}
+
 // Rebuild branch: the block's moves are first checked against the move rule
-// with the block's current triangulation (left untouched until the rebuild)
-// and the list of points already moved this step; applied moves only change
-// positions.  Then the block's DT* is rebuilt from scratch.
+// (a dry run over the positions: the moved points and their new places are
+// kept in LDS, occupancy comes from a position hash when the block is small
+// enough, else from a walk in the block's current triangulation, untouched
+// until the rebuild); then the new positions are written and the block's
+// DT* is rebuilt from scratch.
+// The build: here, by this one wavefront, with the block's working state in
+// the kernel's dynamic LDS `dynx` when it fits (s.step_lds bytes); else left
+// to k_build_blocks (defer: the block is flagged) or done here in place.
 __device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv, int m0,
-                                   int m1, int8_t* applied, BlockStats* st) {
+                                   int m1, int8_t* applied, BlockStats* st, bool defer, char* dynx) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
     const int lane = lane_id();
+    const bool hashed = B.n + (m1 - m0) <= PH_CAP / 2;
+    static_assert(sizeof(unsigned long long) * PH_CAP <= offsetof(WaveLDS, st), "position hash overlaps the counters");
+    unsigned long long* T = reinterpret_cast<unsigned long long*>(&S);
+    if (hashed) ph_build(T, B.xy, B.n);
     int nmoved = 0;  // wave-uniform; S.dry_v / S.dry_q: moved points and their new places
-    for (int m = m0; m < m1; ++m) {
-        const kdt_move_t r = mv[m];
-        const int p = r.point, dir = r.dir, dist = r.dist;
-        if (p < 0 || p >= B.n || dir < 0 || dir > 3 || dist < 1) return ST_ARG;
-        const int2 o = B.xy[p];
-        long long qx = o.x, qy = o.y;
-        if (dir == 0) qx += dist;
-        else if (dir == 1) qx -= dist;
-        else if (dir == 2) qy += dist;
-        else qy -= dist;
-        bool ok = qx >= fr.x && qx < fr.z && qy >= fr.y && qy < fr.w;
-        const int2 q = make_int2((int)qx, (int)qy);
-        int prev = -1;  // p's entry in the moved list
-        if (ok) {
-            bool held = false;
-            for (int i = lane; i < nmoved; i += WAVE) {
-                held |= same(S.dry_q[i], q);
+    for (int c0 = m0; c0 < m1; c0 += WAVE) {
+        // the chunk's moves and their points' places at the start of the step, one per lane
+        kdt_move_t r;
+        r.point = 0; r.dir = 0; r.dist = 1; r.pad = 0;
+        int2 o0 = make_int2(0, 0);
+        bool bad = false;
+        if (c0 + lane < m1) {
+            r = mv[c0 + lane];
+            bad = r.point < 0 || r.point >= B.n || r.dir < 0 || r.dir > 3 || r.dist < 1;
+            if (!bad) o0 = B.xy[r.point];
+        }
+        if (ballot(bad)) return ST_ARG;
+        const int cn = min(WAVE, m1 - c0);
+        for (int j = 0; j < cn; ++j) {
+            const int m = c0 + j;
+            const int p = __shfl(r.point, j), dir = __shfl(r.dir, j), dist = __shfl(r.dist, j);
+            int2 o = make_int2(__shfl(o0.x, j), __shfl(o0.y, j));
+            int prev = -1;  // p's entry in the moved list
+            for (int i = lane; i < nmoved; i += WAVE)
                 if (S.dry_v[i] == p) prev = i;
-            }
-            ok = !ballot(held);
             const uint64_t mp = ballot(prev >= 0);
             prev = mp ? __shfl(prev, first_lane(mp)) : -1;
-        }
-        if (ok) {
-            // a point of the old triangulation at q that has not moved away
-            int hit, hops = 0;
-            const int tq = walk<false>(B, &S, B.vtri[p], q, &hit, &hops);
-            if (tq < 0) return ST_INTERNAL;
-            if (hit >= 0 && same(B.xy[hit], q)) ok = false;
-        }
-        if (ok) {
-            const int slot = prev >= 0 ? prev : nmoved;
-            if (slot >= DRYMAX) return ST_CAPACITY;
-            if (lane == 0) {
-                B.xy[p] = q;
-                S.dry_v[slot] = p;
-                S.dry_q[slot] = q;
-                st->applied += 1;
+            if (prev >= 0) o = S.dry_q[prev];
+            long long qx = o.x, qy = o.y;
+            if (dir == 0) qx += dist;
+            else if (dir == 1) qx -= dist;
+            else if (dir == 2) qy += dist;
+            else qy -= dist;
+            bool ok = qx >= fr.x && qx < fr.z && qy >= fr.y && qy < fr.w;
+            const int2 q = make_int2((int)qx, (int)qy);
+            if (ok && hashed) {
+                ok = ph_find(T, ph_key(q)) < 0;
+            } else if (ok) {
+                bool held = false;
+                for (int i = lane; i < nmoved; i += WAVE) held |= same(S.dry_q[i], q);
+                ok = !ballot(held);
+                if (ok) {
+                    // a point of the old triangulation at q that has not moved away
+                    int hit, hops = 0;
+                    const int tq = walk<false>(B, &S, B.vtri[p], q, &hit, &hops);
+                    if (tq < 0) return ST_INTERNAL;
+                    if (hit >= 0) {
+                        bool gone = false;
+                        for (int i = lane; i < nmoved; i += WAVE) gone |= S.dry_v[i] == hit;
+                        ok = ballot(gone) != 0;
+                    }
+                }
             }
-            if (prev < 0) ++nmoved;
-            gsync();
-        } else if (lane == 0) {
-            st->blocked += 1;
+            if (ok) {
+                const int slot = prev >= 0 ? prev : nmoved;
+                if (slot >= DRYMAX) return ST_CAPACITY;
+                if (hashed) {
+                    const int e = ph_find(T, ph_key(o));
+                    if (e < 0) return ST_INTERNAL;
+                    if (lane == 0) T[e] = PH_GONE;
+                    wsync();
+                    ph_insert(T, ph_key(q));
+                }
+                if (lane == 0) {
+                    S.dry_v[slot] = p;
+                    S.dry_q[slot] = q;
+                    st->applied += 1;
+                }
+                if (prev < 0) ++nmoved;
+                wsync();
+            } else if (lane == 0) {
+                st->blocked += 1;
+            }
+            if (applied && lane == 0) applied[m] = ok ? 1 : 0;
         }
-        if (applied && lane == 0) applied[m] = ok ? 1 : 0;
     }
+    for (int i = lane; i < nmoved; i += WAVE) B.xy[S.dry_v[i]] = S.dry_q[i];
     gsync();
-    // the attempts overlay the wavefront's repair scratch, unused here
-    static_assert(offsetof(WaveLDS, st) >= sizeof(int) * WAVE * ATT_INTS, "attempts overlap the counters");
-    const int rc = pbuild_block(B, s.order + s.pt_off[b], s.owner + s.tri_off[b], S.pb_lds,
-                                reinterpret_cast<int*>(&S));
-    table_clear(S);
     if (lane == 0) {
         st->rebuilt += 1;
         st->alg_bytes += 64LL * B.ntri + 12LL * B.n;  // records written, positions read, vtri written
         st->tri_touched += B.ntri;
     }
+    const bool in_lds = pb_block_lds(B.n) <= (size_t)s.step_lds;
+    if (defer && !in_lds) {
+        if (lane == 0) s.rb_flag[b] = 1;
+        table_clear(S);
+        return ST_OK;
+    }
+    // the attempts overlay the wavefront's repair scratch, unused here
+    static_assert(offsetof(WaveLDS, st) >= sizeof(int) * WAVE * ATT_B_INTS, "attempts overlap the counters");
+    PBMem M;
+    M.att = reinterpret_cast<int*>(&S);
+    if (in_lds) {
+        M.tri = reinterpret_cast<Tri*>(dynx);
+        M.cown = reinterpret_cast<int*>(M.tri + B.ntri);
+        M.bown = M.cown + B.ntri;
+        M.vtri = M.bown + B.ntri;
+    } else {
+        M.tri = B.tri;
+        M.vtri = B.vtri;
+        M.cown = s.owner + s.tri_off[b];
+        M.bown = s.own2 + s.tri_off[b];
+    }
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], M, S.pb_lds);
+    table_clear(S);
     return rc;
 }
 
@@ -319,7 +462,7 @@ __device__ int choose_branch(const DevState& s, const float* f) {
 }
 
 __device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
-                                int m0, int m1, int8_t* applied, long long step) {
+                                int m0, int m1, int8_t* applied, long long step, bool defer, char* dynx) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
     const int lane = lane_id();
@@ -358,6 +501,7 @@ __device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_
         f[10] = 100.f * (float)k / (float)B.n; f[11] = sq / (float)k; f[12] = f[4] * lk;
         f[13] = log2f(sp); f[14] = lk / ln; f[15] = 1.f;
         branch = choose_branch(s, f);
+        if (k > DRYMAX) branch = 0;  // more moves than the dry run holds: repair
     }
     const long long c0 = wall_clock64();
     int rc = ST_OK;
@@ -370,7 +514,7 @@ __device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_
             if (rc != ST_OK) break;
         }
     } else {
-        rc = dry_run_and_rebuild(s, S, b, mv, m0, m1, applied, &S.st);
+        rc = dry_run_and_rebuild(s, S, b, mv, m0, m1, applied, &S.st, defer, dynx);
     }
     const long long c1 = wall_clock64();
     wsync();
@@ -399,22 +543,24 @@ __device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
                                                const int* __restrict__ off, int8_t* applied, long long step) {
     __shared__ WaveLDS S;
+    extern __shared__ __align__(16) char dynx[];
     const int b = blockIdx.x;
     if (s.status[b] != 0) return;
     scratch_init(S);
-    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step);
+    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step, true, dynx);
 }
 
 __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* __restrict__ mv,
                                                     const int* __restrict__ off, int n_steps, int n_blocks,
                                                     int8_t* applied, long long step0) {
     __shared__ WaveLDS S;
+    extern __shared__ __align__(16) char dynx[];
     const int b = blockIdx.x;
     scratch_init(S);
     for (int t = 0; t < n_steps; ++t) {
         if (s.status[b] != 0) return;
         const int* o = off + (long long)t * (n_blocks + 1);
-        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied, step0 + t);
+        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied, step0 + t, false, dynx);
         gsync();
     }
 }
@@ -430,6 +576,7 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
                                                        int n_blocks, int8_t* applied, long long step) {
     __shared__ WaveLDS S;
     __shared__ int next;
+    extern __shared__ __align__(16) char dynx[];
     scratch_init(S);
     while (true) {
         if (lane_id() == 0) next = atomicAdd(&queue[0], 1);
@@ -439,7 +586,7 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
         if (qi >= n_blocks) break;
         const int b = order[qi];
         if (s.status[b] != 0) continue;
-        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step);
+        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step, true, dynx);
         gsync();
     }
     if (lane_id() == 0) {
@@ -1065,7 +1212,7 @@ __global__ void __launch_bounds__(WAVE) k_digest(DevState s, unsigned long long*
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, qcount, qoff,
+    size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
         qtris, stage_mv, stage_off, sticky, lpt, queue, total;
 };
 
@@ -1084,6 +1231,8 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.status = take(sizeof(int) * B);
     L.stats = take(sizeof(BlockStats) * B);
     L.qmap = take(sizeof(int) * ntri);
+    L.own2 = take(sizeof(int) * ntri);
+    L.rb_flag = take(sizeof(int) * B);
     L.qcount = take(sizeof(int) * B);
     L.qoff = take(sizeof(long long) * (B + 1));
     L.qtris = take(sizeof(int) * 3 * ntri);
@@ -1185,6 +1334,9 @@ struct kdt_ctx {
     long long step_count = 0;  // time steps launched so far (log index)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
+    int pb_lds = 0;         // dynamic LDS of k_build_blocks at init
+    int pb_lds_follow = 0;  // ... after a step, for the blocks too large for the step kernels
+    bool follow = false;    // some block is too large to be rebuilt inside the step kernels
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;  // recorded pairs
     size_t ev_used = 0;
     // global mode: one triangulation over all points (block 0)
@@ -1230,6 +1382,61 @@ void release_events(kdt_ctx* c) {
     }
     c->ev.clear();
     c->ev_used = 0;
+}
+
+// Dynamic LDS for the block build: PB_LDS_BYTES if the device lets a
+// kernel have that much, else the default limit.
+int pb_lds_bytes() {
+    static int bytes = -1;
+    if (bytes < 0) {
+        bytes = hipFuncSetAttribute((const void*)k_build_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    PB_LDS_BYTES) == hipSuccess
+                    ? PB_LDS_BYTES
+                    : 64 * 1024;
+        (void)hipGetLastError();
+    }
+    return bytes;
+}
+
+// Dynamic LDS the step kernels may have on top of their static LDS under a
+// rebuilding policy (two workgroups per compute unit still fit), or 0 if the
+// device refuses it.
+constexpr int STEP_LDS_EXTRA_MAX = 44 * 1024;
+int step_lds_limit() {
+    static int bytes = -1;
+    if (bytes < 0) {
+        bool ok = true;
+        for (const void* k : {(const void*)k_step, (const void*)k_step_persist, (const void*)k_run_fused})
+            ok = ok && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, STEP_LDS_EXTRA_MAX) ==
+                           hipSuccess;
+        (void)hipGetLastError();
+        bytes = ok ? STEP_LDS_EXTRA_MAX : 0;
+    }
+    return bytes;
+}
+
+// Largest LDS need of a block build above `above` and within `limit` (0 if none).
+size_t max_block_need(const kdt_ctx* c, size_t above, size_t limit) {
+    size_t best = 0;
+    for (int32_t b = 0; b < c->B; ++b) {
+        const size_t need = pb_block_lds(c->pt_off[b + 1] - c->pt_off[b]);
+        if (need > above && need <= limit) best = std::max(best, need);
+    }
+    return best;
+}
+
+// Launch sizes for the rebuild branch under the current policy: the step
+// kernels get room to build the largest block that fits their extra LDS;
+// larger blocks are built by k_build_blocks after the step.
+void plan_rebuild_lds(kdt_ctx* c) {
+    c->dev.step_lds = 0;
+    c->follow = false;
+    if (c->dev.policy == KDT_POLICY_REPAIR) return;
+    c->dev.step_lds = (int)((max_block_need(c, 0, (size_t)step_lds_limit()) + 255) & ~(size_t)255);
+    for (int32_t b = 0; b < c->B && !c->follow; ++b)
+        c->follow = pb_block_lds(c->pt_off[b + 1] - c->pt_off[b]) > (size_t)c->dev.step_lds;
+    c->pb_lds_follow =
+        (int)(pb_fixed_lds() + max_block_need(c, (size_t)c->dev.step_lds, pb_lds_bytes() - pb_fixed_lds()));
 }
 
 int64_t orient_h(const int32_t* a, const int32_t* b, const int32_t* c) {
@@ -1401,6 +1608,8 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->dev.sticky = (int*)(w + L.sticky);
     c->dev.order = (const int*)(w + L.order);
     c->dev.owner = (int*)(w + L.qmap);
+    c->dev.own2 = (int*)(w + L.own2);
+    c->dev.rb_flag = (int*)(w + L.rb_flag);
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.tau = 0.f;
     c->dev.mlp_w = nullptr;
@@ -1416,6 +1625,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     rc |= check_hip(c, hipMemcpyAsync(w + L.tri_off, c->tri_off.data(), sizeof(long long) * (n_blocks + 1), hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemcpyAsync(w + L.frame, fr.data(), sizeof(int4) * n_blocks, hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int) * n_blocks, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.rb_flag, 0, sizeof(int) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.queue, 0, sizeof(int) * 4, s));
@@ -1433,7 +1643,9 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
         c->cus = cus;
     }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
-    k_pbuild<<<n_blocks, PB_THREADS, 0, s>>>(c->dev, c->dev.owner);
+    c->pb_lds = (int)(pb_fixed_lds() + max_block_need(c, 0, pb_lds_bytes() - pb_fixed_lds()));
+    c->dev.step_lds = 0;
+    k_build_blocks<<<n_blocks, PB_THREADS, c->pb_lds, s>>>(c->dev, 0, 0, c->pb_lds);
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
     rc = check_hip(c, hipStreamSynchronize(s));
     if (rc != KDT_OK) { delete c; return rc; }
@@ -1492,8 +1704,12 @@ int kdt_step(kdt_ctx* c) {
                                       hipMemcpyHostToDevice, c->stream));
     if (rc != KDT_OK) return KDT_E_DEVICE;
     hipEvent_t e0 = timing_begin(c);
-    k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
-                                         (const int*)(w + c->L.stage_off), nullptr, c->step_count++);
+    k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
+                                                       (const int*)(w + c->L.stage_off), nullptr, c->step_count);
+    if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
+        k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
+                                                                          c->pb_lds_follow);
+    c->step_count++;
     timing_end(c, e0);
     return check_hip(c, hipGetLastError());
 }
@@ -1508,8 +1724,8 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
     char* w = c->ws;
     if (flags == KDT_RUN_FUSED) {
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
-        k_run_fused<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied,
-                                                  c->step_count);
+        k_run_fused<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, step_off, n_steps, c->B, applied,
+                                                                c->step_count);
         c->step_count += n_steps;
         if (timed) timing_end(c, e0);
         return check_hip(c, hipGetLastError());
@@ -1519,10 +1735,13 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
         const int32_t* off = step_off + (int64_t)t * (c->B + 1);
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
         if (flags == KDT_RUN_PERSISTENT)
-            k_step_persist<<<grid, WAVE, 0, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
+            k_step_persist<<<grid, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
                                                          (int*)(w + c->L.queue), c->B, applied, c->step_count);
         else
-            k_step<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, applied, c->step_count);
+            k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count);
+        if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
+            k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
+                                                                              c->pb_lds_follow);
         c->step_count++;
         if (timed) timing_end(c, e0);
     }
@@ -1607,6 +1826,7 @@ int kdt_set_policy(kdt_ctx* c, int32_t policy, float tau, const float* mlp_w) {
     c->dev.policy = policy;
     c->dev.tau = tau;
     c->dev.mlp_w = mlp_w;
+    if (!c->global) plan_rebuild_lds(c);
     return KDT_OK;
 }
 
@@ -1883,6 +2103,8 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->dev.sticky = (int*)(w + L.sticky);
     c->dev.order = (const int*)(w + L.order);
     c->dev.owner = (int*)(w + L.qmap);
+    c->dev.own2 = (int*)(w + L.own2);
+    c->dev.rb_flag = (int*)(w + L.rb_flag);
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.n_blocks = 1;
     c->g.claim = (unsigned long long*)(w + G.claim);

@@ -6,31 +6,38 @@
 //            breadth-first search over a consistent snapshot (nobody
 //            writes), and claims each cavity triangle and each triangle
 //            behind the cavity boundary (whose back-pointer it will patch);
-//   commit   a thread that holds every one of its claims takes two fresh
-//            slots and writes its fan; the others write nothing;
+//   commit   a thread that no contender of smaller priority conflicts with
+//            takes two fresh slots and writes its fan; the others write
+//            nothing;
 //   release  claims are cleared (or outdated by the next round's stamps).
-// Winners' cavities and patched neighbours are disjoint, so every commit
-// sees exactly the triangles it planned on: a triangle the new point's fan
-// creates has its circumcircle inside the union of the circumcircles of the
-// cavity triangle and the surviving triangle on its edge, so it conflicts
-// with no other winner's point.  The contender with the smallest priority
-// always wins, so each round makes progress.  Points are taken level by
+// Two attempts conflict when a cavity triangle of one is a cavity triangle
+// or a boundary neighbour of the other.  Two attempts that only share a
+// boundary neighbour patch different edges of it (their cavities, on the
+// other side of those edges, are disjoint) and do not conflict.  Winners
+// therefore touch disjoint records, and every commit sees exactly the
+// triangles it planned on: a triangle the new point's fan creates has its
+// circumcircle inside the union of the circumcircles of the cavity triangle
+// and the surviving triangle on its edge, so it conflicts with no other
+// winner's point.  The contender with the smallest priority always wins,
+// so each round makes progress.  Points are taken level by
 // level along a Hilbert order (stride 2^L, 2^(L-1), ..., 1): a point's walk
 // starts at a triangle of its neighbour one stride back, already inserted at
 // a coarser level.  DT* is unique, so the order of insertions never changes
 // the result.
 //
-// Two users: the block builder below (one workgroup per block, claims and
-// attempts in its memory) and the grid-wide builder of the global mode
-// (claims stamped with a round number, attempts in global memory).
+// Two users: the block builder below (one workgroup per block, its records
+// and claims in LDS when they fit) and the grid-wide builder of the global
+// mode (claims stamped with a round number, attempts in global memory).
 #pragma once
 
 #include "kdt_device.hpp"
 
 namespace kdt {
 
-constexpr int TCM = 24;                // cavity triangles one thread's attempt can hold
+constexpr int TCM = 24;                // cavity triangles one thread's attempt can hold (grid-wide build)
 constexpr int ATT_INTS = 4 * TCM + 6;  // ints one such attempt spans
+constexpr int TCM_B = 12;                  // the same in the block builder (larger cavities wait)
+constexpr int ATT_B_INTS = 4 * TCM_B + 6;
 constexpr int FREE_OWNER = 0x7fffffff;
 constexpr int PB_ROUNDS = 64;  // rounds of one chunk before its points are deferred
 constexpr int PB_DEFER = 256;  // deferred points a block can hold
@@ -80,6 +87,7 @@ __device__ int tplan(const BlockView& B, int v, int2 q, int hint, const AttView&
         Tri nr[3];
         int ns[3];
         bool in[3];
+#pragma unroll
         for (int e = 0; e < 3; ++e) {
             ns[e] = vget(r.n, e) >> 2;
             if (bad_slot(B, ns[e])) return ST_INTERNAL;
@@ -87,6 +95,7 @@ __device__ int tplan(const BlockView& B, int v, int2 q, int hint, const AttView&
             for (int m = 0; m < nc; ++m) in[e] |= A.cav(m) == ns[e];
             if (!in[e]) nr[e] = B.tri[ns[e]];  // the three loads go out together
         }
+#pragma unroll
         for (int e = 0; e < 3; ++e) {
             if (in[e]) continue;
             bool dup = false;  // accepted earlier in this loop
@@ -186,20 +195,37 @@ __device__ __forceinline__ int pb_prio(int i) {
     return (int)((((unsigned)i * 2654435761u) >> 24) << 22) | i;
 }
 
-// Build block B's DT* from scratch with all threads of the workgroup.
-// ord: the block's points in Hilbert order; owner: one int per triangle
-// slot of the block (scratch); lds: four ints of shared memory plus
-// PB_DEFER for deferred points; att: blockDim.x * ATT_INTS ints of shared
-// memory for the attempts.  Every thread must call it.
-__device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int* lds, int* att) {
+// Where a block build keeps its working state: the records and incident
+// triangles it writes (the block's own, or LDS copies written back at the
+// end), the two claim arrays (one int per slot each) and the attempts
+// (blockDim.x * ATT_B_INTS ints of LDS).
+struct PBMem {
+    Tri* tri;
+    int* vtri;
+    int* cown;  // smallest priority holding the triangle in its cavity
+    int* bown;  // smallest priority holding it behind its cavity boundary
+    int* att;
+};
+
+// Build block G's DT* from scratch with all threads of the workgroup.
+// ord: the block's points in Hilbert order; lds: four ints of shared memory
+// plus PB_DEFER for deferred points.  Every thread must call it.
+__device__ int pbuild_block(const BlockView& G, const int* ord, const PBMem& M, int* lds) {
     const int tid = threadIdx.x, NT = blockDim.x;
+    BlockView B = G;
+    B.tri = M.tri;
+    B.vtri = M.vtri;
+    int* att = M.att;
     const int n = B.n;
     int& kmin = lds[0];    // index of the first point off the first line
     int& used = lds[1];    // triangle slots in use
     int& status = lds[2];  // first error
     int& ndef = lds[3];    // deferred points
     int* deferred = lds + 4;
-    for (int i = tid; i < B.ntri; i += NT) own_set(&owner[i], FREE_OWNER);
+    for (int i = tid; i < B.ntri; i += NT) {
+        own_set(&M.cown[i], FREE_OWNER);
+        own_set(&M.bown[i], FREE_OWNER);
+    }
     if (tid == 0) {
         kmin = 0x7fffffff;
         used = 4;
@@ -221,7 +247,7 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
     // index 0 and the first triangle's points are already in
     int top = 1;
     while (top * 2 < n) top *= 2;
-    const AttView A{att + tid, NT, TCM};
+    const AttView A{att + tid, NT, TCM_B};
     for (int s = top; s >= 1; s >>= 1) {
         const int count = s < n ? (n - 1 - s) / (2 * s) + 1 : 0;
         const int nch = (count + NT - 1) / NT;
@@ -244,8 +270,8 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
                     const int rc = tplan(B, v, q, hint, A, &nc, &nb);
                     if (rc == 0) {
                         planned = true;
-                        for (int m = 0; m < nc; ++m) own_min(&owner[A.cav(m)], prio);
-                        for (int e = 0; e < nb; ++e) own_min(&owner[A.bout(e) >> 2], prio);
+                        for (int m = 0; m < nc; ++m) own_min(&M.cown[A.cav(m)], prio);
+                        for (int e = 0; e < nb; ++e) own_min(&M.bown[A.bout(e) >> 2], prio);
                     } else if (rc == 1) {  // cavity too large for one thread: later, alone
                         const int d = atomicAdd(&ndef, 1);
                         if (d < PB_DEFER) deferred[d] = i;
@@ -259,8 +285,11 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
                 __syncthreads();
                 if (planned) {
                     bool won = true;
-                    for (int m = 0; m < nc; ++m) won &= own_get(&owner[A.cav(m)]) == prio;
-                    for (int e = 0; e < nb; ++e) won &= own_get(&owner[A.bout(e) >> 2]) == prio;
+                    for (int m = 0; m < nc; ++m) {
+                        const int t = A.cav(m);
+                        won &= own_get(&M.cown[t]) == prio && own_get(&M.bown[t]) > prio;
+                    }
+                    for (int e = 0; e < nb; ++e) won &= own_get(&M.cown[A.bout(e) >> 2]) > prio;
                     if (won) {
                         const int f = atomicAdd(&used, 2);
                         const int rc = f + 1 < B.ntri ? tcommit(B, A, nc, nb, v, q, f, f + 1) : ST_INTERNAL;
@@ -271,8 +300,8 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
                 __threadfence_block();
                 __syncthreads();
                 if (planned) {
-                    for (int m = 0; m < nc; ++m) own_set(&owner[A.cav(m)], FREE_OWNER);
-                    for (int e = 0; e < nb; ++e) own_set(&owner[A.bout(e) >> 2], FREE_OWNER);
+                    for (int m = 0; m < nc; ++m) own_set(&M.cown[A.cav(m)], FREE_OWNER);
+                    for (int e = 0; e < nb; ++e) own_set(&M.bown[A.bout(e) >> 2], FREE_OWNER);
                 }
                 __threadfence_block();
                 if (!__syncthreads_or(pending)) break;
@@ -288,7 +317,7 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
     // deferred points, one at a time by thread 0 (no contention), whose
     // attempt spans all the threads' attempt memory
     if (tid == 0) {
-        const AttView big{att, 1, (NT * ATT_INTS - 6) / 4};
+        const AttView big{att, 1, (NT * ATT_B_INTS - 6) / 4};
         const int nd = ndef < PB_DEFER ? ndef : PB_DEFER;
         for (int d = 0; d < nd && status == ST_OK; ++d) {
             const int i = deferred[d];
@@ -304,7 +333,14 @@ __device__ int pbuild_block(const BlockView& B, const int* ord, int* owner, int*
         if (status == ST_OK && used != B.ntri) status = ST_INTERNAL;
     }
     __syncthreads();
-    return status;
+    const int rc = status;
+    if (rc == ST_OK && M.tri != G.tri) {  // built in LDS: write the block back
+        for (int i = tid; i < B.ntri; i += NT) G.tri[i] = M.tri[i];
+        for (int i = tid; i < n; i += NT) G.vtri[i] = M.vtri[i];
+        __threadfence_block();
+        __syncthreads();
+    }
+    return rc;
 }
 
 }  // namespace kdt

@@ -168,6 +168,50 @@ def multi2048(seed=1, steps=100, blocks=2048, per_block=4096, side=16384,
                 mv_off=offs.astype(np.int32))
 
 
+def selector_mix(seed=1, steps=12, small=256, large=256, n_small=256, n_large=4096,
+                 side_small=1024, side_large=16384):
+    """Blocks where either branch of the repair-or-rebuild choice can be the
+    cheaper one: `small` blocks of n_small points most of which move far
+    every step (k ~ U{n/2..n} distinct movers, distances U{side/8..side/2})
+    and `large` blocks of n_large points with a few short moves (k ~
+    U{1..8}, distances U{1..8}); the two kinds are interleaved at random.
+    Every block has its own frame, side by side along x."""
+    rng = np.random.default_rng(seed)
+    kinds = np.zeros(small + large, dtype=np.int64)
+    kinds[rng.permutation(small + large)[:large]] = 1
+    B = len(kinds)
+    sizes = np.where(kinds == 1, n_large, n_small).astype(np.int64)
+    sides = np.where(kinds == 1, side_large, side_small).astype(np.int64)
+    x0 = np.concatenate([[0], np.cumsum(sides)[:-1]])
+    if x0[-1] + sides[-1] > (1 << 24):
+        raise ValueError("frames do not fit the lattice")
+    pt_off = np.zeros(B + 1, dtype=np.int64)
+    pt_off[1:] = np.cumsum(sizes)
+    xy = np.concatenate([_distinct_uniform(rng, int(sizes[b]), int(x0[b]), 0, int(sides[b]), int(sides[b]))
+                         for b in range(B)])
+    frame = np.stack([x0, np.zeros(B, np.int64), x0 + sides, sides], axis=1).astype(np.int32)
+    recs, offs, base = [], np.zeros((steps, B + 1), dtype=np.int64), 0
+    for t in range(steps):
+        offs[t, 0] = base
+        for b in range(B):
+            n, sd = int(sizes[b]), int(sides[b])
+            if kinds[b] == 0:
+                k = int(rng.integers(n // 2, n + 1))
+                dist = rng.integers(sd // 8, sd // 2 + 1, size=k)
+            else:
+                k = int(rng.integers(1, 9))
+                dist = rng.integers(1, 9, size=k)
+            r = np.zeros((k, 4), dtype=np.int32)
+            r[:, 0] = rng.choice(n, size=k, replace=False)
+            r[:, 1] = rng.integers(0, 4, size=k)
+            r[:, 2] = dist
+            recs.append(r)
+            base += k
+            offs[t, b + 1] = base
+    return dict(name="selector_mix", xy=xy, pt_off=pt_off, frame=frame, mv=np.concatenate(recs),
+                mv_off=offs.astype(np.int32), kind=kinds)
+
+
 def subset_blocks(w, blocks, steps=None):
     """Restrict a per-block workload to the listed blocks (and first steps).
     Global ids are renumbered to rows of the new xy, block by block."""

@@ -111,3 +111,89 @@ def test_selector_train_and_evaluate_end_to_end():
     for pol in ("repair", "rebuild", "threshold", "mlp"):
         assert res[pol]["applied"] == res["repair"]["applied"]
         assert res[pol]["regret_ticks"] >= 0
+
+
+def _three_sizes(seed=11, steps=4):
+    """Blocks of 256, 600 and 4096 points (the three build paths: inside the
+    step kernel in LDS, after the step in LDS, after the step in place),
+    each with about half its points moving far every step."""
+    rng = np.random.default_rng(seed)
+    sizes, sides = [256, 600, 4096, 256], [1024, 2048, 8192, 1024]
+    xy, frames, x0 = [], [], 0
+    for n, sd in zip(sizes, sides):
+        cells = rng.choice(sd * sd, size=n, replace=False)
+        xy.append(np.stack([x0 + cells % sd, cells // sd], 1))
+        frames.append([x0, 0, x0 + sd, sd])
+        x0 += sd
+    pt_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    recs, offs, base = [], np.zeros((steps, len(sizes) + 1), np.int64), 0
+    for t in range(steps):
+        offs[t, 0] = base
+        for b, (n, sd) in enumerate(zip(sizes, sides)):
+            k = min(n // 2, 200)  # the rebuild branch takes at most 256 moves per block and step
+            r = np.zeros((k, 4), np.int32)
+            r[:, 0] = rng.choice(n, size=k, replace=False)
+            r[:, 1] = rng.integers(0, 4, size=k)
+            r[:, 2] = rng.integers(sd // 8, sd // 2 + 1, size=k)
+            recs.append(r)
+            base += k
+            offs[t, b + 1] = base
+    return dict(xy=np.concatenate(xy).astype(np.int32), pt_off=pt_off,
+                frame=np.array(frames, np.int32), mv=np.concatenate(recs), mv_off=offs.astype(np.int32))
+
+
+def test_rebuild_paths_bit_exact():
+    w = _three_sizes()
+    st, log = _policy_run(w, "rebuild")
+    assert st["errors"] == 0 and st["rebuilt"] == 4 * 4
+    # the step log's cost includes the builds done after the step
+    assert (log[..., 17] > 0).all()
+
+
+def test_rebuild_policy_repairs_blocks_with_too_many_moves():
+    w = _three_sizes(seed=13, steps=2)
+    # a third step with 300 moves in the 600-point block: repaired
+    rng = np.random.default_rng(5)
+    extra = np.zeros((300, 4), np.int32)
+    extra[:, 0] = rng.choice(600, size=300, replace=False)
+    extra[:, 1] = rng.integers(0, 4, size=300)
+    extra[:, 2] = rng.integers(1, 64, size=300)
+    base = int(w["mv_off"][-1, -1])
+    row = np.array([base, base, base + 300, base + 300, base + 300], np.int32)
+    w = dict(w, mv=np.concatenate([w["mv"], extra]), mv_off=np.concatenate([w["mv_off"], row[None]]))
+    st, log = _policy_run(w, "rebuild")
+    assert st["errors"] == 0
+    assert log[2, 1, 16] == 0 and log[2, 1, 18] == 300
+
+
+def test_rebuild_fused_launch_bit_exact():
+    from paper_2308_06484_amd.kdt import KineticDT
+    w = _three_sizes(seed=12, steps=3)
+    dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+    dt.set_policy("rebuild")
+    mv = torch.from_numpy(w["mv"]).to(DEV)
+    off = torch.from_numpy(np.ascontiguousarray(w["mv_off"])).to(DEV)
+    dt.run(mv, off, mode="fused")
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    for t in range(3):
+        ref.apply_step(w["mv"], w["mv_off"][t])
+    assert np.array_equal(dt.positions(), ref.xy)
+    assert np.array_equal(dt.query_canonical(), ref.all_dt(8))
+
+
+def test_learned_selector_gains_on_mixed_blocks():
+    """Where each branch wins on some blocks, the trained network's choices
+    cost less device time than always repairing or always rebuilding, and
+    its policy runs faster than both."""
+    from paper_2308_06484_amd import selector as S
+    calib = W.selector_mix(seed=111, steps=4, small=48, large=48)
+    X, Y = S.collect(calib, 4)
+    wts = S.train(X, Y, epochs=200, batch=256, lr=0.02)
+    tau = S.calibrate_threshold(X, Y)
+    evalw = W.selector_mix(seed=11, steps=4, small=48, large=48)
+    res = S.evaluate(evalw, 4, torch.from_numpy(wts).to(DEV), tau)
+    m, rp, rb = res["mlp"], res["repair"], res["rebuild"]
+    print({k: (round(v["seconds"] * 1e3, 2), round(v["chosen_ticks"] / v["best_ticks"], 3)) for k, v in res.items()})
+    assert 0.2 < m["rebuild_fraction"] < 0.8
+    assert m["chosen_ticks"] < 0.9 * rp["chosen_ticks"] and m["chosen_ticks"] < 0.5 * rb["chosen_ticks"]
+    assert m["seconds"] < rp["seconds"] and m["seconds"] < rb["seconds"]
