@@ -67,7 +67,7 @@ __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
     return B;
 }
 
-__device__ void fail_block(const DevState& s, int b, int code) {
+__device__ __forceinline__ void fail_block(const DevState& s, int b, int code) {
     if (threadIdx.x == 0) {
         s.status[b] = code;
         atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b].errors), 1ull);
@@ -139,7 +139,7 @@ struct MovePlan {
     int k, used, npath;
 };
 
-__device__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
+__device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
                           BlockStats* st, int* applied, int mode = MV_APPLY, MovePlan* plan = nullptr) {
     const int lane = lane_id();
     *applied = 0;
@@ -317,7 +317,7 @@ __device__ void ph_build(unsigned long long* T, const int2* xy, int n) {
 // The build: here, by this one wavefront, with the block's working state in
 // the kernel's dynamic LDS `dynx` when it fits (s.step_lds bytes); else left
 // to k_build_blocks (defer: the block is flagged) or done here in place.
-__device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv, int m0,
+__device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv, int m0,
                                    int m1, int8_t* applied, BlockStats* st, bool defer, char* dynx) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
@@ -432,7 +432,7 @@ __device__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const k
 }
 
 // The branch the policy takes for this block and step: 0 repair, 1 rebuild.
-__device__ int choose_branch(const DevState& s, const float* f) {
+__device__ __forceinline__ int choose_branch(const DevState& s, const float* f) {
     if (s.policy == KDT_POLICY_REBUILD) return 1;
     if (s.policy == KDT_POLICY_THRESHOLD) return f[3] > s.tau ? 1 : 0;
     if (s.policy != KDT_POLICY_MLP || !s.mlp_w) return 0;
@@ -461,7 +461,7 @@ __device__ int choose_branch(const DevState& s, const float* f) {
     return o1 < o0 ? 1 : 0;
 }
 
-__device__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
+__device__ __forceinline__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
                                 int m0, int m1, int8_t* applied, long long step, bool defer, char* dynx) {
     BlockView B = view_of(s, b);
     const int4 fr = s.frame[b];
@@ -655,7 +655,7 @@ struct GBuild {
     int* big;        // the attempt of a deferred point
 };
 
-__device__ void fail_global(const DevState& s, int code) {
+__device__ __forceinline__ void fail_global(const DevState& s, int code) {
     s.status[0] = code;
     atomicMin(s.sticky, code);
 }
@@ -678,7 +678,7 @@ __device__ __forceinline__ int cell_slot(unsigned long long k, int mask) {
     return (int)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask;
 }
 // The table holds at least 8 entries per move, so a free entry is found.
-__device__ void cell_add(const GlobalDev& g, unsigned long long k) {
+__device__ __forceinline__ void cell_add(const GlobalDev& g, unsigned long long k) {
     int h = cell_slot(k, g.hmask);
     for (int i = 0; i <= g.hmask; ++i) {
         const unsigned long long prev = atomicCAS(&g.hkey[h], 0ull, k);
@@ -689,7 +689,7 @@ __device__ void cell_add(const GlobalDev& g, unsigned long long k) {
         h = (h + 1) & g.hmask;
     }
 }
-__device__ int cell_count(const GlobalDev& g, unsigned long long k) {
+__device__ __forceinline__ int cell_count(const GlobalDev& g, unsigned long long k) {
     int h = cell_slot(k, g.hmask);
     for (int i = 0; i <= g.hmask; ++i) {
         const unsigned long long cur = g.hkey[h];
@@ -713,7 +713,7 @@ __device__ __forceinline__ bool move_target(int2 o, int dir, int dist, int4 fr, 
 
 // kd cell of a position: from the root, right iff its key -- (x, y) at even
 // levels, (y, x) at odd ones -- is not below the node's split key.
-__device__ int kd_cell_of(const int2* split, int depth, int2 p) {
+__device__ __forceinline__ int kd_cell_of(const int2* split, int depth, int2 p) {
     int k = 1;
     for (int l = 0; l < depth; ++l) {
         const int2 sk = split[k];
@@ -724,7 +724,7 @@ __device__ int kd_cell_of(const int2* split, int depth, int2 p) {
 }
 
 // After an applied move of p (by this lane): the point's kd cell.
-__device__ void update_owner(const DevState& s, const GlobalDev& g, int p) {
+__device__ __forceinline__ void update_owner(const DevState& s, const GlobalDev& g, int p) {
     const int cell = kd_cell_of(g.split, g.depth, s.xy[p]);
     if (cell != g.powner[p]) {
         g.powner[p] = cell;
@@ -747,7 +747,7 @@ __device__ __forceinline__ void stats_flush(const DevState& s, WaveLDS& S) {
 }
 
 // The last workgroup of a kernel to get here advances the round stamp.
-__device__ void round_done(const GlobalDev& g) {
+__device__ __forceinline__ void round_done(const GlobalDev& g) {
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&g.ctr[GC_DONE], 1) == (int)gridDim.x - 1) {
