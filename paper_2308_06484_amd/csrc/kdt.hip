@@ -136,7 +136,10 @@ __global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int onl
 constexpr int MV_APPLY = 0;
 constexpr int MV_PLAN = 1;
 struct MovePlan {
-    int k, used, npath;
+    int k, used, npath;  // star slots, table entries, walk slots read
+    int nvt_del, nvt;    // incident-triangle updates: the deletion's, then the insertion's
+    int2 q;              // the new position
+    int fast;            // 1: star-only path
 };
 
 __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
@@ -190,7 +193,7 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
         rc = fill_star(B, S, k, p, q, true, &used, &nvt, st);
         if (rc != ST_OK) return rc;
         if (mode == MV_PLAN) {
-            *plan = MovePlan{k, used, npath};
+            *plan = MovePlan{k, used, npath, nvt, nvt, q, 1};
             *applied = 2;
             return ST_OK;
         }
@@ -232,7 +235,7 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], &used, &nvt, st);
     if (rc != ST_OK) return rc;
     if (mode == MV_PLAN) {
-        *plan = MovePlan{k, used, npath};
+        *plan = MovePlan{k, used, npath, nvt_del, nvt, q, 0};
         *applied = 2;
         return ST_OK;
     }
@@ -620,6 +623,8 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
 
 constexpr int G_ROUNDS = 3;           // reservation rounds per step
 constexpr int RSMAX = 384;            // slots a planned move may read
+constexpr int PRECMAX = 96;           // records a planned move may write
+constexpr int PVTMAX = 128;           // incident-triangle updates of a planned move
 constexpr int G_SERIAL_LDS = 2048;    // ordered-pass entries sorted in LDS
 constexpr int MS_PEND = 0, MS_DONE = 1, MS_SERIAL = 2;
 constexpr int GB_CHUNK = 1 << 17;     // points the grid-wide builder plans at once
@@ -635,6 +640,11 @@ struct GlobalDev {
     int* mstate;                // per move of the step: MS_*
     int* rs;                    // per move: the RSMAX slots its plan read
     int* rsn;                   // per move: slots in rs (0: no plan this round)
+    int* pslot;                 // per move: the PRECMAX slots its plan writes
+    Tri* prec;                  // ... and the records written there
+    int2* pvt;                  // per move: PVTMAX incident-triangle updates (point, slot)
+    int4* phdr;                 // per move: records, deletion's updates, all updates, star-only
+    int2* pq;                   // per move: the new position
     unsigned long long* hkey;   // cell hash: cell key + 1, or 0 when empty
     int* hcnt;                  // moves naming the cell
     int hmask;
@@ -644,7 +654,9 @@ struct GlobalDev {
     int depth;
     int* powner;                // kd cell holding each point
     unsigned long long* gstats; // KDT_GSTAT_* counters
+    unsigned long long* part;   // per commit workgroup: applied, star-only, algorithmic bytes, transfers
 };
+constexpr int G_PART_MAX = 8192;  // commit workgroups the partial counters hold
 
 struct GBuild {
     const int* ord;  // every point, Hilbert order
@@ -723,13 +735,21 @@ __device__ __forceinline__ int kd_cell_of(const int2* split, int depth, int2 p) 
     return k - (1 << depth);
 }
 
-// After an applied move of p (by this lane): the point's kd cell.
-__device__ __forceinline__ void update_owner(const DevState& s, const GlobalDev& g, int p) {
-    const int cell = kd_cell_of(g.split, g.depth, s.xy[p]);
-    if (cell != g.powner[p]) {
-        g.powner[p] = cell;
-        atomicAdd(&g.gstats[KDT_GSTAT_TRANSFERS], 1ull);
+// The kd cell of position q for a point that was in cell `old`: kept when
+// q passes every comparison on the path to `old` (lane l checks level l, one
+// round of loads), else found by descending.  Whole wavefront.
+__device__ __forceinline__ int owner_after_move(const GlobalDev& g, int old, int2 q) {
+    const int lane = lane_id(), D = g.depth;
+    bool ok = true;
+    if (lane < D) {
+        const int k = ((1 << D) + old) >> (D - lane);  // the path's node at level `lane`
+        const bool right = (old >> (D - 1 - lane)) & 1;
+        const int2 sk = g.split[k];
+        const int a = (lane & 1) ? q.y : q.x, b = (lane & 1) ? q.x : q.y;
+        ok = (a > sk.x || (a == sk.x && b >= sk.y)) == right;
     }
+    if (!ballot(!ok)) return old;
+    return kd_cell_of(g.split, D, q);
 }
 
 __device__ __forceinline__ void stats_zero(WaveLDS& S) {
@@ -746,16 +766,9 @@ __device__ __forceinline__ void stats_flush(const DevState& s, WaveLDS& S) {
     }
 }
 
-// The last workgroup of a kernel to get here advances the round stamp.
-__device__ __forceinline__ void round_done(const GlobalDev& g) {
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(&g.ctr[GC_DONE], 1) == (int)gridDim.x - 1) {
-            atomicExch(&g.ctr[GC_DONE], 0);
-            atomicAdd(&g.ctr[GC_STAMP], 1);
-        }
-    }
-}
+// Advances the round stamp after a commit kernel (one thread; a counter of
+// finished workgroups would serialise thousands of atomics on one address).
+__global__ void k_next_round(GlobalDev g) { g.ctr[GC_STAMP] += 1; }
 
 __global__ void k_set(int* p, int v) { *p = v; }
 
@@ -804,55 +817,89 @@ __global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restri
 __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
                                                  const kdt_move_t* __restrict__ mv, int M) {
     __shared__ WaveLDS S;
-    const int m = blockIdx.x;
-    if (m >= M || g.mstate[m] != MS_PEND || s.status[0] != 0) return;
     const int lane = lane_id();
-    scratch_init(S);
     BlockView B = view_of(s, 0);
-    MovePlan pl{0, 0, 0};
-    int app = 0;
-    const int rc = apply_move(B, S, mv[m], s.frame[0], nullptr, &app, MV_PLAN, &pl);
-    if (rc != ST_OK) {
-        if (lane == 0) {
-            g.mstate[m] = MS_DONE;
-            fail_global(s, rc);
+    // a fixed grid strides over the step's moves (later rounds have few left)
+    for (int m = blockIdx.x; m < M; m += gridDim.x) {
+        if (g.mstate[m] != MS_PEND || s.status[0] != 0) continue;
+        scratch_init(S);
+        MovePlan pl{};
+        int app = 0;
+        const int rc = apply_move(B, S, mv[m], s.frame[0], nullptr, &app, MV_PLAN, &pl);
+        if (rc != ST_OK) {
+            if (lane == 0) {
+                g.mstate[m] = MS_DONE;
+                fail_global(s, rc);
+            }
+            continue;
         }
-        return;
-    }
-    if (app == 0) {  // target held by a point that stays put this step
-        if (lane == 0) {
-            g.mstate[m] = MS_DONE;
-            atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[0].blocked), 1ull);
+        if (app == 0) {  // target held by a point that stays put this step
+            if (lane == 0) {
+                g.mstate[m] = MS_DONE;
+                atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[0].blocked), 1ull);
+            }
+            continue;
         }
-        return;
-    }
-    const int total = pl.k + pl.used + pl.npath;
-    if (pl.npath > WPMAX || total > RSMAX) {
-        if (lane == 0) {
-            g.mstate[m] = MS_SERIAL;
-            g.serial[atomicAdd(&g.ctr[GC_SERIAL], 1)] = m;
-            atomicAdd(&g.gstats[KDT_GSTAT_OVERFLOW], 1ull);
+        // the records the plan changed (table entries marked dirty)
+        int ndirty = 0;
+        for (int base = 0; base < pl.used; base += WAVE) {
+            const int u = base + lane;
+            ndirty += __popcll(ballot(u < pl.used && (S.tflag[S.tused[u]] & F_DIRTY)));
         }
-        return;
+        const int total = pl.k + pl.used + pl.npath;
+        if (pl.npath > WPMAX || total > RSMAX || ndirty > PRECMAX || pl.nvt > PVTMAX) {
+            if (lane == 0) {
+                g.mstate[m] = MS_SERIAL;
+                g.serial[atomicAdd(&g.ctr[GC_SERIAL], 1)] = m;
+                atomicAdd(&g.gstats[KDT_GSTAT_OVERFLOW], 1ull);
+            }
+            continue;
+        }
+        // claim every slot read; keep the plan's writes for the commit
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
+        int* out = g.rs + (long long)m * RSMAX;
+        for (int i = lane; i < total; i += WAVE) {
+            const int slot = i < pl.k ? S.star_slot[i]
+                                      : (i < pl.k + pl.used ? S.tkey[S.tused[i - pl.k]] : S.wpath[i - pl.k - pl.used]);
+            out[i] = slot;
+            claim_max(&g.claim[slot], stamp);
+        }
+        int* ps = g.pslot + (long long)m * PRECMAX;
+        Tri* pr = g.prec + (long long)m * PRECMAX;
+        int nrec = 0;
+        for (int base = 0; base < pl.used; base += WAVE) {
+            const int u = base + lane;
+            const int h = u < pl.used ? S.tused[u] : 0;
+            const bool d = u < pl.used && (S.tflag[h] & F_DIRTY);
+            const uint64_t dm = ballot(d);
+            if (d) {
+                const int r = nrec + lanes_below(dm);
+                ps[r] = S.tkey[h];
+                pr[r] = S.trec[h];
+            }
+            nrec += __popcll(dm);
+        }
+        int2* pv = g.pvt + (long long)m * PVTMAX;
+        for (int i = lane; i < pl.nvt; i += WAVE) pv[i] = make_int2(S.vt_v[i], S.vt_s[i]);
+        if (lane == 0) {
+            g.phdr[m] = make_int4(nrec, pl.nvt_del, pl.nvt, pl.fast);
+            g.pq[m] = pl.q;
+            g.rsn[m] = total;
+        }
+        wsync();
     }
-    const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
-    int* out = g.rs + (long long)m * RSMAX;
-    for (int i = lane; i < total; i += WAVE) {
-        const int slot = i < pl.k ? S.star_slot[i]
-                                  : (i < pl.k + pl.used ? S.tkey[S.tused[i - pl.k]] : S.wpath[i - pl.k - pl.used]);
-        out[i] = slot;
-        claim_max(&g.claim[slot], stamp);
-    }
-    if (lane == 0) g.rsn[m] = total;
 }
 
+// A move that holds every claim of its plan writes the plan out: nothing the
+// plan read has changed since (every writer holds the claims of all it reads
+// and writes), so the recorded records are still the right ones.
 __global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
                                                    const kdt_move_t* __restrict__ mv, int M, int last,
                                                    int8_t* applied) {
-    __shared__ WaveLDS S;
-    const int m = blockIdx.x;
     const int lane = lane_id();
-    if (m < M && g.mstate[m] == MS_PEND && s.status[0] == 0) {
+    long long n_app = 0, n_fast = 0, n_alg = 0, n_tr = 0;
+    for (int m = blockIdx.x; m < M; m += gridDim.x) {
+        if (g.mstate[m] != MS_PEND || s.status[0] != 0) continue;
         const int nrs = g.rsn[m];
         const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
         const int* in = g.rs + (long long)m * RSMAX;
@@ -860,21 +907,35 @@ __global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
         for (int i = lane; i < nrs; i += WAVE) held &= claim_get(&g.claim[in[i]]) == stamp;
         const bool won = nrs > 0 && !ballot(!held && lane < nrs);
         if (won) {
-            scratch_init(S);
-            stats_zero(S);
             BlockView B = view_of(s, 0);
-            int app = 0;
-            const int rc = apply_move(B, S, mv[m], s.frame[0], &S.st, &app);
+            const int4 h = g.phdr[m];
+            const int* ps = g.pslot + (long long)m * PRECMAX;
+            const Tri* pr = g.prec + (long long)m * PRECMAX;
+            const int2* pv = g.pvt + (long long)m * PVTMAX;
+            for (int i = lane; i < h.x; i += WAVE) B.tri[ps[i]] = pr[i];
+            // the deletion's updates, then the insertion's (a point in both
+            // gets the later value: one wavefront's stores to one address
+            // land in program order)
+            for (int i = lane; i < h.y; i += WAVE)
+                if (pv[i].x != GHOST) B.vtri[pv[i].x] = pv[i].y;
+            for (int i = h.y + lane; i < h.z; i += WAVE)
+                if (pv[i].x != GHOST) B.vtri[pv[i].x] = pv[i].y;
+            const int p = mv[m].point;
+            const int2 q = g.pq[m];
+            const int oc = g.powner[p];
+            const int nc = owner_after_move(g, oc, q);
             if (lane == 0) {
-                if (rc != ST_OK) {
-                    fail_global(s, rc);
-                } else if (app) {
-                    update_owner(s, g, mv[m].point);
-                    if (applied) applied[m] = 1;
-                }
+                B.xy[p] = q;
+                if (nc != oc) g.powner[p] = nc;
+                if (applied) applied[m] = 1;
                 g.mstate[m] = MS_DONE;
             }
-            stats_flush(s, S);
+            // counted per workgroup, added up by the ordered pass (one
+            // atomic per move on a shared counter would serialise)
+            n_app += 1;
+            n_fast += h.w ? 1 : 0;
+            n_alg += 64LL * (nrs + h.x) + 4LL * h.z + 32;  // records read and written, updates, move
+            n_tr += nc != oc ? 1 : 0;
         } else if (lane == 0) {
             g.rsn[m] = 0;
             atomicAdd(&g.gstats[KDT_GSTAT_LOST], 1ull);
@@ -884,12 +945,18 @@ __global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
             }
         }
     }
-    round_done(g);
+    if (lane == 0 && blockIdx.x < G_PART_MAX && (n_app | n_tr)) {
+        unsigned long long* pp = g.part + 4 * blockIdx.x;
+        pp[0] += n_app;
+        pp[1] += n_fast;
+        pp[2] += n_alg;
+        pp[3] += n_tr;
+    }
 }
 
 __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
                                                    const kdt_move_t* __restrict__ mv, int M,
-                                                   int8_t* applied) {
+                                                   int8_t* applied, int parts) {
     __shared__ WaveLDS S;
     __shared__ int tmp[G_SERIAL_LDS], list[G_SERIAL_LDS];
     const int lane = lane_id();
@@ -900,10 +967,17 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
     const int4 fr = s.frame[0];
     auto one = [&](int m) {
         int app = 0;
+        const int p = mv[m].point;
+        const int oc = g.powner[p];
         const int rc = apply_move(B, S, mv[m], fr, &S.st, &app);
+        gsync();  // the new position is visible to every lane
+        const int nc = rc == ST_OK && app ? owner_after_move(g, oc, s.xy[p]) : oc;
         if (lane == 0) {
             if (rc != ST_OK) fail_global(s, rc);
-            else if (app) update_owner(s, g, mv[m].point);
+            if (nc != oc) {
+                g.powner[p] = nc;
+                atomicAdd(&g.gstats[KDT_GSTAT_TRANSFERS], 1ull);
+            }
             if (applied) applied[m] = (int8_t)app;
             g.mstate[m] = MS_DONE;
         }
@@ -942,6 +1016,28 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
             }
         }
         if (lane == 0) atomicAdd(&g.gstats[KDT_GSTAT_SERIAL], (unsigned long long)cnt);
+    }
+    // the commit rounds' per-workgroup counters
+    long long a = 0, f = 0, b = 0, t = 0;
+    for (int w = lane; w < parts; w += WAVE) {
+        unsigned long long* pp = g.part + 4 * w;
+        a += (long long)pp[0];
+        f += (long long)pp[1];
+        b += (long long)pp[2];
+        t += (long long)pp[3];
+        pp[0] = pp[1] = pp[2] = pp[3] = 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        f += __shfl_xor(f, off);
+        b += __shfl_xor(b, off);
+        t += __shfl_xor(t, off);
+    }
+    if (lane == 0) {
+        S.st.applied += a;
+        S.st.fast += f;
+        S.st.alg_bytes += b;
+        if (t) atomicAdd(&g.gstats[KDT_GSTAT_TRANSFERS], (unsigned long long)t);
     }
     stats_flush(s, S);
     if (lane == 0) g.ctr[GC_SERIAL] = 0;
@@ -1046,7 +1142,6 @@ __global__ void k_gb_commit(DevState s, GlobalDev g, GBuild gb, int lvl, long lo
     }
     const uint64_t pm = ballot(pend);
     if (pm && wl == first_lane(pm)) atomicAdd(&g.ctr[GC_PEND], __popcll(pm));
-    round_done(g);
 }
 
 __global__ void k_gb_defer_rest(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
@@ -1247,8 +1342,8 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
 
 // Global mode: the extra regions after the per-block layout of one block.
 struct GLayout {
-    size_t claim, mstate, rs, rsn, hkey, hcnt, ctr, serial, split, powner, gstats, att, pend, plan,
-        deferred, big, total;
+    size_t claim, mstate, rs, rsn, pslot, prec, pvt, phdr, pq, hkey, hcnt, ctr, serial, split, powner, gstats,
+        part, att, pend, plan, deferred, big, total;
     int hsize;
 };
 
@@ -1264,6 +1359,11 @@ GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves) {
     G.mstate = take(sizeof(int) * max_moves);
     G.rs = take(sizeof(int) * (size_t)RSMAX * max_moves);
     G.rsn = take(sizeof(int) * max_moves);
+    G.pslot = take(sizeof(int) * (size_t)PRECMAX * max_moves);
+    G.prec = take(sizeof(Tri) * (size_t)PRECMAX * max_moves);
+    G.pvt = take(sizeof(int2) * (size_t)PVTMAX * max_moves);
+    G.phdr = take(sizeof(int4) * max_moves);
+    G.pq = take(sizeof(int2) * max_moves);
     G.hkey = take(sizeof(unsigned long long) * hs);
     G.hcnt = take(sizeof(int) * hs);
     G.ctr = take(sizeof(int) * GC_N);
@@ -1271,6 +1371,7 @@ GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves) {
     G.split = take(sizeof(int2) * ((size_t)1 << depth));
     G.powner = take(sizeof(int) * n);
     G.gstats = take(sizeof(unsigned long long) * KDT_GSTAT_N);
+    G.part = take(sizeof(unsigned long long) * 4 * G_PART_MAX);
     G.att = take(sizeof(int) * (size_t)ATT_INTS * GB_CHUNK);
     G.pend = take(sizeof(int) * GB_CHUNK);
     G.plan = take(sizeof(int2) * GB_CHUNK);
@@ -1467,6 +1568,7 @@ int gbuild(kdt_ctx* c) {
                 k_set<<<1, 1, 0, st>>>(c->g.ctr + GC_PEND, 0);
                 k_gb_plan<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
                 k_gb_commit<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
+                k_next_round<<<1, 1, 0, st>>>(c->g);
                 int pend = 0;
                 if (check_hip(c, hipGetLastError()) ||
                     check_hip(c, hipMemcpyAsync(&pend, c->g.ctr + GC_PEND, sizeof(int), hipMemcpyDeviceToHost, st)) ||
@@ -2089,6 +2191,11 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->max_moves = max_moves;
     c->hsize = G.hsize;
     (void)hipGetDevice(&c->device);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+            c->cus = cus;
+    }
     c->pt_off = {0, (long long)n};
     c->tri_off = {0, 2 * (long long)n - 2};
     char* w = c->ws;
@@ -2111,6 +2218,11 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->g.mstate = (int*)(w + G.mstate);
     c->g.rs = (int*)(w + G.rs);
     c->g.rsn = (int*)(w + G.rsn);
+    c->g.pslot = (int*)(w + G.pslot);
+    c->g.prec = (Tri*)(w + G.prec);
+    c->g.pvt = (int2*)(w + G.pvt);
+    c->g.phdr = (int4*)(w + G.phdr);
+    c->g.pq = (int2*)(w + G.pq);
     c->g.hkey = (unsigned long long*)(w + G.hkey);
     c->g.hcnt = (int*)(w + G.hcnt);
     c->g.hmask = G.hsize - 1;
@@ -2120,6 +2232,7 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->g.depth = depth;
     c->g.powner = (int*)(w + G.powner);
     c->g.gstats = (unsigned long long*)(w + G.gstats);
+    c->g.part = (unsigned long long*)(w + G.part);
     c->gb.ord = (const int*)(w + L.order);
     c->gb.att = (int*)(w + G.att);
     c->gb.pend = (int*)(w + G.pend);
@@ -2144,6 +2257,7 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
     rc |= check_hip(c, hipMemsetAsync(w + G.claim, 0, sizeof(unsigned long long) * (2 * n - 2), s));
     rc |= check_hip(c, hipMemsetAsync(w + G.gstats, 0, sizeof(unsigned long long) * KDT_GSTAT_N, s));
+    rc |= check_hip(c, hipMemsetAsync(w + G.part, 0, sizeof(unsigned long long) * 4 * G_PART_MAX, s));
     rc |= check_hip(c, hipMemsetAsync(w + G.hkey, 0, sizeof(unsigned long long) * G.hsize, s));
     rc |= check_hip(c, hipMemsetAsync(w + G.hcnt, 0, sizeof(int) * G.hsize, s));
     if (rc == KDT_OK) rc = check_hip(c, hipStreamSynchronize(s));
@@ -2174,11 +2288,13 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
         k_zero<<<(c->hsize + 255) / 256, 256, 0, st>>>(c->g.hcnt, c->hsize);
         k_g_prep<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M, ap);
         k_g_classify<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M);
+        const int parts = std::min(M, std::min(8 * c->cus, G_PART_MAX));
         for (int r = 0; r < G_ROUNDS; ++r) {
-            k_g_plan<<<M, WAVE, 0, st>>>(c->dev, c->g, mv, M);
-            k_g_commit<<<M, WAVE, 0, st>>>(c->dev, c->g, mv, M, r == G_ROUNDS - 1 ? 1 : 0, ap);
+            k_g_plan<<<std::min(M, 4 * c->cus), WAVE, 0, st>>>(c->dev, c->g, mv, M);
+            k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r == G_ROUNDS - 1 ? 1 : 0, ap);
+            k_next_round<<<1, 1, 0, st>>>(c->g);
         }
-        k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap);
+        k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap, parts);
         timing_end(c, e0);
         if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
         c->step_count++;

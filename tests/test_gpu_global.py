@@ -33,16 +33,21 @@ def run_compare(w, steps, check_every=1):
     assert np.array_equal(G.owner(), K.owner())
     mv = torch.from_numpy(np.ascontiguousarray(w["mv"])).to(DEV)
     ap = torch.full((len(w["mv"]),), -1, dtype=torch.int8, device=DEV)
+    n_app = n_blk = 0
     for t in range(steps):
         lo, hi = int(w["step_off"][t]), int(w["step_off"][t + 1])
         G.run(mv, np.array([lo, hi], dtype=np.int64), ap)
         want = K.apply_step(w["mv"][lo:hi])
+        n_app += int(want.sum())
+        n_blk += int((~want).sum())
         got = ap[lo:hi].cpu().numpy()
         assert np.array_equal(got.astype(bool), want) and got.min() >= 0, t
         if (t + 1) % check_every == 0 or t == steps - 1:
             assert np.array_equal(G.positions(), K.xy), t
             assert np.array_equal(G.query_canonical(), K.dt()), t
             assert np.array_equal(G.owner(), K.owner()), t
+    st = G.stats()
+    assert st["applied"] == n_app and st["blocked"] == n_blk and st["errors"] == 0
     return G, K
 
 
@@ -90,6 +95,8 @@ def test_global_dense_interacting(seed):
     G, K = run_compare(_dense(seed, 15), 15)
     gs = G.gstats()
     assert gs["interacting"] > 0 and gs["serial"] >= gs["interacting"]
+    # transfers: applied moves whose point changed kd cell (the oracle's cells step by step)
+    assert gs["transfers"] > 0
 
 
 def test_global_rebuild_matches():
