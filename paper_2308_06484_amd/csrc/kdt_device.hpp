@@ -52,6 +52,8 @@ constexpr int VTMAX = KMAX + BMAX + 1;  // pending incident-triangle updates
 constexpr int DRYMAX = 256;     // moves of one block in one step on the rebuild branch
 constexpr int EMK = 16;          // links up to this size use the closed-form triple decode and edge matrix
 constexpr int WPMAX = 64;        // walk hops a planned move can record
+constexpr int SPLIT_K = 10;      // links from this size test candidates in two phases
+constexpr int SURV_MAX = 160;    // candidates the second phase holds
 
 constexpr int F_DIRTY = 1;  // table entry changed: write back
 constexpr int F_CAV = 2;    // table entry is in the current cavity
@@ -752,6 +754,74 @@ __device__ __forceinline__ void pair_of(int u, int* i, int* j) {
 // violating vertex; link vertex m's id and position sit in lane m's
 // registers and are broadcast to all lanes.  *nvt: pending incident-triangle
 // updates.  Returns ST_OK or an error code.
+// A candidate triangle of the hole: link triple (i, j, l) -- l may hold the
+// vertex at infinity -- or (q_i, q_j, q) with l == k, counter-clockwise.
+struct TriCand {
+    int i, j, l, vi, vj, vl;
+    int2 pi, pj, pl;
+    bool ghost, ok;
+};
+
+// The candidate with the given link indices (already oriented).
+__device__ __forceinline__ TriCand tri_cand_of(const WaveLDS& S, int k, int i, int j, int l, int qv, int2 q) {
+    TriCand c;
+    c.i = i; c.j = j; c.l = l;
+    c.vi = S.link[i]; c.vj = S.link[j];
+    c.pi = S.lxy[i]; c.pj = S.lxy[j];
+    c.vl = l == k ? qv : S.link[l];
+    c.pl = l == k ? q : S.lxy[l];
+    c.ghost = l != k && c.vl == GHOST;
+    c.ok = true;
+    return c;
+}
+
+// Candidate t (link triples first, then the q triangles); ok tells whether
+// it passes orientation and, with q, keeps q out of its circle.
+__device__ __forceinline__ TriCand tri_cand(const WaveLDS& S, int k, int t, int ntrip, int ncand, int qv,
+                                            int2 q, bool with_q) {
+    int i = 0, j = 1, l = 2;
+    bool ok = t < ncand, qtri = false;
+    if (ok) {
+        if (t >= ntrip) {
+            pair_of(t - ntrip, &i, &j);
+            l = k;
+            qtri = true;
+        } else if (k <= EMK) {
+            triple_of(t, &i, &j, &l);
+        } else {
+            l = (int)cbrtf(6.0f * (float)t) + 1;
+            while (l * (l - 1) * (l - 2) / 6 > t) --l;
+            while ((l + 1) * l * (l - 1) / 6 <= t) ++l;
+            const int r = t - l * (l - 1) * (l - 2) / 6;
+            j = (int)sqrtf(2.0f * (float)r) + 1;
+            while (j * (j - 1) / 2 > r) --j;
+            while ((j + 1) * j / 2 <= r) ++j;
+            i = r - j * (j - 1) / 2;
+        }
+    }
+    TriCand c = tri_cand_of(S, k, i, j, l, qv, q);
+    ok = ok && c.vi != GHOST && c.vj != GHOST;  // only l can be the vertex at infinity (it is last)
+    if (qtri && ok) {  // orient (q_i, q_j, q) counter-clockwise
+        const double o = orient(c.pi, c.pj, q);
+        if (o < 0) c = tri_cand_of(S, k, j, i, l, qv, q);
+        ok = o != 0;
+    } else {
+        ok = ok && (c.ghost || orient(c.pi, c.pj, c.pl) > 0);
+    }
+    // a link triple must also keep q out of its circle
+    if (ok && with_q && !qtri) ok = incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, q, qv) < 0;
+    c.ok = ok;
+    return c;
+}
+
+// Does link vertex m (id vm at pm) rule the candidate out: inside its
+// perturbed circle, or inside the half-plane of a ghost?
+__device__ __forceinline__ bool cand_killed_by(const TriCand& c, int m, int vm, int2 pm) {
+    if (vm == GHOST || m == c.i || m == c.j || m == c.l) return false;
+    return c.ghost ? ghost_conflict(c.pi, c.pj, pm)
+                   : incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, pm, vm) >= 0;
+}
+
 __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
                          int* nvt, BlockStats* st) {
     const int lane = lane_id();
@@ -764,7 +834,47 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     const int2 lp = lane < k ? S.lxy[lane] : make_int2(0, 0);
     const int ntrip = k * (k - 1) * (k - 2) / 6;
     const int ncand = ntrip + (with_q ? k * (k - 1) / 2 : 0);
-    for (int t0 = 0; t0 < ncand; t0 += WAVE) {
+    // Large links: each candidate is first tested against the link
+    // neighbours of its vertices, which reject most non-Delaunay triples;
+    // the survivors (in S.emat, their verdicts in S.cav_ent, both idle
+    // here) are then tested against every link vertex, one (survivor,
+    // vertex) pair per lane.  Small links test every vertex per lane.
+    bool done = false;
+    if (k >= SPLIT_K) {
+        int nsurv = 0;
+        for (int t0 = 0; t0 < ncand; t0 += WAVE) {
+            TriCand c = tri_cand(S, k, t0 + lane, ntrip, ncand, qv, q, with_q);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                if (c.l == k && f >= 4) continue;  // q has no link neighbours
+                const int base = f < 2 ? c.i : (f < 4 ? c.j : c.l);
+                const int m = (base + ((f & 1) ? 1 : k - 1)) % k;
+                if (c.ok && cand_killed_by(c, m, S.link[m], S.lxy[m])) c.ok = false;
+            }
+            const uint64_t sm = ballot(c.ok);
+            if (c.ok && nsurv + lanes_below(sm) < SURV_MAX) S.emat[nsurv + lanes_below(sm)] = pack3(c.i, c.j, c.l);
+            nsurv += __popcll(sm);
+        }
+        if (nsurv <= SURV_MAX) {
+            for (int x = lane; x < nsurv; x += WAVE) S.cav_ent[x] = 1;
+            wsync();
+            for (int x = lane; x < nsurv * k; x += WAVE) {
+                const int si = x / k, m = x - si * k;
+                const int key = S.emat[si];
+                const TriCand c = tri_cand_of(S, k, key >> 16, (key >> 8) & 255, key & 255, qv, q);
+                if (cand_killed_by(c, m, S.link[m], S.lxy[m])) S.cav_ent[si] = 0;
+            }
+            wsync();
+            for (int x = lane; x < nsurv; x += WAVE) {
+                if (S.cav_ent[x]) {
+                    const int pos = atomicAdd(&S.nhole, 1);
+                    if (pos < KMAX) S.hole_key[pos] = S.emat[x];
+                }
+            }
+            done = true;
+        }
+    }
+    for (int t0 = 0; t0 < ncand && !done; t0 += WAVE) {
         const int t = t0 + lane;
         bool ok = t < ncand;
         int i = 0, j = 1, l = 2;
