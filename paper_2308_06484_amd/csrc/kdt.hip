@@ -766,16 +766,12 @@ __device__ __forceinline__ void stats_flush(const DevState& s, WaveLDS& S) {
     }
 }
 
-// Advances the round stamp after a commit kernel (one thread; a counter of
-// finished workgroups would serialise thousands of atomics on one address).
-__global__ void k_next_round(GlobalDev g) { g.ctr[GC_STAMP] += 1; }
+// Round r of a step (or of a chunk of a build) stamps its claims with
+// ctr[GC_STAMP] + r; the base advances past the rounds once they are done.
+__global__ void k_add(int* p, int v) { *p += v; }
 
 __global__ void k_set(int* p, int v) { *p = v; }
 
-__global__ void k_zero(int* p, long long n) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
 
 __global__ void k_g_prep(DevState s, GlobalDev g, const kdt_move_t* __restrict__ mv, int M,
                          int8_t* applied) {
@@ -815,10 +811,16 @@ __global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restri
 }
 
 __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
-                                                 const kdt_move_t* __restrict__ mv, int M) {
+                                                 const kdt_move_t* __restrict__ mv, int M, int round) {
     __shared__ WaveLDS S;
     const int lane = lane_id();
     BlockView B = view_of(s, 0);
+    if (round == 0) {  // the step's cell hash has been read: empty it for the next step
+        for (int h = blockIdx.x * WAVE + lane; h <= g.hmask; h += gridDim.x * WAVE) {
+            g.hkey[h] = 0ull;
+            g.hcnt[h] = 0;
+        }
+    }
     // a fixed grid strides over the step's moves (later rounds have few left)
     for (int m = blockIdx.x; m < M; m += gridDim.x) {
         if (g.mstate[m] != MS_PEND || s.status[0] != 0) continue;
@@ -856,7 +858,7 @@ __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
             continue;
         }
         // claim every slot read; keep the plan's writes for the commit
-        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP] + round, pb_prio(m));
         int* out = g.rs + (long long)m * RSMAX;
         for (int i = lane; i < total; i += WAVE) {
             const int slot = i < pl.k ? S.star_slot[i]
@@ -894,14 +896,14 @@ __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
 // plan read has changed since (every writer holds the claims of all it reads
 // and writes), so the recorded records are still the right ones.
 __global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
-                                                   const kdt_move_t* __restrict__ mv, int M, int last,
-                                                   int8_t* applied) {
+                                                   const kdt_move_t* __restrict__ mv, int M, int round,
+                                                   int last, int8_t* applied) {
     const int lane = lane_id();
     long long n_app = 0, n_fast = 0, n_alg = 0, n_tr = 0;
     for (int m = blockIdx.x; m < M; m += gridDim.x) {
         if (g.mstate[m] != MS_PEND || s.status[0] != 0) continue;
         const int nrs = g.rsn[m];
-        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(m));
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP] + round, pb_prio(m));
         const int* in = g.rs + (long long)m * RSMAX;
         bool held = nrs > 0;
         for (int i = lane; i < nrs; i += WAVE) held &= claim_get(&g.claim[in[i]]) == stamp;
@@ -1040,7 +1042,10 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
         if (t) atomicAdd(&g.gstats[KDT_GSTAT_TRANSFERS], (unsigned long long)t);
     }
     stats_flush(s, S);
-    if (lane == 0) g.ctr[GC_SERIAL] = 0;
+    if (lane == 0) {
+        g.ctr[GC_SERIAL] = 0;
+        g.ctr[GC_STAMP] += G_ROUNDS;  // past this step's rounds
+    }
 }
 
 // ---- grid-wide builder: the rounds of the block builder with every chunk
@@ -1074,7 +1079,7 @@ __global__ void k_gb_chunk(GlobalDev g, GBuild gb, int lvl, long long j0, int cn
     gb.plan[t] = make_int2(0, 0);
 }
 
-__global__ void k_gb_plan(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+__global__ void k_gb_plan(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt, int round) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= cnt || !gb.pend[t] || s.status[0] != 0) return;
     BlockView B = view_of(s, 0);
@@ -1087,7 +1092,7 @@ __global__ void k_gb_plan(DevState s, GlobalDev g, GBuild gb, int lvl, long long
     int nc = 0, nb = 0;
     const int rc = tplan(B, v, B.xy[v], hint, A, &nc, &nb);
     if (rc == 0) {
-        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(i));
+        const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP] + round, pb_prio(i));
         for (int m = 0; m < nc; ++m) claim_max(&g.claim[A.cav(m)], stamp);
         for (int e = 0; e < nb; ++e) claim_max(&g.claim[A.bout(e) >> 2], stamp);
         gb.plan[t] = make_int2(nc, nb);
@@ -1103,7 +1108,7 @@ __global__ void k_gb_plan(DevState s, GlobalDev g, GBuild gb, int lvl, long long
     }
 }
 
-__global__ void k_gb_commit(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt) {
+__global__ void k_gb_commit(DevState s, GlobalDev g, GBuild gb, int lvl, long long j0, int cnt, int round) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     BlockView B = view_of(s, 0);
     int i = 0;
@@ -1115,7 +1120,7 @@ __global__ void k_gb_commit(DevState s, GlobalDev g, GBuild gb, int lvl, long lo
         pl = gb.plan[t];
         i = (int)(lvl + 2LL * lvl * (j0 + t));
         if (pl.x > 0) {
-            const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP], pb_prio(i));
+            const unsigned long long stamp = stamp_of(g.ctr[GC_STAMP] + round, pb_prio(i));
             won = true;
             for (int m = 0; m < pl.x; ++m) won &= claim_get(&g.claim[A.cav(m)]) == stamp;
             for (int e = 0; e < pl.y; ++e) won &= claim_get(&g.claim[A.bout(e) >> 2]) == stamp;
@@ -1566,9 +1571,8 @@ int gbuild(kdt_ctx* c) {
             int r = 0;
             for (; r < GB_ROUNDS; ++r) {
                 k_set<<<1, 1, 0, st>>>(c->g.ctr + GC_PEND, 0);
-                k_gb_plan<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
-                k_gb_commit<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
-                k_next_round<<<1, 1, 0, st>>>(c->g);
+                k_gb_plan<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt, r);
+                k_gb_commit<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt, r);
                 int pend = 0;
                 if (check_hip(c, hipGetLastError()) ||
                     check_hip(c, hipMemcpyAsync(&pend, c->g.ctr + GC_PEND, sizeof(int), hipMemcpyDeviceToHost, st)) ||
@@ -1578,6 +1582,7 @@ int gbuild(kdt_ctx* c) {
                 if (pend == 0) break;
             }
             if (r == GB_ROUNDS) k_gb_defer_rest<<<grid, 256, 0, st>>>(c->dev, c->g, c->gb, lvl, j0, cnt);
+            k_add<<<1, 1, 0, st>>>(c->g.ctr + GC_STAMP, GB_ROUNDS + 1);  // past this chunk's rounds
         }
     }
     k_gb_serial<<<1, 1, 0, st>>>(c->dev, c->g, c->gb);
@@ -2284,15 +2289,12 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
         const kdt_move_t* mv = moves + step_off[t];
         int8_t* ap = applied ? applied + step_off[t] : nullptr;
         hipEvent_t e0 = timing_begin(c);
-        k_zero<<<(2 * c->hsize + 255) / 256, 256, 0, st>>>((int*)c->g.hkey, 2LL * c->hsize);
-        k_zero<<<(c->hsize + 255) / 256, 256, 0, st>>>(c->g.hcnt, c->hsize);
         k_g_prep<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M, ap);
         k_g_classify<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M);
         const int parts = std::min(M, std::min(8 * c->cus, G_PART_MAX));
         for (int r = 0; r < G_ROUNDS; ++r) {
-            k_g_plan<<<std::min(M, 4 * c->cus), WAVE, 0, st>>>(c->dev, c->g, mv, M);
-            k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r == G_ROUNDS - 1 ? 1 : 0, ap);
-            k_next_round<<<1, 1, 0, st>>>(c->g);
+            k_g_plan<<<std::min(M, 4 * c->cus), WAVE, 0, st>>>(c->dev, c->g, mv, M, r);
+            k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r, r == G_ROUNDS - 1 ? 1 : 0, ap);
         }
         k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap, parts);
         timing_end(c, e0);
