@@ -334,6 +334,29 @@ def main():
             g.close()
         d2.close()
 
+    # the alternative the paper weighs against updating (Sec. I): rebuild
+    # every block from scratch after each step, on the first steps of the
+    # same stream
+    if not args.no_variants:
+        R = min(20, K)
+        d2 = fresh(stream)
+        d2.set_policy("rebuild")
+        a0 = d2.stats()["applied"]
+        off_r = off_timed[:R].contiguous()
+        with torch.cuda.stream(stream):
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(stream)
+            d2.run(mv, off_r)
+            f1.record(stream)
+            stream.synchronize()
+        vms = f0.elapsed_time(f1)
+        d2.sync()
+        napp = d2.stats()["applied"] - a0
+        variants["full_rebuild_per_step"] = {"moves_per_s": napp / (vms / 1e3), "ms_per_step": vms / R,
+                                             "steps": R}
+        log(f"variant full_rebuild_per_step: {vms:.2f} ms for {R} steps, {napp / (vms / 1e3):.3e} moves/s")
+        d2.close()
+
     applied = s1["applied"] - s0["applied"]
     blocked = s1["blocked"] - s0["blocked"]
     alg = s1["alg_bytes"] - s0["alg_bytes"]

@@ -1054,9 +1054,12 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
 __global__ void k_gb_kidx(DevState s, GlobalDev g, GBuild gb) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x + 2;
     const int n = (int)s.pt_off[1];
-    if (i >= n) return;
     const int2 a = s.xy[gb.ord[0]], b = s.xy[gb.ord[1]];
-    if (orient(a, b, s.xy[gb.ord[i]]) != 0) atomicMin(&g.ctr[GC_KIDX], (int)i);
+    const bool off = i < n && orient(a, b, s.xy[gb.ord[i]]) != 0;
+    // one atomic per wavefront: its first lane off the line has its smallest index
+    const uint64_t m = ballot(off);
+    if (m && (int)(threadIdx.x & (WAVE - 1)) == first_lane(m) && (int)i < g.ctr[GC_KIDX])
+        atomicMin(&g.ctr[GC_KIDX], (int)i);
 }
 
 __global__ void k_gb_seed(DevState s, GlobalDev g, GBuild gb) {
