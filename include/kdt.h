@@ -132,9 +132,10 @@ int kdt_step(kdt_ctx* ctx);
 #define KDT_RUN_FUSED 1
 #define KDT_RUN_PERSISTENT 2
 /* KDT_RUN_PERSISTENT launches, per step, a fixed grid of workgroups (a few
- * per compute unit, see kdt_set_launch) that take blocks from a queue,
- * largest blocks first, so blocks of uneven size share the machine evenly.
- * All three forms give identical results. */
+ * per compute unit, see kdt_set_launch) that share the blocks sorted by
+ * size, largest first, each workgroup taking ranks alternately from the
+ * large and the small end of every round, so blocks of uneven size share the
+ * machine evenly.  All three forms give identical results. */
 int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
             int32_t n_steps, int8_t* applied, int32_t flags);
 

@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the per-step paths of libkdt.
 
 Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
-one kernel per step, the persistent queue launch with 1..8 workgroups per
+one kernel per step, the persistent launch with 1..8 workgroups per
 compute unit, each either launched step by step or captured as a HIP graph,
 and the fused multi-step launch.  Every candidate computes the same
 triangulations (tests check this bit for bit), so the choice only changes

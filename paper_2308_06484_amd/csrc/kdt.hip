@@ -568,36 +568,27 @@ __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t
     }
 }
 
-// One time step on a fixed grid of workgroups (a few per compute unit) that
-// take blocks from a queue in the given order -- largest expected cost
-// first -- until it is empty.  The last workgroup to leave resets the queue
-// for the next launch, so consecutive launches (and graph replays) need no
-// reset of their own.
+// One time step on a fixed grid of G workgroups (a few per compute unit)
+// that share the blocks in the given order -- largest expected cost first --
+// without a queue: in round r workgroup w takes rank r*G + w, or r*G + G-1-w
+// in odd rounds (each workgroup's blocks alternate between the large and the
+// small end of every round, so the totals even out).  A shared counter would
+// serialise one atomic per block.
 __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_move_t* __restrict__ mv,
                                                        const int* __restrict__ off,
-                                                       const int* __restrict__ order, int* queue,
-                                                       int n_blocks, int8_t* applied, long long step) {
+                                                       const int* __restrict__ order, int n_blocks,
+                                                       int8_t* applied, long long step) {
     __shared__ WaveLDS S;
-    __shared__ int next;
     extern __shared__ __align__(16) char dynx[];
     scratch_init(S);
-    while (true) {
-        if (lane_id() == 0) next = atomicAdd(&queue[0], 1);
-        wsync();
-        const int qi = next;
-        wsync();
-        if (qi >= n_blocks) break;
+    const int G = gridDim.x, w = blockIdx.x;
+    for (int r = 0; r * G < n_blocks; ++r) {
+        const int qi = r * G + ((r & 1) ? G - 1 - w : w);
+        if (qi >= n_blocks) continue;
         const int b = order[qi];
         if (s.status[b] != 0) continue;
         run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step, true, dynx);
         gsync();
-    }
-    if (lane_id() == 0) {
-        __threadfence();
-        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
-            atomicExch(&queue[0], 0);
-            atomicExch(&queue[1], 0);
-        }
     }
 }
 
@@ -1316,7 +1307,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
-        qtris, stage_mv, stage_off, sticky, lpt, queue, total;
+        qtris, stage_mv, stage_off, sticky, lpt, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -1343,7 +1334,6 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_off = take(sizeof(int) * (B + 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
-    L.queue = take(sizeof(int) * 4);
     L.total = o;
     return L;
 }
@@ -1738,9 +1728,8 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     rc |= check_hip(c, hipMemsetAsync(w + L.rb_flag, 0, sizeof(int) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
-    rc |= check_hip(c, hipMemsetAsync(w + L.queue, 0, sizeof(int) * 4, s));
     {
-        // queue order for the persistent launch: largest blocks first
+        // block order of the persistent launch: largest blocks first
         std::vector<int> lpt(n_blocks);
         for (int32_t b = 0; b < n_blocks; ++b) lpt[b] = b;
         std::stable_sort(lpt.begin(), lpt.end(), [&](int x, int y) {
@@ -1846,7 +1835,7 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
         if (flags == KDT_RUN_PERSISTENT)
             k_step_persist<<<grid, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
-                                                         (int*)(w + c->L.queue), c->B, applied, c->step_count);
+                                                                       c->B, applied, c->step_count);
         else
             k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count);
         if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
