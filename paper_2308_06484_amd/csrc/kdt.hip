@@ -1433,6 +1433,8 @@ struct kdt_ctx {
     long long step_count = 0;  // time steps launched so far (log index)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
+    int timing_period = 1;      // record every timing_period-th launch
+    long long timing_count = 0;  // launches seen since timing was enabled
     int pb_lds = 0;         // dynamic LDS of k_build_blocks at init
     int pb_lds_follow = 0;  // ... after a step, for the blocks too large for the step kernels
     bool follow = false;    // some block is too large to be rebuilt inside the step kernels
@@ -1459,6 +1461,7 @@ int check_hip(kdt_ctx* c, hipError_t e) {
 // Event pair around one launch when timing is on.
 hipEvent_t timing_begin(kdt_ctx* c) {
     if (!c->timing) return nullptr;
+    if (c->timing_count++ % c->timing_period != 0) return nullptr;
     if (c->ev_used == c->ev.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess) return nullptr;
@@ -2097,8 +2100,11 @@ int kdt_block_status(kdt_ctx* c, int32_t* host_status) {
 int kdt_timing(kdt_ctx* c, int32_t enable) {
     if (!c) return KDT_E_ARG;
     if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    if (enable < 0) return KDT_E_ARG;
     c->ev_used = 0;
     c->timing = enable != 0;
+    c->timing_period = enable > 0 ? enable : 1;
+    c->timing_count = 0;
     if (!c->timing) release_events(c);
     return KDT_OK;
 }

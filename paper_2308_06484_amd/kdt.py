@@ -312,9 +312,10 @@ class KineticDT:
         _check(_lib().kdt_block_status(self.ctx, _ptr(out)), "kdt_block_status")
         return out
 
-    def timing(self, enable=True):
-        """Record a HIP event pair around every launch (see kdt_timing)."""
-        _check(_lib().kdt_timing(self.ctx, 1 if enable else 0), "kdt_timing")
+    def timing(self, enable=True, period=1):
+        """Record a HIP event pair around every period-th step's launch (see
+        kdt_timing); enable=False stops."""
+        _check(_lib().kdt_timing(self.ctx, int(period) if enable else 0), "kdt_timing")
 
     def timing_read(self):
         """(summed kernel milliseconds, launches) since timing was enabled."""
