@@ -1,6 +1,6 @@
-"""Launch forms (one kernel per step, persistent queue, fused, HIP graph
-replay) and the autotuner: every form gives the same triangulations, bit
-for bit, as the oracle."""
+"""Launch forms (one kernel per step, persistent, fused, HIP graph replay)
+and the autotuner: every form gives the same triangulations, bit for bit,
+as the oracle, under the repair and the rebuild policies."""
 import numpy as np
 import pytest
 import torch
@@ -12,13 +12,15 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _run(w, mode, graph=False, per_cu=None, repeat=1):
+def _run(w, mode, graph=False, per_cu=None, repeat=1, policy=None):
     from paper_2308_06484_amd.kdt import KineticDT
     stream = torch.cuda.Stream(device=DEV)
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
         if per_cu:
             dt.set_launch(per_cu)
+        if policy:
+            dt.set_policy(policy)
         mv = torch.from_numpy(w["mv"]).to(DEV)
         off = torch.from_numpy(w["mv_off"]).to(DEV)
         applied = torch.zeros(w["mv"].shape[0], dtype=torch.int8, device=DEV)
@@ -80,3 +82,19 @@ def test_autotune_returns_a_timed_candidate(tmp_path, monkeypatch):
     assert len(best["table"]) == len(A.DEFAULT_CANDIDATES)
     again = A.autotune(w, steps=10)  # served from the cache
     assert again["mode"] == best["mode"] and again["s_per_step"] == best["s_per_step"]
+
+
+def test_rebuild_policy_in_every_launch_form(uneven):
+    """Blocks of 64..3000 points: the small ones are rebuilt inside the step
+    kernel, the large ones by the build kernel launched after it (recorded
+    in the graph too); every form matches the oracle."""
+    w = uneven
+    oracle = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    app = np.concatenate([oracle.apply_step(w["mv"], w["mv_off"][t]) for t in range(w["mv_off"].shape[0])])
+    for mode, graph, per_cu in [("step", False, None), ("step", True, None), ("persistent", True, 2),
+                                ("fused", False, None)]:
+        got = _run(w, mode, graph, per_cu, policy="rebuild")
+        assert np.array_equal(got[0], oracle.all_dt(8)), (mode, graph)
+        assert np.array_equal(got[1], oracle.xy), (mode, graph)
+        assert np.array_equal(got[2].astype(bool), app), (mode, graph)
+        assert got[3]["errors"] == 0 and got[3]["rebuilt"] > 0
