@@ -184,9 +184,9 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
         return ST_OK;
     }
     const long long c2 = wall_clock64();
-    // fast path: q inside the star, p not on the hull, and no triangle
-    // around the star destroyed by q -- the star polygon alone changes
-    bool fast = in_star && S.link[k - 1] != GHOST && k + 1 <= EMK;
+    // fast path: q inside the star and no triangle around the star
+    // destroyed by q -- the star region alone changes
+    bool fast = in_star && k + 1 <= EMK;
     if (fast) fast = !ballot(lane < k && conflicts(S.trec[S.out_ent[lane]], q, p));
     int rc;
     if (fast) {
@@ -622,8 +622,8 @@ constexpr int GB_CHUNK = 1 << 17;     // points the grid-wide builder plans at o
 constexpr int GB_BIG = 1 << 14;       // cavity capacity of a deferred point's attempt
 constexpr int GB_DEFER = 1 << 16;     // deferred points of one build
 constexpr int GB_ROUNDS = 64;         // rounds of one chunk before its points are deferred
-// g.ctr entries
-constexpr int GC_STAMP = 0, GC_DONE = 1, GC_SERIAL = 2, GC_USED = 3, GC_PEND = 4, GC_DEFER = 5,
+// g.ctr entries (entry 1 unused)
+constexpr int GC_STAMP = 0, GC_SERIAL = 2, GC_USED = 3, GC_PEND = 4, GC_DEFER = 5,
               GC_KIDX = 6, GC_N = 16;
 
 struct GlobalDev {

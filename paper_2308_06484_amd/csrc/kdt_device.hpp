@@ -743,49 +743,62 @@ __device__ __forceinline__ void pair_of(int u, int* i, int* j) {
 //    DT*(S - p) there; k - 2 of them take the first k - 2 star slots and the
 //    last two star slots become free.
 //  * With q -- Delete and Insert at once, used when q lies inside the star
-//    and destroys none of the triangles around it: then every link edge stays
-//    Delaunay, nothing outside the star changes, and the star polygon holds
-//    DT*(link + q) restricted to it: the link triples above that also keep q
-//    out of their circle, and the counter-clockwise triangles (q_i, q_j, q)
-//    whose circle holds no link vertex.  There are k of them, one per star
-//    slot.
+//    (a ghost's half-plane included) and destroys none of the triangles
+//    around it: then every link edge stays Delaunay, nothing outside the
+//    star changes, and the star region holds DT*(link + q) restricted to
+//    it: the link triples above that also keep q out of their circle or
+//    half-plane, the counter-clockwise triangles (q_i, q_j, q) whose circle
+//    holds no link vertex and, when p is on the hull, the ghosts
+//    (q_i, q, inf) and (q, q_i, inf) with no link vertex beyond their edge
+//    (q on the hull: every face around q lies in the star region, whose
+//    boundary edges are Delaunay).  There are k of them, one per star slot.
 //
 // Lanes stride over the candidate triangles, each rejected at its first
-// violating vertex; link vertex m's id and position sit in lane m's
-// registers and are broadcast to all lanes.  *nvt: pending incident-triangle
-// updates.  Returns ST_OK or an error code.
-// A candidate triangle of the hole: link triple (i, j, l) -- l may hold the
-// vertex at infinity -- or (q_i, q_j, q) with l == k, counter-clockwise.
+// violating vertex.  *nvt: pending incident-triangle updates.  Returns ST_OK
+// or an error code.
+//
+// A candidate triangle by polygon index in stored order: link indices
+// 0..k-1, index k for q; only the last stored vertex can be the vertex at
+// infinity.
 struct TriCand {
     int i, j, l, vi, vj, vl;
     int2 pi, pj, pl;
     bool ghost, ok;
 };
 
-// The candidate with the given link indices (already oriented).
+// The candidate with the given indices (already oriented).
 __device__ __forceinline__ TriCand tri_cand_of(const WaveLDS& S, int k, int i, int j, int l, int qv, int2 q) {
     TriCand c;
     c.i = i; c.j = j; c.l = l;
-    c.vi = S.link[i]; c.vj = S.link[j];
-    c.pi = S.lxy[i]; c.pj = S.lxy[j];
+    c.vi = i == k ? qv : S.link[i];
+    c.vj = j == k ? qv : S.link[j];
     c.vl = l == k ? qv : S.link[l];
+    c.pi = i == k ? q : S.lxy[i];
+    c.pj = j == k ? q : S.lxy[j];
     c.pl = l == k ? q : S.lxy[l];
-    c.ghost = l != k && c.vl == GHOST;
+    c.ghost = c.vl == GHOST;
     c.ok = true;
     return c;
 }
 
-// Candidate t (link triples first, then the q triangles); ok tells whether
-// it passes orientation and, with q, keeps q out of its circle.
-__device__ __forceinline__ TriCand tri_cand(const WaveLDS& S, int k, int t, int ntrip, int ncand, int qv,
-                                            int2 q, bool with_q) {
-    int i = 0, j = 1, l = 2;
-    bool ok = t < ncand, qtri = false;
+// Candidate t: the link triples first, then the pairs (q_i, q_j) with q,
+// then (p on the hull) the ghosts with q; ok tells whether it passes
+// orientation and, with q, keeps q out of its circle or half-plane.
+__device__ __forceinline__ TriCand tri_cand(const WaveLDS& S, int k, int t, int ntrip, int npair, int ncand,
+                                            int qv, int2 q, bool with_q) {
+    int i = 0, j = 1, l = 2, kind = 0;  // 0 link triple, 1 (q_i, q_j, q), 2 ghost with q
+    bool ok = t < ncand;
     if (ok) {
-        if (t >= ntrip) {
+        if (t >= ntrip + npair) {
+            const int u = t - ntrip - npair, a = u >> 1;
+            i = (u & 1) ? k : a;
+            j = (u & 1) ? a : k;
+            l = k - 1;
+            kind = 2;
+        } else if (t >= ntrip) {
             pair_of(t - ntrip, &i, &j);
             l = k;
-            qtri = true;
+            kind = 1;
         } else if (k <= EMK) {
             triple_of(t, &i, &j, &l);
         } else {
@@ -800,16 +813,18 @@ __device__ __forceinline__ TriCand tri_cand(const WaveLDS& S, int k, int t, int 
         }
     }
     TriCand c = tri_cand_of(S, k, i, j, l, qv, q);
-    ok = ok && c.vi != GHOST && c.vj != GHOST;  // only l can be the vertex at infinity (it is last)
-    if (qtri && ok) {  // orient (q_i, q_j, q) counter-clockwise
+    ok = ok && c.vi != GHOST && c.vj != GHOST;
+    if (kind == 1 && ok) {  // orient (q_i, q_j, q) counter-clockwise
         const double o = orient(c.pi, c.pj, q);
         if (o < 0) c = tri_cand_of(S, k, j, i, l, qv, q);
         ok = o != 0;
-    } else {
+    } else if (kind == 0) {
         ok = ok && (c.ghost || orient(c.pi, c.pj, c.pl) > 0);
+        // a link triple must also keep q out of its circle or half-plane
+        if (ok && with_q)
+            ok = c.ghost ? !ghost_conflict(c.pi, c.pj, q)
+                         : incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, q, qv) < 0;
     }
-    // a link triple must also keep q out of its circle
-    if (ok && with_q && !qtri) ok = incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, q, qv) < 0;
     c.ok = ok;
     return c;
 }
@@ -833,7 +848,9 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     const int lv = lane < k ? S.link[lane] : GHOST;
     const int2 lp = lane < k ? S.lxy[lane] : make_int2(0, 0);
     const int ntrip = k * (k - 1) * (k - 2) / 6;
-    const int ncand = ntrip + (with_q ? k * (k - 1) / 2 : 0);
+    const int npair = with_q ? k * (k - 1) / 2 : 0;
+    const int nqg = with_q && S.link[k - 1] == GHOST ? 2 * (k - 1) : 0;
+    const int ncand = ntrip + npair + nqg;
     // Large links: each candidate is first tested against the link
     // neighbours of its vertices, which reject most non-Delaunay triples;
     // the survivors (in S.emat, their verdicts in S.cav_ent, both idle
@@ -843,11 +860,11 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     if (k >= SPLIT_K) {
         int nsurv = 0;
         for (int t0 = 0; t0 < ncand; t0 += WAVE) {
-            TriCand c = tri_cand(S, k, t0 + lane, ntrip, ncand, qv, q, with_q);
+            TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                if (c.l == k && f >= 4) continue;  // q has no link neighbours
                 const int base = f < 2 ? c.i : (f < 4 ? c.j : c.l);
+                if (base == k) continue;  // q has no link neighbours
                 const int m = (base + ((f & 1) ? 1 : k - 1)) % k;
                 if (c.ok && cand_killed_by(c, m, S.link[m], S.lxy[m])) c.ok = false;
             }
@@ -875,59 +892,17 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
         }
     }
     for (int t0 = 0; t0 < ncand && !done; t0 += WAVE) {
-        const int t = t0 + lane;
-        bool ok = t < ncand;
-        int i = 0, j = 1, l = 2;
-        bool qtri = false;
-        if (ok) {
-            if (t >= ntrip) {
-                pair_of(t - ntrip, &i, &j);
-                l = k;
-                qtri = true;
-            } else if (k <= EMK) {
-                triple_of(t, &i, &j, &l);
-            } else {
-                l = (int)cbrtf(6.0f * (float)t) + 1;
-                while (l * (l - 1) * (l - 2) / 6 > t) --l;
-                while ((l + 1) * l * (l - 1) / 6 <= t) ++l;
-                const int r = t - l * (l - 1) * (l - 2) / 6;
-                j = (int)sqrtf(2.0f * (float)r) + 1;
-                while (j * (j - 1) / 2 > r) --j;
-                while ((j + 1) * j / 2 <= r) ++j;
-                i = r - j * (j - 1) / 2;
-            }
-        }
-        int vi = S.link[i], vj = S.link[j];
-        int2 pi2 = S.lxy[i], pj2 = S.lxy[j];
-        const int vl = qtri ? qv : S.link[l];
-        const int2 pl2 = qtri ? q : S.lxy[l];
-        // only l can be the vertex at infinity (it is last)
-        ok = ok && vi != GHOST && vj != GHOST;
-        const bool ghost = !qtri && vl == GHOST;
-        if (qtri && ok) {  // orient (q_i, q_j, q) counter-clockwise
-            const double o = orient(pi2, pj2, q);
-            if (o < 0) {
-                const int ti = i; i = j; j = ti;
-                const int tv = vi; vi = vj; vj = tv;
-                const int2 tp = pi2; pi2 = pj2; pj2 = tp;
-            }
-            ok = o != 0;
-        } else {
-            ok = ok && (ghost || orient(pi2, pj2, pl2) > 0);
-        }
-        // a link triple must also keep q out of its circle
-        if (ok && with_q && !qtri) ok = incircle_star(pi2, vi, pj2, vj, pl2, vl, q, qv) < 0;
+        TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
+        // link vertex m's id and position sit in lane m's registers
         for (int m = 0; m < k; ++m) {
-            if (!ballot(ok)) break;
+            if (!ballot(c.ok)) break;
             const int vm = __builtin_amdgcn_readlane(lv, m);
             const int2 pm = make_int2(__builtin_amdgcn_readlane(lp.x, m), __builtin_amdgcn_readlane(lp.y, m));
-            if (!ok || vm == GHOST || m == i || m == j || m == l) continue;
-            if (ghost) ok = !ghost_conflict(pi2, pj2, pm);
-            else ok = incircle_star(pi2, vi, pj2, vj, pl2, vl, pm, vm) < 0;
+            if (c.ok && cand_killed_by(c, m, vm, pm)) c.ok = false;
         }
-        if (ok) {
+        if (c.ok) {
             const int pos = atomicAdd(&S.nhole, 1);
-            if (pos < KMAX) S.hole_key[pos] = pack3(i, j, l);
+            if (pos < KMAX) S.hole_key[pos] = pack3(c.i, c.j, c.l);
         }
     }
     wsync();
@@ -960,12 +935,11 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     if (lane < nh) {
         const int hk = S.hole_key[lane];
         const int cs[3] = {hk >> 16, (hk >> 8) & 255, hk & 255};
-        const int2 c0 = S.lxy[cs[0]], c1 = S.lxy[cs[1]];
-        const bool q2 = cs[2] == k;  // only the last vertex can be q (index k)
-        has_q = q2;
-        const int v2 = q2 ? qv : S.link[cs[2]];
-        const int2 c2 = q2 ? q : S.lxy[cs[2]];
-        h.v = make_int4(S.link[cs[0]], S.link[cs[1]], v2, 0);
+        const TriCand c = tri_cand_of(S, k, cs[0], cs[1], cs[2], qv, q);
+        const int2 c0 = c.pi, c1 = c.pj, c2 = c.pl;
+        const int v2 = c.vl;
+        has_q = cs[0] == k || cs[1] == k || cs[2] == k;
+        h.v = make_int4(c.vi, c.vj, v2, 0);
         h.n = make_int4(0, 0, 0, 0);
         h.c01 = make_int4(c0.x, c0.y, c1.x, c1.y);
         h.c2 = v2 != GHOST ? make_int4(c2.x, c2.y, 0, 0) : make_int4(0, 0, 0, 0);
