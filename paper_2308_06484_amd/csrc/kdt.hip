@@ -149,6 +149,7 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     const int p = mv.point, dir = mv.dir, dist = mv.dist;
     if (p < 0 || p >= B.n || dir < 0 || dir > 3 || dist < 1) return ST_ARG;
     const int2 o = B.xy[p];
+    const int t0 = B.vtri[p];  // read beside the position: one round trip
     long long qx = o.x, qy = o.y;
     if (dir == 0) qx += dist;
     else if (dir == 1) qx -= dist;
@@ -163,7 +164,7 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     int npath = 0;
     int* path = mode == MV_PLAN ? S.wpath : nullptr;
     int used = 0, nvt = 0;
-    const int k = gather_star(B, S, p, &used, st);
+    const int k = gather_star(B, S, p, t0, &used, st);
     if (k < 0) return k;
     const long long c1 = wall_clock64();
     bool in_star, on_vertex;
@@ -216,23 +217,21 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     rc = fill_star(B, S, k, p, q, false, &used, &nvt, st);
     if (rc != ST_OK) return rc;
     const long long c3 = wall_clock64();
-    // a triangle of DT*(S - p) that q destroys: the one the walk found
-    // (outside the star, so untouched by the deletion), else a hole
-    // triangle, else the end of a walk from the hole
-    int seed = tq;
+    // where the cavity of q in DT*(S - p) starts: the triangle the walk
+    // found (outside the star, so untouched by the deletion), else every
+    // hole or surrounding triangle q destroys, else the end of a walk from
+    // the hole
+    int seed = tq, nseed = 0;
     if (in_star) {
-        const bool c = lane < k - 2 && conflicts(S.trec[S.hole_ent[lane]], q, p);
-        const uint64_t m = ballot(c);
-        if (m) {
-            seed = S.star_slot[first_lane(m)];
-        } else {
+        nseed = seed_cavity(S, k, q, p);
+        if (nseed == 0) {
             int hit2;
             seed = walk<true>(B, &S, S.star_slot[0], q, &hit2, &hops, path, &npath);
             if (seed < 0 || hit2 >= 0) return ST_INTERNAL;
         }
     }
     const int nvt_del = nvt;
-    rc = insert_vertex(B, S, p, q, seed, S.star_slot[k - 2], S.star_slot[k - 1], &used, &nvt, st);
+    rc = insert_vertex(B, S, p, q, seed, nseed, S.star_slot[k - 2], S.star_slot[k - 1], &used, &nvt, st);
     if (rc != ST_OK) return rc;
     if (mode == MV_PLAN) {
         *plan = MovePlan{k, used, npath, nvt_del, nvt, q, 0};

@@ -419,28 +419,33 @@ __device__ __forceinline__ int3 fan_phys(int a, int b) {
 }
 
 // Insert point qv at q into the block's DT* (Bowyer-Watson, Sec. IV), in the
-// write-back table.  `seed` is a triangle q destroys; f0, f1 are two free
-// slots that take the two triangles the insertion adds.  The cavity grows
-// level by level: the lanes test the frontier's neighbours, ballots and
-// prefix counts compact the survivors.  *used: table entries in use;
-// *nvt: pending incident-triangle updates.  Returns ST_OK or an error code
-// (the table is then not to be written back).
-__device__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int f0, int f1,
-                             int* used, int* nvt, BlockStats* st) {
+// write-back table.  The cavity starts from the nseed table entries already
+// in S.cav_ent (flagged F_CAV) or, when nseed is 0, from `seed`, a triangle
+// q destroys; f0, f1 are two free slots that take the two triangles the
+// insertion adds.  The cavity grows level by level: the lanes test the
+// frontier's neighbours, ballots and prefix counts compact the survivors.
+// *used: table entries in use; *nvt: pending incident-triangle updates.
+// Returns ST_OK or an error code (the table is then not to be written back).
+__device__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int nseed, int f0,
+                             int f1, int* used, int* nvt, BlockStats* st) {
     const int lane = lane_id();
-    if (bad_slot(B, seed) || bad_slot(B, f0) || bad_slot(B, f1)) return ST_INTERNAL;
+    if (bad_slot(B, f0) || bad_slot(B, f1)) return ST_INTERNAL;
     const int fetched0 = *used;
-    const int se = tget(B, S, lane == 0, seed, used);
-    const int se0 = __shfl(se, 0);
-    if (se0 < 0) return ST_CAPACITY;
-    if (bad_tri(B, S.trec[se0].v)) return ST_INTERNAL;
-    if (lane == 0) {
-        S.cav_ent[0] = se0;
-        S.tflag[se0] |= F_CAV;
+    int ncav = nseed, nbnd = 0;  // wave-uniform counts of S.cav_ent and S.bnd_*
+    if (nseed == 0) {
+        if (bad_slot(B, seed)) return ST_INTERNAL;
+        const int se = tget(B, S, lane == 0, seed, used);
+        const int se0 = __shfl(se, 0);
+        if (se0 < 0) return ST_CAPACITY;
+        if (bad_tri(B, S.trec[se0].v)) return ST_INTERNAL;
+        if (lane == 0) {
+            S.cav_ent[0] = se0;
+            S.tflag[se0] |= F_CAV;
+        }
+        wsync();
+        ncav = 1;
     }
-    wsync();
-    int fs = 0, fe = 1;
-    int ncav = 1, nbnd = 0;  // wave-uniform counts of S.cav_ent and S.bnd_*
+    int fs = 0, fe = ncav;
     while (fs < fe) {
         const int ncand = 3 * (fe - fs);
         for (int base = 0; base < ncand; base += WAVE) {
@@ -611,10 +616,9 @@ __device__ void table_drop(WaveLDS& S, int used) {
 // the vertex at infinity, if p is on the hull, rotated to the last place;
 // and the triangles outside the link edges into the table.  Two walkers
 // turn around p in opposite directions and meet halfway.
-// Returns the degree k (>= 3) or an error code.
-__device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int* used, BlockStats* st) {
+// t0: p's incident triangle.  Returns the degree k (>= 3) or an error code.
+__device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* used, BlockStats* st) {
     const int lane = lane_id();
-    const int t0 = B.vtri[p];
     if (bad_slot(B, t0)) return ST_INTERNAL;
     const Tri r0 = B.tri[t0];
     if (bad_tri(B, r0.v)) return ST_INTERNAL;
@@ -717,6 +721,32 @@ __device__ __forceinline__ void locate_in_star(const WaveLDS& S, int k, int2 pp,
     }
     *in_star = ballot(in) != 0;
     *on_vertex = ballot(on) != 0;
+}
+
+// After the hole of p is filled (q inside the star): every triangle of the
+// table that q destroys -- hole triangles, then triangles around the star,
+// each once -- goes into S.cav_ent, flagged F_CAV.  The triangles a point
+// destroys form one connected region, so the cavity grows from these
+// without a walk.  Returns their number.
+__device__ __forceinline__ int seed_cavity(WaveLDS& S, int k, int2 q, int qv) {
+    const int lane = lane_id();
+    const int he = lane < k - 2 ? S.hole_ent[lane] : -1;
+    const bool ch = he >= 0 && conflicts(S.trec[he], q, qv);
+    const uint64_t mh = ballot(ch);
+    if (ch) {
+        S.cav_ent[lanes_below(mh)] = he;
+        S.tflag[he] |= F_CAV;
+    }
+    const int nh = __popcll(mh);
+    wsync();
+    const int oe = lane < k ? S.out_ent[lane] : -1;
+    bool co = oe >= 0 && conflicts(S.trec[oe], q, qv);
+    // a triangle outside two link edges is taken once
+    if (co) co = (atomicOr(&S.tflag[oe], F_CAV) & F_CAV) == 0;
+    const uint64_t mo = ballot(co);
+    if (co) S.cav_ent[nh + lanes_below(mo)] = oe;
+    wsync();
+    return nh + __popcll(mo);
 }
 
 __device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
