@@ -170,11 +170,29 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     bool in_star, on_vertex;
     locate_in_star(S, k, o, q, &in_star, &on_vertex);
     int hops = 0, tq = -1;
+    bool in_ring = false;
     if (!in_star) {
-        int hit;
-        tq = walk<false>(B, &S, S.star_slot[0], q, &hit, &hops, path, &npath);
-        if (tq < 0) return ST_INTERNAL;
-        on_vertex = hit >= 0;
+        // q in a (closed, real) triangle around the star: no walk
+        bool hit = false, occ = false;
+        if (lane < k) {
+            const Tri t = S.trec[S.out_ent[lane]];
+            if (t.v.z != GHOST) {
+                const int2 a = cget(t, 0), b = cget(t, 1), c = cget(t, 2);
+                hit = orient(a, b, q) >= 0 && orient(b, c, q) >= 0 && orient(c, a, q) >= 0;
+                occ = hit && (same(a, q) || same(b, q) || same(c, q));
+            }
+        }
+        const uint64_t hm = ballot(hit);
+        if (hm) {
+            in_ring = true;
+            on_vertex = ballot(occ) != 0;
+            tq = S.outref[first_lane(hm)] >> 2;
+        } else {
+            int hit2;
+            tq = walk<false>(B, &S, S.star_slot[0], q, &hit2, &hops, path, &npath);
+            if (tq < 0) return ST_INTERNAL;
+            on_vertex = hit2 >= 0;
+        }
     }
     if (on_vertex) {
         table_clear(S);
@@ -186,12 +204,22 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     }
     const long long c2 = wall_clock64();
     // fast path: q inside the star and no triangle around the star
-    // destroyed by q -- the star region alone changes
-    bool fast = in_star && k + 1 <= EMK;
-    if (fast) fast = !ballot(lane < k && conflicts(S.trec[S.out_ent[lane]], q, p));
+    // destroyed by q -- the star region alone changes -- or q inside the
+    // region grown by the destroyed triangles around the star
+    bool fast = (in_star || in_ring) && k + 1 <= EMK;
+    int kr = k;
+    if (fast) {
+        const uint64_t cm = ballot(lane < k && conflicts(S.trec[S.out_ent[lane]], q, p));
+        if (cm) {
+            kr = grow_region(B, S, k, q, p, cm, &used);
+            fast = kr > 0;
+        } else {
+            fast = in_star;  // q in a triangle around the star destroys it
+        }
+    }
     int rc;
     if (fast) {
-        rc = fill_star(B, S, k, p, q, true, &used, &nvt, st);
+        rc = fill_star(B, S, kr, p, q, true, &used, &nvt, st);
         if (rc != ST_OK) return rc;
         if (mode == MV_PLAN) {
             *plan = MovePlan{k, used, npath, nvt, nvt, q, 1};

@@ -178,6 +178,34 @@ __device__ __forceinline__ bool bad_tri(const BlockView& B, const int4& v) {
            (v.z != GHOST && (unsigned)v.z >= (unsigned)B.n);
 }
 
+// A record with all four parts requested before any is used.  Left to
+// itself the compiler issues the parts that a check's branch does not need
+// behind that branch, one memory round trip later; the empty asm takes every
+// part as an operand, so all four loads leave together and one wait covers
+// them.
+__device__ __forceinline__ Tri load_tri(const Tri* p) {
+    const int4* q = reinterpret_cast<const int4*>(p);
+    Tri t;
+    t.v = q[0];
+    t.n = q[1];
+    t.c01 = q[2];
+    t.c2 = q[3];
+    asm volatile("" : "+v"(t.v.x), "+v"(t.v.y), "+v"(t.v.z), "+v"(t.n.x), "+v"(t.n.y), "+v"(t.n.z),
+                 "+v"(t.c01.x), "+v"(t.c01.y), "+v"(t.c01.z), "+v"(t.c01.w), "+v"(t.c2.x), "+v"(t.c2.y));
+    return t;
+}
+// Two records at once, in one round trip.
+__device__ __forceinline__ void load_tri2(const Tri* p, const Tri* r, Tri& a, Tri& b) {
+    const int4* q = reinterpret_cast<const int4*>(p);
+    const int4* u = reinterpret_cast<const int4*>(r);
+    a.v = q[0]; a.n = q[1]; a.c01 = q[2]; a.c2 = q[3];
+    b.v = u[0]; b.n = u[1]; b.c01 = u[2]; b.c2 = u[3];
+    asm volatile("" : "+v"(a.v.x), "+v"(a.v.y), "+v"(a.v.z), "+v"(a.n.x), "+v"(a.n.y), "+v"(a.n.z),
+                 "+v"(a.c01.x), "+v"(a.c01.y), "+v"(a.c01.z), "+v"(a.c01.w), "+v"(a.c2.x), "+v"(a.c2.y),
+                 "+v"(b.v.x), "+v"(b.v.y), "+v"(b.v.z), "+v"(b.n.x), "+v"(b.n.y), "+v"(b.n.z),
+                 "+v"(b.c01.x), "+v"(b.c01.y), "+v"(b.c01.z), "+v"(b.c01.w), "+v"(b.c2.x), "+v"(b.c2.y));
+}
+
 // ---------------------------------------------------------------- predicates
 // Every coordinate is in [0, 2^24), so differences are below 2^24 in
 // magnitude.
@@ -343,7 +371,14 @@ __device__ __forceinline__ int tget(const BlockView& B, WaveLDS& S, bool want, i
     bool mine;
     const int e = tclaim(S, want, s, &mine);
     if (mine) {
-        S.trec[e] = B.tri[s];
+        // all four parts in flight before the first is stored
+        const int4* src = reinterpret_cast<const int4*>(B.tri + s);
+        const int4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
+        int4* dst = reinterpret_cast<int4*>(&S.trec[e]);
+        dst[0] = r0;
+        dst[1] = r1;
+        dst[2] = r2;
+        dst[3] = r3;
         S.tflag[e] = 0;
     }
     tnote(S, mine, e, used);
@@ -355,7 +390,7 @@ __device__ __forceinline__ int tget(const BlockView& B, WaveLDS& S, bool want, i
 __device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s) {
     const int e = tfind(S, s);
     if (e >= 0) return S.trec[e];
-    return B.tri[s];
+    return load_tri(B.tri + s);
 }
 
 // ---------------------------------------------------------------- walk
@@ -376,7 +411,7 @@ __device__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int
             if (*npath < WPMAX && lane_id() == 0) path[*npath] = cur;
             ++*npath;
         }
-        const Tri t = TABLE ? tread(B, *S, cur) : B.tri[cur];
+        const Tri t = TABLE ? tread(B, *S, cur) : load_tri(B.tri + cur);
         if (bad_tri(B, t.v)) return -1;
         const int2 p0 = cget(t, 0), p1 = cget(t, 1);
         if (t.v.z == GHOST) {
@@ -426,7 +461,7 @@ __device__ __forceinline__ int3 fan_phys(int a, int b) {
 // frontier's neighbours, ballots and prefix counts compact the survivors.
 // *used: table entries in use; *nvt: pending incident-triangle updates.
 // Returns ST_OK or an error code (the table is then not to be written back).
-__device__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int nseed, int f0,
+__device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int nseed, int f0,
                              int f1, int* used, int* nvt, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, f0) || bad_slot(B, f1)) return ST_INTERNAL;
@@ -620,7 +655,7 @@ __device__ void table_drop(WaveLDS& S, int used) {
 __device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* used, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, t0)) return ST_INTERNAL;
-    const Tri r0 = B.tri[t0];
+    const Tri r0 = load_tri(B.tri + t0);
     if (bad_tri(B, r0.v)) return ST_INTERNAL;
     const int pi0 = r0.v.x == p ? 0 : (r0.v.y == p ? 1 : (r0.v.z == p ? 2 : -1));
     if (pi0 < 0) return ST_INTERNAL;
@@ -640,8 +675,8 @@ __device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* u
         const int cs = ccw_ref >> 2, ws = cw_ref >> 2;
         if (cs == last_cw) break;
         if (bad_slot(B, cs) || bad_slot(B, ws)) return ST_INTERNAL;
-        const Tri rc = B.tri[cs];
-        const Tri rw = B.tri[ws];
+        Tri rc, rw;
+        load_tri2(B.tri + cs, B.tri + ws, rc, rw);
         const int pc = ((ccw_ref & 3) + 1) % 3, pw = ((cw_ref & 3) + 2) % 3;
         if (bad_tri(B, rc.v) || bad_tri(B, rw.v) || vget(rc.v, pc) != p || vget(rw.v, pw) != p)
             return ST_INTERNAL;
@@ -747,6 +782,83 @@ __device__ __forceinline__ int seed_cavity(WaveLDS& S, int k, int2 q, int qv) {
     if (co) S.cav_ent[nh + lanes_below(mo)] = oe;
     wsync();
     return nh + __popcll(mo);
+}
+
+// Widen the star region by the triangles around the star that q destroys,
+// so that the star-only path covers them as well: triangle T_s outside link
+// edge s = (q_s, q_s+1) is (r_s, q_s+1, q_s), and the region's boundary runs
+// q_s, r_s, q_s+1 there.  Taken only if every T_s is a real triangle, its
+// r_s off the link, the r_s distinct (the region stays a simple polygon with no
+// vertex inside), no triangle across a new boundary edge is destroyed by q
+// (the triangles q destroys are connected, so its cavity then stays in the
+// region) and the polygon keeps at most EMK - 1 vertices.  The region's
+// triangles are then retriangulated like a star: DT*(boundary + q) inside
+// it.  cm: link edges whose outside triangle q destroys.  Returns the new
+// vertex count -- the polygon arrays rewritten, the grown triangles' slots
+// after the star's in S.star_slot -- or 0 with the polygon unchanged.
+__device__ __forceinline__ int grow_region(const BlockView& B, WaveLDS& S, int k, int2 q, int qv, uint64_t cm,
+                                           int* used) {
+    const int lane = lane_id();
+    const int k2 = k + __popcll(cm);
+    if (k2 + 1 > EMK) return 0;
+    const bool c = lane < k && ((cm >> lane) & 1ull);
+    int lv = GHOST, orf = 0, oen = 0, r = GHOST, u1 = 0, u2 = 0;
+    int2 lp = make_int2(0, 0), pr = make_int2(0, 0);
+    bool ghost = false;
+    if (lane < k) {
+        lv = S.link[lane];
+        lp = S.lxy[lane];
+        orf = S.outref[lane];
+        oen = S.out_ent[lane];
+    }
+    if (c) {
+        const Tri t = S.trec[oen];
+        const int e = orf & 3;
+        ghost = t.v.z == GHOST;
+        r = vget(t.v, e);
+        pr = cget(t, e);
+        u1 = vget(t.n, (e + 1) % 3);  // across (q_s, r_s)
+        u2 = vget(t.n, (e + 2) % 3);  // across (r_s, q_s+1)
+    }
+    if (ballot(c && ghost)) return 0;  // the hull changes beyond the star: no
+    bool clash = false;
+    for (int m = 0; m < k; ++m) {
+        const int lm = __builtin_amdgcn_readlane(lv, m), rm = __builtin_amdgcn_readlane(r, m);
+        clash = clash || (c && (lm == r || (m != lane && ((cm >> m) & 1ull) && rm == r)));
+    }
+    if (ballot(clash)) return 0;
+    // the triangles across the new boundary edges: lanes 0..31 the first
+    // edge of T_s, lanes 32..63 the second (k <= EMK < 32)
+    const int src = lane & 31;
+    const bool want = src < k && ((cm >> src) & 1ull);
+    // both reads by every lane: a lane-dependent choice between two shuffles
+    // would run each with half the lanes off, and a read from a lane that is
+    // off does not return its value
+    const int s1 = __shfl(u1, src), s2 = __shfl(u2, src);
+    const int uref = lane < 32 ? s1 : s2;
+    if (ballot(want && bad_slot(B, uref >> 2))) return 0;
+    const int ue = tget(B, S, want, uref >> 2, used);
+    if (ballot(want && ue < 0)) return 0;
+    if (ballot(want && conflicts(S.trec[ue], q, qv))) return 0;
+    const int ue1 = __shfl(ue, src), ue2 = __shfl(ue, src + 32);
+    // q_s moves to s + (grown edges before s), r_s right after it
+    const int at = lane + lanes_below(cm);
+    wsync();
+    if (lane < k) {
+        S.link[at] = lv;
+        S.lxy[at] = lp;
+        S.outref[at] = c ? u1 : orf;
+        S.out_ent[at] = c ? ue1 : oen;
+    }
+    if (c) {
+        S.link[at + 1] = r;
+        S.lxy[at + 1] = pr;
+        S.outref[at + 1] = u2;
+        S.out_ent[at + 1] = ue2;
+        S.star_slot[k + lanes_below(cm)] = orf >> 2;
+    }
+    wsync();
+    return k2;
 }
 
 __device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
@@ -881,22 +993,26 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     const int npair = with_q ? k * (k - 1) / 2 : 0;
     const int nqg = with_q && S.link[k - 1] == GHOST ? 2 * (k - 1) : 0;
     const int ncand = ntrip + npair + nqg;
-    // Large links: each candidate is first tested against the link
-    // neighbours of its vertices, which reject most non-Delaunay triples;
-    // the survivors (in S.emat, their verdicts in S.cav_ent, both idle
-    // here) are then tested against every link vertex, one (survivor,
-    // vertex) pair per lane.  Small links test every vertex per lane.
+    // Two phases: the candidates that pass orientation (and keep q out)
+    // are compacted into S.emat, their verdicts in S.cav_ent (both idle
+    // here), and then tested against every link vertex, one (candidate,
+    // vertex) pair per lane.  Large links first test each candidate against
+    // the link neighbours of its vertices, which reject most non-Delaunay
+    // triples.  Too many survivors: every lane tests its candidate against
+    // every vertex.
     bool done = false;
-    if (k >= SPLIT_K) {
+    {
         int nsurv = 0;
         for (int t0 = 0; t0 < ncand; t0 += WAVE) {
             TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
+            if (k >= SPLIT_K) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const int base = f < 2 ? c.i : (f < 4 ? c.j : c.l);
-                if (base == k) continue;  // q has no link neighbours
-                const int m = (base + ((f & 1) ? 1 : k - 1)) % k;
-                if (c.ok && cand_killed_by(c, m, S.link[m], S.lxy[m])) c.ok = false;
+                for (int f = 0; f < 6; ++f) {
+                    const int base = f < 2 ? c.i : (f < 4 ? c.j : c.l);
+                    if (base == k) continue;  // q has no link neighbours
+                    const int m = (base + ((f & 1) ? 1 : k - 1)) % k;
+                    if (c.ok && cand_killed_by(c, m, S.link[m], S.lxy[m])) c.ok = false;
+                }
             }
             const uint64_t sm = ballot(c.ok);
             if (c.ok && nsurv + lanes_below(sm) < SURV_MAX) S.emat[nsurv + lanes_below(sm)] = pack3(c.i, c.j, c.l);
@@ -1007,7 +1123,7 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     bool mine;
     const int he = tclaim(S, lane < nh, S.star_slot[lane < nh ? lane : 0], &mine);
     tnote(S, mine, he, used);
-    if (ballot(lane < nh && !mine)) return ST_INTERNAL;  // star slots were not in the table
+    if (ballot(lane < nh && he < 0)) return ST_CAPACITY;
     if (lane < nh) {
         S.trec[he] = h;
         S.tflag[he] = F_DIRTY;
