@@ -32,6 +32,10 @@ constexpr int KDT_COORD_LIMIT = 1 << 24;
 
 // ------------------------------------------------------------------ device
 
+// Kernel arguments are read through the scalar cache in 64-byte lines; the
+// fields a move reads sit in the first line and, with the step kernels' own
+// arguments, the third, so that the second (build, global mode, selection
+// inputs) is not fetched on the way to a move.
 struct DevState {
     Tri* tri;
     int2* xy;
@@ -40,21 +44,21 @@ struct DevState {
     const long long* tri_off;
     const int4* frame;
     int* status;
-    BlockStats* stats;
+    int policy;    // repair-or-rebuild selection: KDT_POLICY_*
+    int step_lds;  // dynamic LDS the step kernels run with: blocks whose build fits it are rebuilt there
     int* sticky;
     const int* order;  // per-block insertion order (Hilbert order at init)
     int* owner;        // one int per triangle slot: cavity claims of the parallel build
     int* own2;         // one int per triangle slot: boundary claims of the parallel build
     int* rb_flag;      // per block: rebuild after this step (set by the dry run)
-    int step_lds;      // dynamic LDS the step kernels run with: blocks whose build fits it are rebuilt there
-    // repair-or-rebuild selection
-    int policy;          // KDT_POLICY_*
-    float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
     const float* mlp_w;  // MLP parameters (policy MLP)
-    float* log;          // per step and block: LOG_FIELDS floats, or null
     long long log_cap;   // steps the log holds (ring)
+    float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
     int n_blocks;
+    BlockStats* stats;
+    float* log;  // per step and block: LOG_FIELDS floats, or null
 };
+static_assert(offsetof(DevState, step_lds) < 64 && offsetof(DevState, stats) >= 128, "move fields off their lines");
 
 __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
     BlockView B;
@@ -65,6 +69,34 @@ __device__ __forceinline__ BlockView view_of(const DevState& s, int b) {
     B.n = (int)(p1 - p0);
     B.ntri = 2 * B.n - 2;
     return B;
+}
+
+// What a block's step reads first -- its status, move range, point range,
+// record offset and frame -- requested in one round trip.
+struct BlockHead {
+    int status, m0, m1;
+    long long p0, p1, toff;
+    int4 fr;
+};
+__device__ __forceinline__ BlockHead load_head(const DevState& s, int b, const int* off) {
+    BlockHead h;
+    h.status = s.status[b];
+    h.m0 = off[b];
+    h.m1 = off[b + 1];
+    h.p0 = s.pt_off[b];
+    h.p1 = s.pt_off[b + 1];
+    h.toff = s.tri_off[b];
+    h.fr = s.frame[b];
+    return h;
+}
+// Nothing to do: a failed block, or a move range that starts past its end
+// (no moves, as the loop would find).  The other fields are tested too,
+// against what never holds (a block's points lie inside its frame), so that
+// the compiler keeps every load of the head ahead of this branch.
+__device__ __forceinline__ bool head_skip(const BlockHead& h) {
+    // (bitwise: a chain of || would wait for each load at its own branch)
+    return ((h.status != 0) | (h.m0 > h.m1) | (h.p0 > h.p1) | (h.toff < 0) | (h.fr.x > h.fr.z) |
+            (h.fr.y > h.fr.w)) != 0;
 }
 
 __device__ __forceinline__ void fail_block(const DevState& s, int b, int code) {
@@ -169,7 +201,7 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     const long long c1 = wall_clock64();
     bool in_star, on_vertex;
     locate_in_star(S, k, o, q, &in_star, &on_vertex);
-    int hops = 0, tq = -1;
+    int hops = 0, tq = -1, kr = k;
     bool in_ring = false;
     if (!in_star) {
         // q in a (closed, real) triangle around the star: no walk
@@ -207,11 +239,10 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     // destroyed by q -- the star region alone changes -- or q inside the
     // region grown by the destroyed triangles around the star
     bool fast = (in_star || in_ring) && k + 1 <= EMK;
-    int kr = k;
     if (fast) {
         const uint64_t cm = ballot(lane < k && conflicts(S.trec[S.out_ent[lane]], q, p));
         if (cm) {
-            kr = grow_region(B, S, k, q, p, cm, &used);
+            kr = grow_region(B, S, k, q, p, cm, &used, !in_star);
             fast = kr > 0;
         } else {
             fast = in_star;  // q in a triangle around the star destroys it
@@ -491,10 +522,16 @@ __device__ __forceinline__ int choose_branch(const DevState& s, const float* f) 
     return o1 < o0 ? 1 : 0;
 }
 
-__device__ __forceinline__ void run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
-                                int m0, int m1, int8_t* applied, long long step, bool defer, char* dynx) {
-    BlockView B = view_of(s, b);
-    const int4 fr = s.frame[b];
+__device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
+                                const BlockHead& h, int8_t* applied, long long step, bool defer, char* dynx) {
+    BlockView B;
+    B.tri = s.tri + h.toff;
+    B.xy = s.xy + h.p0;
+    B.vtri = s.vtri + h.p0;
+    B.n = (int)(h.p1 - h.p0);
+    B.ntri = 2 * B.n - 2;
+    const int4 fr = h.fr;
+    const int m0 = h.m0, m1 = h.m1;
     const int lane = lane_id();
     // counters start at zero in LDS and are added to the block's totals at
     // the end (no load of the totals on the way in)
@@ -568,6 +605,7 @@ __device__ __forceinline__ void run_block_moves(const DevState& s, WaveLDS& S, i
         if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b]) + lane, (unsigned long long)v);
     }
     if (rc != ST_OK) fail_block(s, b, rc);
+    return rc;
 }
 
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
@@ -575,9 +613,10 @@ __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __r
     __shared__ WaveLDS S;
     extern __shared__ __align__(16) char dynx[];
     const int b = blockIdx.x;
-    if (s.status[b] != 0) return;
+    const BlockHead h = load_head(s, b, off);
+    if (head_skip(h)) return;
     scratch_init(S);
-    run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step, true, dynx);
+    run_block_moves(s, S, b, mv, h, applied, step, true, dynx);
 }
 
 __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t* __restrict__ mv,
@@ -586,11 +625,16 @@ __global__ void __launch_bounds__(WAVE) k_run_fused(DevState s, const kdt_move_t
     __shared__ WaveLDS S;
     extern __shared__ __align__(16) char dynx[];
     const int b = blockIdx.x;
+    // the status changes from here on only by this wavefront
+    BlockHead h = load_head(s, b, off);
+    if (h.status != 0) return;
     scratch_init(S);
     for (int t = 0; t < n_steps; ++t) {
-        if (s.status[b] != 0) return;
         const int* o = off + (long long)t * (n_blocks + 1);
-        run_block_moves(s, S, b, mv, o[b], o[b + 1], applied, step0 + t, false, dynx);
+        h.m0 = o[b];
+        h.m1 = o[b + 1];
+        if (head_skip(h)) continue;
+        if (run_block_moves(s, S, b, mv, h, applied, step0 + t, false, dynx) != ST_OK) return;
         gsync();
     }
 }
@@ -613,8 +657,9 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
         const int qi = r * G + ((r & 1) ? G - 1 - w : w);
         if (qi >= n_blocks) continue;
         const int b = order[qi];
-        if (s.status[b] != 0) continue;
-        run_block_moves(s, S, b, mv, off[b], off[b + 1], applied, step, true, dynx);
+        const BlockHead h = load_head(s, b, off);
+        if (head_skip(h)) continue;
+        run_block_moves(s, S, b, mv, h, applied, step, true, dynx);
         gsync();
     }
 }

@@ -784,81 +784,130 @@ __device__ __forceinline__ int seed_cavity(WaveLDS& S, int k, int2 q, int qv) {
     return nh + __popcll(mo);
 }
 
-// Widen the star region by the triangles around the star that q destroys,
-// so that the star-only path covers them as well: triangle T_s outside link
-// edge s = (q_s, q_s+1) is (r_s, q_s+1, q_s), and the region's boundary runs
-// q_s, r_s, q_s+1 there.  Taken only if every T_s is a real triangle, its
-// r_s off the link, the r_s distinct (the region stays a simple polygon with no
-// vertex inside), no triangle across a new boundary edge is destroyed by q
-// (the triangles q destroys are connected, so its cavity then stays in the
-// region) and the polygon keeps at most EMK - 1 vertices.  The region's
-// triangles are then retriangulated like a star: DT*(boundary + q) inside
-// it.  cm: link edges whose outside triangle q destroys.  Returns the new
-// vertex count -- the polygon arrays rewritten, the grown triangles' slots
-// after the star's in S.star_slot -- or 0 with the polygon unchanged.
+// Widen the star region by the triangles q destroys around it, level by
+// level, so that the star-only path covers them as well: a destroyed
+// triangle T outside boundary edge (a, b) is (r, b, a), and the boundary
+// then runs a, r, b there; the triangles across (a, r) and (r, b) are read
+// and tested in turn.  Taken only if every grown T is a real triangle whose
+// r is not on the boundary yet, the r of one level are distinct (the region
+// stays a simple polygon with no vertex inside), the polygon keeps at most
+// EMK - 1 vertices and, at the end, no triangle across the boundary is
+// destroyed by q (the triangles q destroys are connected, so its cavity
+// then lies in the region).  The region is then retriangulated like a star:
+// DT*(boundary + q) inside it.  cm: link edges whose outside triangle q
+// destroys.  q_out: q lies outside the star, and the region must come to
+// hold it (in a grown triangle, not at its corner).  Returns the new vertex
+// count -- the polygon arrays rewritten, the grown triangles' slots after
+// the star's in S.star_slot -- or 0 with the star's polygon as it was.
 __device__ __forceinline__ int grow_region(const BlockView& B, WaveLDS& S, int k, int2 q, int qv, uint64_t cm,
-                                           int* used) {
+                                           int* used, bool q_out) {
     const int lane = lane_id();
-    const int k2 = k + __popcll(cm);
-    if (k2 + 1 > EMK) return 0;
-    const bool c = lane < k && ((cm >> lane) & 1ull);
-    int lv = GHOST, orf = 0, oen = 0, r = GHOST, u1 = 0, u2 = 0;
-    int2 lp = make_int2(0, 0), pr = make_int2(0, 0);
-    bool ghost = false;
+    // the star's polygon, put back if the growth stops short
+    int lv0 = GHOST, orf0 = 0, oen0 = 0;
+    int2 lp0 = make_int2(0, 0);
     if (lane < k) {
-        lv = S.link[lane];
-        lp = S.lxy[lane];
-        orf = S.outref[lane];
-        oen = S.out_ent[lane];
+        lv0 = S.link[lane];
+        lp0 = S.lxy[lane];
+        orf0 = S.outref[lane];
+        oen0 = S.out_ent[lane];
     }
-    if (c) {
-        const Tri t = S.trec[oen];
-        const int e = orf & 3;
-        ghost = t.v.z == GHOST;
-        r = vget(t.v, e);
-        pr = cget(t, e);
-        u1 = vget(t.n, (e + 1) % 3);  // across (q_s, r_s)
-        u2 = vget(t.n, (e + 2) % 3);  // across (r_s, q_s+1)
+    int kr = k, nslot = k;
+    bool ok = true, q_in = !q_out;
+    while (cm) {
+        const int k2 = kr + __popcll(cm);
+        if (k2 + 1 > EMK) {
+            ok = false;
+            break;
+        }
+        const bool c = lane < kr && ((cm >> lane) & 1ull);
+        int lv = GHOST, orf = 0, oen = 0, r = GHOST, u1 = 0, u2 = 0;
+        int2 lp = make_int2(0, 0), pr = make_int2(0, 0);
+        bool ghost = false;
+        if (lane < kr) {
+            lv = S.link[lane];
+            lp = S.lxy[lane];
+            orf = S.outref[lane];
+            oen = S.out_ent[lane];
+        }
+        if (c) {
+            const Tri t = S.trec[oen];
+            const int e = orf & 3;
+            ghost = t.v.z == GHOST;
+            r = vget(t.v, e);
+            pr = cget(t, e);
+            u1 = vget(t.n, (e + 1) % 3);  // across (a, r)
+            u2 = vget(t.n, (e + 2) % 3);  // across (r, b)
+        }
+        // grown triangle (r, b, a) on boundary edge (a, b): does it hold q?
+        const int nb = lane + 1 < kr ? lane + 1 : 0;
+        const int2 pb = make_int2(__shfl(lp.x, nb), __shfl(lp.y, nb));
+        const bool qt = c && !ghost && orient(pr, pb, q) >= 0 && orient(pb, lp, q) >= 0 && orient(lp, pr, q) >= 0;
+        q_in = q_in || ballot(qt) != 0;
+        bool clash = (c && ghost) || (qt && same(pr, q));  // the hull changes beyond the region, or q is held
+        for (int m = 0; m < kr; ++m) {
+            const int lm = __builtin_amdgcn_readlane(lv, m), rm = __builtin_amdgcn_readlane(r, m);
+            clash = clash || (c && (lm == r || (m != lane && ((cm >> m) & 1ull) && rm == r)));
+        }
+        if (ballot(clash)) {
+            ok = false;
+            break;
+        }
+        // the triangles across the new boundary edges: lanes 0..31 the first
+        // edge of each grown triangle, lanes 32..63 the second (kr < 32); both
+        // shuffles by every lane (a lane-dependent choice between them would
+        // run each with half the lanes off, and a read from a lane that is off
+        // does not return its value)
+        const int src = lane & 31;
+        const bool want = src < kr && ((cm >> src) & 1ull);
+        const int s1 = __shfl(u1, src), s2 = __shfl(u2, src);
+        const int uref = lane < 32 ? s1 : s2;
+        if (ballot(want && bad_slot(B, uref >> 2))) {
+            ok = false;
+            break;
+        }
+        const int ue = tget(B, S, want, uref >> 2, used);
+        if (ballot(want && ue < 0)) {
+            ok = false;
+            break;
+        }
+        const bool uc = want && conflicts(S.trec[ue], q, qv);
+        const int ue1 = __shfl(ue, src), ue2 = __shfl(ue, src + 32);
+        const int uc1 = __shfl((int)uc, src), uc2 = __shfl((int)uc, src + 32);
+        // a moves to a + (grown edges before it), r right after it
+        const int at = lane + lanes_below(cm);
+        wsync();
+        if (lane < kr) {
+            S.link[at] = lv;
+            S.lxy[at] = lp;
+            S.outref[at] = c ? u1 : orf;
+            S.out_ent[at] = c ? ue1 : oen;
+            S.cav_ent[at] = c ? uc1 : 0;  // the next level's edges
+        }
+        if (c) {
+            S.link[at + 1] = r;
+            S.lxy[at + 1] = pr;
+            S.outref[at + 1] = u2;
+            S.out_ent[at + 1] = ue2;
+            S.cav_ent[at + 1] = uc2;
+            S.star_slot[nslot + lanes_below(cm)] = orf >> 2;
+        }
+        wsync();
+        nslot += __popcll(cm);
+        kr = k2;
+        cm = ballot(lane < kr && S.cav_ent[lane] != 0);
     }
-    if (ballot(c && ghost)) return 0;  // the hull changes beyond the star: no
-    bool clash = false;
-    for (int m = 0; m < k; ++m) {
-        const int lm = __builtin_amdgcn_readlane(lv, m), rm = __builtin_amdgcn_readlane(r, m);
-        clash = clash || (c && (lm == r || (m != lane && ((cm >> m) & 1ull) && rm == r)));
+    ok = ok && q_in;
+    if (!ok) {
+        if (lane < k) {
+            S.link[lane] = lv0;
+            S.lxy[lane] = lp0;
+            S.outref[lane] = orf0;
+            S.out_ent[lane] = oen0;
+        }
+        wsync();
+        return 0;
     }
-    if (ballot(clash)) return 0;
-    // the triangles across the new boundary edges: lanes 0..31 the first
-    // edge of T_s, lanes 32..63 the second (k <= EMK < 32)
-    const int src = lane & 31;
-    const bool want = src < k && ((cm >> src) & 1ull);
-    // both reads by every lane: a lane-dependent choice between two shuffles
-    // would run each with half the lanes off, and a read from a lane that is
-    // off does not return its value
-    const int s1 = __shfl(u1, src), s2 = __shfl(u2, src);
-    const int uref = lane < 32 ? s1 : s2;
-    if (ballot(want && bad_slot(B, uref >> 2))) return 0;
-    const int ue = tget(B, S, want, uref >> 2, used);
-    if (ballot(want && ue < 0)) return 0;
-    if (ballot(want && conflicts(S.trec[ue], q, qv))) return 0;
-    const int ue1 = __shfl(ue, src), ue2 = __shfl(ue, src + 32);
-    // q_s moves to s + (grown edges before s), r_s right after it
-    const int at = lane + lanes_below(cm);
-    wsync();
-    if (lane < k) {
-        S.link[at] = lv;
-        S.lxy[at] = lp;
-        S.outref[at] = c ? u1 : orf;
-        S.out_ent[at] = c ? ue1 : oen;
-    }
-    if (c) {
-        S.link[at + 1] = r;
-        S.lxy[at + 1] = pr;
-        S.outref[at + 1] = u2;
-        S.out_ent[at + 1] = ue2;
-        S.star_slot[k + lanes_below(cm)] = orf >> 2;
-    }
-    wsync();
-    return k2;
+    return kr;
 }
 
 __device__ __forceinline__ int pack3(int i, int j, int l) { return (i << 16) | (j << 8) | l; }
