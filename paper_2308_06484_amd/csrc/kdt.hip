@@ -250,14 +250,16 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     }
     int rc;
     if (fast) {
-        rc = fill_star(B, S, kr, p, q, true, &used, &nvt, st);
+        // applied moves write the region straight to memory; a plan keeps it
+        // in the table
+        rc = fill_star(B, S, kr, p, q, true, &used, &nvt, st, mode == MV_APPLY);
         if (rc != ST_OK) return rc;
         if (mode == MV_PLAN) {
             *plan = MovePlan{k, used, npath, nvt, nvt, q, 1};
             *applied = 2;
             return ST_OK;
         }
-        commit(B, S, used, nvt, nvt);
+        table_drop(S, used);
         if (lane == 0) B.xy[p] = q;
         const long long c4 = wall_clock64();
         if (lane == 0 && st) {

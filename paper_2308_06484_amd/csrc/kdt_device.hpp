@@ -1029,7 +1029,7 @@ __device__ __forceinline__ bool cand_killed_by(const TriCand& c, int m, int vm, 
 }
 
 __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
-                         int* nvt, BlockStats* st) {
+                         int* nvt, BlockStats* st, bool direct = false) {
     const int lane = lane_id();
     if (k < 3) return ST_INTERNAL;
     if (k > TRIPLE_KMAX || (with_q && k + 1 > EMK)) return ST_CAPACITY;
@@ -1077,39 +1077,40 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
                 if (cand_killed_by(c, m, S.link[m], S.lxy[m])) S.cav_ent[si] = 0;
             }
             wsync();
-            for (int x = lane; x < nsurv; x += WAVE) {
-                if (S.cav_ent[x]) {
-                    const int pos = atomicAdd(&S.nhole, 1);
-                    if (pos < KMAX) S.hole_key[pos] = S.emat[x];
-                }
+            int nh = 0;
+            for (int x0 = 0; x0 < nsurv; x0 += WAVE) {
+                const int x = x0 + lane;
+                const bool keep = x < nsurv && S.cav_ent[x];
+                const uint64_t km = ballot(keep);
+                if (keep && nh + lanes_below(km) < KMAX) S.hole_key[nh + lanes_below(km)] = S.emat[x];
+                nh += __popcll(km);
             }
+            if (lane == 0) S.nhole = nh;
             done = true;
         }
     }
-    for (int t0 = 0; t0 < ncand && !done; t0 += WAVE) {
-        TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
-        // link vertex m's id and position sit in lane m's registers
-        for (int m = 0; m < k; ++m) {
-            if (!ballot(c.ok)) break;
-            const int vm = __builtin_amdgcn_readlane(lv, m);
-            const int2 pm = make_int2(__builtin_amdgcn_readlane(lp.x, m), __builtin_amdgcn_readlane(lp.y, m));
-            if (c.ok && cand_killed_by(c, m, vm, pm)) c.ok = false;
+    if (!done) {
+        int nh = 0;
+        for (int t0 = 0; t0 < ncand; t0 += WAVE) {
+            TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
+            // link vertex m's id and position sit in lane m's registers
+            for (int m = 0; m < k; ++m) {
+                if (!ballot(c.ok)) break;
+                const int vm = __builtin_amdgcn_readlane(lv, m);
+                const int2 pm = make_int2(__builtin_amdgcn_readlane(lp.x, m), __builtin_amdgcn_readlane(lp.y, m));
+                if (c.ok && cand_killed_by(c, m, vm, pm)) c.ok = false;
+            }
+            const uint64_t km = ballot(c.ok);
+            if (c.ok && nh + lanes_below(km) < KMAX) S.hole_key[nh + lanes_below(km)] = pack3(c.i, c.j, c.l);
+            nh += __popcll(km);
         }
-        if (c.ok) {
-            const int pos = atomicAdd(&S.nhole, 1);
-            if (pos < KMAX) S.hole_key[pos] = pack3(c.i, c.j, c.l);
-        }
+        if (lane == 0) S.nhole = nh;
     }
     wsync();
+    // the new triangles in the order the candidates were found (the same on
+    // every run: compaction by ballot and prefix count)
     const int nh = S.nhole;
     if (nh != (with_q ? k : k - 2)) return ST_INTERNAL;
-    // deterministic order: sort the keys (rank sort, one lane per key)
-    const int key = lane < nh ? S.hole_key[lane] : 0x7fffffff;
-    int rank = 0;
-#pragma unroll 8
-    for (int m = 0; m < nh; ++m) rank += S.hole_key[m] < key;
-    wsync();
-    if (lane < nh) S.hole_key[rank] = key;
     const int nv = with_q ? k + 1 : k;  // vertices of the polygon (+ q)
     const bool small = nv <= EMK;
     if (small)
@@ -1167,6 +1168,28 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
     if (ballot(herr)) return ST_INTERNAL;
     wsync();
     if (ballot(lane < k && S.edge_tri[lane] < 0)) return ST_INTERNAL;
+    if (with_q && !ballot(has_q)) return ST_INTERNAL;
+    if (direct) {
+        // every check passed: the region's new records, the outside
+        // neighbours' links into it and the incident triangles go straight
+        // to memory (the move ends here; its table holds only records read)
+        if (lane < nh) B.tri[S.star_slot[lane]] = h;
+        if (lane < k) {
+            const int et = S.edge_tri[lane];
+            const int hs = S.star_slot[et >> 2];
+            const int o = S.outref[lane];
+            reinterpret_cast<int*>(&B.tri[o >> 2].n)[o & 3] = hs * 4 + (et & 3);
+            const int v = S.link[lane];
+            if (v != GHOST) B.vtri[v] = hs;
+        }
+        const uint64_t mq = ballot(has_q);
+        if (lane == first_lane(mq)) B.vtri[qv] = S.star_slot[lane];
+        if (lane == 0 && st) {
+            st->tri_touched += nh;
+            st->alg_bytes += 64LL * nh + 4LL * (k + 1);
+        }
+        return ST_OK;
+    }
     // the new triangles into the table, the outside neighbours patched there,
     // incident triangles of the link vertices (and q) queued
     bool mine;
