@@ -220,8 +220,18 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
             on_vertex = ballot(occ) != 0;
             tq = S.outref[first_lane(hm)] >> 2;
         } else {
+            // walk from the triangle beyond the link edge that the ray from
+            // p toward q crosses (any triangle would do; this one is nearest)
+            bool sec = false;
+            if (lane < k) {
+                const int nx = lane + 1 < k ? lane + 1 : 0;
+                sec = S.link[lane] != GHOST && S.link[nx] != GHOST && orient(o, S.lxy[lane], q) >= 0 &&
+                      orient(o, S.lxy[nx], q) < 0;
+            }
+            const uint64_t sm = ballot(sec);
+            const int start = sm ? (S.outref[first_lane(sm)] >> 2) : S.star_slot[0];
             int hit2;
-            tq = walk<false>(B, &S, S.star_slot[0], q, &hit2, &hops, path, &npath);
+            tq = walk<false>(B, &S, start, q, &hit2, &hops, path, &npath);
             if (tq < 0) return ST_INTERNAL;
             on_vertex = hit2 >= 0;
         }
