@@ -400,7 +400,7 @@ __device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s
 // sitting exactly at q (-1 if none).  Returns -1 if the step limit is hit.
 // TABLE: read through the move's write-back table (after changes).
 template <bool TABLE>
-__device__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops,
+__device__ __forceinline__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops,
                     int* path = nullptr, int* npath = nullptr) {
     int cur = start, entry = -1;
     const int limit = 4 * B.ntri + 16;
@@ -609,7 +609,7 @@ __device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int
 // of the deletion, then those of the insertion (no point occurs twice in
 // one list; stores of one wavefront to one address land in program order,
 // so the insertion's value wins), and empty the table.
-__device__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, int nvt) {
+__device__ __forceinline__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, int nvt) {
     const int lane = lane_id();
     for (int u = lane; u < used; u += WAVE) {
         const int h = S.tused[u];
@@ -634,7 +634,7 @@ __device__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, in
 
 // Empty the table entries of the tused list without writing anything back
 // (a planned move that is not committed).
-__device__ void table_drop(WaveLDS& S, int used) {
+__device__ __forceinline__ void table_drop(WaveLDS& S, int used) {
     wsync();
     for (int u = lane_id(); u < used; u += WAVE) {
         const int h = S.tused[u];
@@ -652,7 +652,7 @@ __device__ void table_drop(WaveLDS& S, int used) {
 // and the triangles outside the link edges into the table.  Two walkers
 // turn around p in opposite directions and meet halfway.
 // t0: p's incident triangle.  Returns the degree k (>= 3) or an error code.
-__device__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* used, BlockStats* st) {
+__device__ __forceinline__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* used, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, t0)) return ST_INTERNAL;
     const Tri r0 = load_tri(B.tri + t0);
@@ -1028,7 +1028,7 @@ __device__ __forceinline__ bool cand_killed_by(const TriCand& c, int m, int vm, 
                    : incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, pm, vm) >= 0;
 }
 
-__device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
+__device__ __forceinline__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
                          int* nvt, BlockStats* st, bool direct = false) {
     const int lane = lane_id();
     if (k < 3) return ST_INTERNAL;
@@ -1139,6 +1139,7 @@ __device__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, 
         h.n = make_int4(0, 0, 0, 0);
         h.c01 = make_int4(c0.x, c0.y, c1.x, c1.y);
         h.c2 = v2 != GHOST ? make_int4(c2.x, c2.y, 0, 0) : make_int4(0, 0, 0, 0);
+#pragma unroll
         for (int e = 0; e < 3; ++e) {
             const int u = cs[(e + 1) % 3], w = cs[(e + 2) % 3];
             int nref;
