@@ -283,9 +283,9 @@ def main():
         return dt
 
     # headline: one plain kernel launch per time step; HIP events around the
-    # whole timed region and around every 8th launch (kdt_timing: a pair per
-    # launch would cost the stream ~16 % of its throughput; the steps are
-    # alike, so a uniform sample gives the average launch duration)
+    # whole timed region and, for the average launch duration, pairs each
+    # spanning 8 consecutive launches (kdt_timing; a pair around every launch
+    # would cost the stream ~16 % of its throughput)
     stream = torch.cuda.Stream(device=dev)
     mode = "fused" if args.fused else "step"
     dt = fresh(stream)
@@ -365,10 +365,10 @@ def main():
     touched = s1["tri_touched"] - s0["tri_touched"]
     value = applied / (ms / 1e3)
     n_launch = 1 if mode == "fused" else K  # kernel launches in the timed region
-    avg_launch_s = kern_ms / 1e3 / max(1, launches)  # over the sampled launches
+    avg_launch_s = kern_ms / 1e3 / max(1, launches)  # over the launches the pairs span
     achieved = alg / n_launch / avg_launch_s / 1e9
     log(f"timed {K} steps: {ms:.2f} ms (host {t_host * 1e3:.1f} ms), kernels {kern_ms:.2f} ms over "
-        f"{launches} sampled launches ({avg_launch_s * 1e6:.2f} us each), applied {applied}, blocked {blocked}")
+        f"{launches} launches in event pairs of 8 ({avg_launch_s * 1e6:.2f} us each), applied {applied}, blocked {blocked}")
     khz = max(1, s1["clock_khz"])
     phases = {ph: (s1["t_" + ph] - s0["t_" + ph]) / khz * 1e3 / max(1, applied)
               for ph in ("star", "locate", "hole", "insert")}
@@ -420,7 +420,7 @@ def main():
             "kernel": "k_run_fused" if args.fused else "k_step",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg / n_launch,
-            "sampled_launches": launches,
+            "timed_launches": launches,
         },
     }
     if not args.no_cpu_baseline:

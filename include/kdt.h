@@ -189,13 +189,15 @@ int kdt_stats(kdt_ctx* ctx, kdt_stats_t* out);
 /* Per-block status (synchronises): host int32 [n_blocks], 0 or KDT_E_*. */
 int kdt_block_status(kdt_ctx* ctx, int32_t* host_status);
 
-/* Kernel timing.  With enable = P > 0, kdt_run and kdt_step record a HIP
- * event pair on the context's stream around every P-th time step they launch
- * (P = 1: every one; a pair costs the stream a few microseconds, so a larger
- * P samples the steps with less disturbance); kdt_timing_read waits for them
- * and returns the summed time (ms) and the number of timed steps since
- * timing was last enabled.  Recording stops (and the pairs are released)
- * when enable == 0; enable < 0 is KDT_E_ARG. */
+/* Kernel timing.  With enable = P > 0, kdt_run and kdt_step record HIP
+ * event pairs on the context's stream, each spanning a run of P consecutive
+ * time-step launches (P = 1: one pair around every launch; a pair costs the
+ * stream a few microseconds, so a larger P disturbs the steps less and
+ * measures the stream's time per launch, gaps between launches included);
+ * kdt_timing_read closes a run cut short, waits for the pairs and returns
+ * their summed time (ms) and the number of launches they span since timing
+ * was last enabled.  Recording stops (and the pairs are released) when
+ * enable == 0; enable < 0 is KDT_E_ARG. */
 int kdt_timing(kdt_ctx* ctx, int32_t enable);
 int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -1517,8 +1517,9 @@ struct kdt_ctx {
     long long step_count = 0;  // time steps launched so far (log index)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
-    int timing_period = 1;      // record every timing_period-th launch
-    long long timing_count = 0;  // launches seen since timing was enabled
+    int timing_period = 1;        // launches one event pair spans
+    long long timing_count = 0;   // launches covered by closed pairs since timing was enabled
+    int timing_open = 0;          // launches in the open pair (0: none open)
     int pb_lds = 0;         // dynamic LDS of k_build_blocks at init
     int pb_lds_follow = 0;  // ... after a step, for the blocks too large for the step kernels
     bool follow = false;    // some block is too large to be rebuilt inside the step kernels
@@ -1542,24 +1543,31 @@ int check_hip(kdt_ctx* c, hipError_t e) {
     return KDT_E_DEVICE;
 }
 
-// Event pair around one launch when timing is on.
+// When timing is on, one event pair spans each run of timing_period
+// consecutive launches: the first launch of a run records the start, the
+// last one the end.
 hipEvent_t timing_begin(kdt_ctx* c) {
     if (!c->timing) return nullptr;
-    if (c->timing_count++ % c->timing_period != 0) return nullptr;
-    if (c->ev_used == c->ev.size()) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess) return nullptr;
-        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
-        c->ev.push_back({a, b});
+    if (c->timing_open == 0) {
+        if (c->ev_used == c->ev.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return nullptr;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
+            c->ev.push_back({a, b});
+        }
+        (void)hipEventRecord(c->ev[c->ev_used].first, c->stream);
     }
-    hipEvent_t a = c->ev[c->ev_used].first;
-    (void)hipEventRecord(a, c->stream);
-    return a;
+    return c->ev[c->ev_used].first;
+}
+void timing_close(kdt_ctx* c) {
+    (void)hipEventRecord(c->ev[c->ev_used].second, c->stream);
+    c->ev_used++;
+    c->timing_count += c->timing_open;
+    c->timing_open = 0;
 }
 void timing_end(kdt_ctx* c, hipEvent_t a) {
     if (!a) return;
-    (void)hipEventRecord(c->ev[c->ev_used].second, c->stream);
-    c->ev_used++;
+    if (++c->timing_open >= c->timing_period) timing_close(c);
 }
 void release_events(kdt_ctx* c) {
     for (auto& p : c->ev) {
@@ -2189,12 +2197,14 @@ int kdt_timing(kdt_ctx* c, int32_t enable) {
     c->timing = enable != 0;
     c->timing_period = enable > 0 ? enable : 1;
     c->timing_count = 0;
+    c->timing_open = 0;
     if (!c->timing) release_events(c);
     return KDT_OK;
 }
 
 int kdt_timing_read(kdt_ctx* c, double* total_ms, int64_t* launches) {
     if (!c || !total_ms || !launches) return KDT_E_ARG;
+    if (c->timing_open > 0) timing_close(c);  // a run cut short ends here
     if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
     double tot = 0.0;
     for (size_t i = 0; i < c->ev_used; ++i) {
@@ -2203,7 +2213,7 @@ int kdt_timing_read(kdt_ctx* c, double* total_ms, int64_t* launches) {
         tot += ms;
     }
     *total_ms = tot;
-    *launches = (int64_t)c->ev_used;
+    *launches = (int64_t)c->timing_count;
     return KDT_OK;
 }
 

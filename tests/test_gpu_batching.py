@@ -98,3 +98,23 @@ def test_rebuild_policy_in_every_launch_form(uneven):
         assert np.array_equal(got[1], oracle.xy), (mode, graph)
         assert np.array_equal(got[2].astype(bool), app), (mode, graph)
         assert got[3]["errors"] == 0 and got[3]["rebuilt"] > 0
+
+
+def test_timing_pairs_span_runs_of_launches(uneven):
+    """kdt_timing(P): event pairs over runs of P consecutive launches; a run
+    cut short is closed by the read, and every launch is counted once."""
+    from paper_2308_06484_amd.kdt import KineticDT
+    w = uneven
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+        mv = torch.from_numpy(w["mv"]).to(DEV)
+        off = torch.from_numpy(w["mv_off"]).to(DEV)
+        T = w["mv_off"].shape[0]
+        for period in (1, 4, T + 3):
+            dt.timing(True, period=period)
+            dt.run(mv, off)
+            ms, n = dt.timing_read()
+            assert n == T and ms > 0, (period, n, ms)
+        dt.timing(False)
+        dt.close()
