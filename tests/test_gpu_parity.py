@@ -128,6 +128,20 @@ def test_grid1024_blocks_subset_every_step():
     run_compare(s)
 
 
+def test_every_move_path_every_step():
+    """Moves of 1..48 units among points 16 units apart: targets in the star,
+    in a surrounding triangle, in a region grown over several levels, and
+    beyond it (walk + Bowyer-Watson), hull points included; bit-exact after
+    every step, and each path is taken."""
+    _say("grid 6x6 cells x 256 points on 256^2, moves of 1..48 units, 60 steps")
+    w = W.grid1024(seed=11, steps=60, cells=6, per_block=256, cell=256)
+    rng = np.random.default_rng(11)
+    w["mv"][:, 2] = rng.integers(1, 49, size=len(w["mv"]))
+    dt, ref, st = run_compare(w)
+    assert 0 < st["fast"] < st["applied"], st   # both the star-only and the general path
+    assert st["walk_sum"] > 0 and st["cavity_sum"] > 0, st
+
+
 def test_dense_lattice_degenerate_moves():
     """Blocks that are nearly full lattices: every move lands on a cocircular
     or collinear configuration, many are blocked, hull points move."""
