@@ -159,7 +159,7 @@ def other_workload(args):
         w = W.uneven4096(seed=args.seed, steps=args.other_steps or 500)
     T = w["mv_off"].shape[0]
     forms = [("per_step", "step", False, None), ("graph_per_step", "step", True, None),
-             ("persistent_lpt", "persistent", False, 4), ("graph_persistent_lpt", "persistent", True, 4),
+             ("persistent_lpt", "persistent", False, None), ("graph_persistent_lpt", "persistent", True, None),
              ("fused", "fused", False, None)]
     res = {}
     if name == "uneven4096":
@@ -309,8 +309,8 @@ def main():
     # the other launch forms on fresh contexts, same stream of moves
     variants = {}
     for name, vmode, graph, per_cu in [] if args.no_variants else [("graph_per_step", "step", True, None),
-                                       ("persistent_lpt", "persistent", False, 4),
-                                       ("graph_persistent_lpt", "persistent", True, 4),
+                                       ("persistent_lpt", "persistent", False, None),
+                                       ("graph_persistent_lpt", "persistent", True, None),
                                        ("fused", "fused", False, None)]:
         d2 = fresh(stream)
         if per_cu:

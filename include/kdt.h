@@ -139,7 +139,8 @@ int kdt_step(kdt_ctx* ctx);
 int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
             int32_t n_steps, int8_t* applied, int32_t flags);
 
-/* Workgroups per compute unit of the persistent launch (1..64, default 4). */
+/* Workgroups per compute unit of the persistent launch (1..64, default 4;
+ * the LDS of an MI355X compute unit holds 5 step workgroups). */
 int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
 
 /* The same n_steps steps captured once as a HIP graph and replayed by

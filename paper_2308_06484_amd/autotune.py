@@ -2,7 +2,7 @@
 
 Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
 one kernel per step, the persistent launch with 1..8 workgroups per
-compute unit, each either launched step by step or captured as a HIP graph,
+compute unit (the LDS of an MI355X compute unit holds 5), each either launched step by step or captured as a HIP graph,
 and the fused multi-step launch.  Every candidate computes the same
 triangulations (tests check this bit for bit), so the choice only changes
 speed.  Each candidate is timed on its own fresh context built from a
@@ -23,7 +23,7 @@ from .kdt import KineticDT
 DEFAULT_CANDIDATES = (
     {"mode": "step", "graph": False},
     {"mode": "step", "graph": True},
-    *({"mode": "persistent", "graph": g, "per_cu": pc} for pc in (1, 2, 4, 8) for g in (False, True)),
+    *({"mode": "persistent", "graph": g, "per_cu": pc} for pc in (1, 2, 4, 5, 8) for g in (False, True)),
     {"mode": "fused", "graph": False},
 )
 

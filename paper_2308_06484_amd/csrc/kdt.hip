@@ -396,10 +396,12 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
     const int4 fr = s.frame[b];
     const int lane = lane_id();
     const bool hashed = B.n + (m1 - m0) <= PH_CAP / 2;
-    static_assert(sizeof(unsigned long long) * PH_CAP <= offsetof(WaveLDS, st), "position hash overlaps the counters");
+    static_assert(sizeof(unsigned long long) * PH_CAP <= DRY_V_OFF, "position hash overlaps the moved points");
     unsigned long long* T = reinterpret_cast<unsigned long long*>(&S);
+    int* dry_v = dry_v_of(S);
+    int2* dry_q = dry_q_of(S);
     if (hashed) ph_build(T, B.xy, B.n);
-    int nmoved = 0;  // wave-uniform; S.dry_v / S.dry_q: moved points and their new places
+    int nmoved = 0;  // wave-uniform; dry_v / dry_q: moved points and their new places
     for (int c0 = m0; c0 < m1; c0 += WAVE) {
         // the chunk's moves and their points' places at the start of the step, one per lane
         kdt_move_t r;
@@ -419,10 +421,10 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
             int2 o = make_int2(__shfl(o0.x, j), __shfl(o0.y, j));
             int prev = -1;  // p's entry in the moved list
             for (int i = lane; i < nmoved; i += WAVE)
-                if (S.dry_v[i] == p) prev = i;
+                if (dry_v[i] == p) prev = i;
             const uint64_t mp = ballot(prev >= 0);
             prev = mp ? __shfl(prev, first_lane(mp)) : -1;
-            if (prev >= 0) o = S.dry_q[prev];
+            if (prev >= 0) o = dry_q[prev];
             long long qx = o.x, qy = o.y;
             if (dir == 0) qx += dist;
             else if (dir == 1) qx -= dist;
@@ -434,7 +436,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
                 ok = ph_find(T, ph_key(q)) < 0;
             } else if (ok) {
                 bool held = false;
-                for (int i = lane; i < nmoved; i += WAVE) held |= same(S.dry_q[i], q);
+                for (int i = lane; i < nmoved; i += WAVE) held |= same(dry_q[i], q);
                 ok = !ballot(held);
                 if (ok) {
                     // a point of the old triangulation at q that has not moved away
@@ -443,7 +445,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
                     if (tq < 0) return ST_INTERNAL;
                     if (hit >= 0) {
                         bool gone = false;
-                        for (int i = lane; i < nmoved; i += WAVE) gone |= S.dry_v[i] == hit;
+                        for (int i = lane; i < nmoved; i += WAVE) gone |= dry_v[i] == hit;
                         ok = ballot(gone) != 0;
                     }
                 }
@@ -459,8 +461,8 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
                     ph_insert(T, ph_key(q));
                 }
                 if (lane == 0) {
-                    S.dry_v[slot] = p;
-                    S.dry_q[slot] = q;
+                    dry_v[slot] = p;
+                    dry_q[slot] = q;
                     st->applied += 1;
                 }
                 if (prev < 0) ++nmoved;
@@ -471,7 +473,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
             if (applied && lane == 0) applied[m] = ok ? 1 : 0;
         }
     }
-    for (int i = lane; i < nmoved; i += WAVE) B.xy[S.dry_v[i]] = S.dry_q[i];
+    for (int i = lane; i < nmoved; i += WAVE) B.xy[dry_v[i]] = dry_q[i];
     gsync();
     if (lane == 0) {
         st->rebuilt += 1;
@@ -485,7 +487,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
         return ST_OK;
     }
     // the attempts overlay the wavefront's repair scratch, unused here
-    static_assert(offsetof(WaveLDS, st) >= sizeof(int) * WAVE * ATT_B_INTS, "attempts overlap the counters");
+    static_assert(PB_LDS_OFF >= (int)sizeof(int) * WAVE * ATT_B_INTS, "attempts overlap the build's counters");
     PBMem M;
     M.att = reinterpret_cast<int*>(&S);
     if (in_lds) {
@@ -499,7 +501,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
         M.cown = s.owner + s.tri_off[b];
         M.bown = s.own2 + s.tri_off[b];
     }
-    const int rc = pbuild_block(B, s.order + s.pt_off[b], M, S.pb_lds);
+    const int rc = pbuild_block(B, s.order + s.pt_off[b], M, pb_lds_of(S));
     table_clear(S);
     return rc;
 }
@@ -1514,6 +1516,7 @@ struct kdt_ctx {
     int sticky;
     int device = 0;
     int cus = 256;
+    int wpc = 4;  // step workgroups (one wavefront each) that fit a compute unit's LDS
     long long step_count = 0;  // time steps launched so far (log index)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
@@ -1576,6 +1579,14 @@ void release_events(kdt_ctx* c) {
     }
     c->ev.clear();
     c->ev_used = 0;
+}
+
+// Step workgroups per compute unit that the LDS holds (each takes a WaveLDS).
+int step_wg_per_cu(int dev) {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds < 1)
+        lds = 160 * 1024;
+    return std::max(1, lds / (int)sizeof(WaveLDS));
 }
 
 // Dynamic LDS for the block build: PB_LDS_BYTES if the device lets a
@@ -1835,6 +1846,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
         c->cus = cus;
+        c->wpc = step_wg_per_cu(dev);
     }
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
     c->pb_lds = (int)(pb_fixed_lds() + max_block_need(c, 0, pb_lds_bytes() - pb_fixed_lds()));
@@ -2292,6 +2304,7 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
             c->cus = cus;
+        c->wpc = step_wg_per_cu(c->device);
     }
     c->pt_off = {0, (long long)n};
     c->tri_off = {0, 2 * (long long)n - 2};
@@ -2385,7 +2398,7 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
         k_g_classify<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M);
         const int parts = std::min(M, std::min(8 * c->cus, G_PART_MAX));
         for (int r = 0; r < G_ROUNDS; ++r) {
-            k_g_plan<<<std::min(M, 4 * c->cus), WAVE, 0, st>>>(c->dev, c->g, mv, M, r);
+            k_g_plan<<<std::min(M, c->wpc * c->cus), WAVE, 0, st>>>(c->dev, c->g, mv, M, r);
             k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r, r == G_ROUNDS - 1 ? 1 : 0, ap);
         }
         k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap, parts);

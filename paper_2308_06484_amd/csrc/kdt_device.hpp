@@ -123,12 +123,23 @@ struct WaveLDS {
     int nhole, pad[3];
     int wpath[WPMAX];  // slots a planned move's walks read (global mode)
     BlockStats st;  // the block's counters while its wavefront works on it
-    // rebuild branch: points moved this step and their new places, and the
-    // parallel build's counters and deferred points
-    int dry_v[DRYMAX];
-    int2 dry_q[DRYMAX];
-    int pb_lds[4 + 256];
 };
+// The rebuild branch does not use the repair scratch (everything before
+// `st`) and lays its own arrays over it, so they cost no LDS of their own
+// (4 KB less lets five step wavefronts share a compute unit instead of four):
+// the dry run's position hash (PH_CAP 8-byte entries) at 0, then the points
+// moved this step and their new places; the parallel build's attempts at 0
+// (the dry run is over by then) and its counters and deferred points after
+// the moved-point arrays.
+constexpr int DRY_HASH_BYTES = 2048 * 8;
+constexpr int DRY_V_OFF = DRY_HASH_BYTES;
+constexpr int DRY_Q_OFF = DRY_V_OFF + 4 * DRYMAX;
+constexpr int PB_LDS_OFF = DRY_Q_OFF + 8 * DRYMAX;
+constexpr int PB_LDS_INTS = 4 + 256;
+static_assert(PB_LDS_OFF + 4 * PB_LDS_INTS <= (int)offsetof(WaveLDS, st), "rebuild arrays overlap the counters");
+__device__ __forceinline__ int* dry_v_of(WaveLDS& S) { return reinterpret_cast<int*>(reinterpret_cast<char*>(&S) + DRY_V_OFF); }
+__device__ __forceinline__ int2* dry_q_of(WaveLDS& S) { return reinterpret_cast<int2*>(reinterpret_cast<char*>(&S) + DRY_Q_OFF); }
+__device__ __forceinline__ int* pb_lds_of(WaveLDS& S) { return reinterpret_cast<int*>(reinterpret_cast<char*>(&S) + PB_LDS_OFF); }
 
 // ---------------------------------------------------------------- wave ops
 
