@@ -142,6 +142,32 @@ def test_every_move_path_every_step():
     assert st["walk_sum"] > 0 and st["cavity_sum"] > 0, st
 
 
+def test_hull_points_move_out_and_in():
+    """Small blocks clustered in the middle of wide frames: about a third of
+    the points are hull vertices, and moves of up to 24 units push them out
+    past the hull or pull them in (ghost candidates with the new point,
+    hull edges that appear and vanish), bit-exact after every step."""
+    _say("24 blocks x 48 clustered points, frames 1024 wide, moves of 1..24 units, 80 steps")
+    rng = np.random.default_rng(19)
+    B, n, T = 24, 48, 80
+    xy, frame = [], []
+    for b in range(B):
+        x0 = (b % 6) * 1024
+        y0 = (b // 6) * 1024
+        frame.append((x0, y0, x0 + 1024, y0 + 1024))
+        cells = rng.choice(64 * 64, size=n, replace=False)
+        xy.append(np.stack([x0 + 480 + cells % 64, y0 + 480 + cells // 64], 1))
+    mv = np.zeros((T * B, 4), np.int32)
+    mv[:, 0] = rng.integers(0, n, size=T * B)
+    mv[:, 1] = rng.integers(0, 4, size=T * B)
+    mv[:, 2] = rng.integers(1, 25, size=T * B)
+    w = dict(xy=np.concatenate(xy).astype(np.int32), pt_off=np.arange(B + 1, dtype=np.int64) * n,
+             frame=np.array(frame, np.int32), mv=mv,
+             mv_off=(np.arange(T)[:, None] * B + np.arange(B + 1)[None, :]).astype(np.int32))
+    dt, ref, st = run_compare(w)
+    assert st["fast"] > 0 and st["applied"] > 0.8 * T * B, st
+
+
 def test_dense_lattice_degenerate_moves():
     """Blocks that are nearly full lattices: every move lands on a cocircular
     or collinear configuration, many are blocked, hull points move."""
