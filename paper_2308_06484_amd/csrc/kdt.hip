@@ -854,19 +854,21 @@ __global__ void k_g_prep(DevState s, GlobalDev g, const kdt_move_t* __restrict__
                          int8_t* applied) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
+    // loads and the hash insertions (which wait for their old values) come
+    // before this thread's plain stores: a load issued after a store waits
+    // for that store
     const kdt_move_t r = mv[m];
+    const bool bad = r.point < 0 || r.point >= (int)s.pt_off[1] || r.dir < 0 || r.dir > 3 || r.dist < 1;
+    if (!bad) {
+        const int2 o = s.xy[r.point];
+        int2 q;
+        cell_add(g, cell_key(o));
+        if (move_target(o, r.dir, r.dist, s.frame[0], &q)) cell_add(g, cell_key(q));
+    }
     g.rsn[m] = 0;
     if (applied) applied[m] = 0;
-    if (r.point < 0 || r.point >= (int)s.pt_off[1] || r.dir < 0 || r.dir > 3 || r.dist < 1) {
-        g.mstate[m] = MS_DONE;
-        fail_global(s, ST_ARG);
-        return;
-    }
-    g.mstate[m] = MS_PEND;
-    const int2 o = s.xy[r.point];
-    int2 q;
-    cell_add(g, cell_key(o));
-    if (move_target(o, r.dir, r.dist, s.frame[0], &q)) cell_add(g, cell_key(q));
+    g.mstate[m] = bad ? MS_DONE : MS_PEND;
+    if (bad) fail_global(s, ST_ARG);
 }
 
 __global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restrict__ mv, int M) {
@@ -1096,15 +1098,23 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
         }
         if (lane == 0) atomicAdd(&g.gstats[KDT_GSTAT_SERIAL], (unsigned long long)cnt);
     }
-    // the commit rounds' per-workgroup counters
+    // the commit rounds' per-workgroup counters: all read first, then
+    // cleared (a load issued after a store waits for that store, so
+    // interleaving them would cost a round trip per group of 64)
     long long a = 0, f = 0, b = 0, t = 0;
+#pragma unroll 4
     for (int w = lane; w < parts; w += WAVE) {
-        unsigned long long* pp = g.part + 4 * w;
-        a += (long long)pp[0];
-        f += (long long)pp[1];
-        b += (long long)pp[2];
-        t += (long long)pp[3];
-        pp[0] = pp[1] = pp[2] = pp[3] = 0;
+        const ulonglong2 p01 = *reinterpret_cast<const ulonglong2*>(g.part + 4 * w);
+        const ulonglong2 p23 = *reinterpret_cast<const ulonglong2*>(g.part + 4 * w + 2);
+        a += (long long)p01.x;
+        f += (long long)p01.y;
+        b += (long long)p23.x;
+        t += (long long)p23.y;
+    }
+    wsync();
+    for (int w = lane; w < parts; w += WAVE) {
+        *reinterpret_cast<ulonglong2*>(g.part + 4 * w) = make_ulonglong2(0ull, 0ull);
+        *reinterpret_cast<ulonglong2*>(g.part + 4 * w + 2) = make_ulonglong2(0ull, 0ull);
     }
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
