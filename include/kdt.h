@@ -127,7 +127,12 @@ int kdt_step(kdt_ctx* ctx);
  *   flags     KDT_RUN_* below
  * KDT_RUN_PER_STEP (0) launches one kernel per step.  KDT_RUN_FUSED runs
  * all steps of a block in one persistent launch; blocks are independent, so
- * the result is the same. */
+ * the result is the same.  A move beyond the repair path's fixed capacities
+ * (a point of degree above 64, or a cavity or write-back table larger than
+ * its on-chip arrays) changes nothing and sends its block through the
+ * rebuild branch for the rest of the step (same result, slower); only a
+ * block with more than 256 moves left in that step then fails with
+ * KDT_E_CAPACITY. */
 #define KDT_RUN_PER_STEP 0
 #define KDT_RUN_FUSED 1
 #define KDT_RUN_PERSISTENT 2

@@ -591,6 +591,16 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
             int app = 0;
             if (m > m0) gsync();  // the previous move's stores are visible
             rc = apply_move(B, S, mv[m], fr, &S.st, &app);
+            if (rc == ST_CAPACITY) {
+                // beyond the move path's fixed capacities (a star of more than
+                // KMAX triangles, a table or a cavity larger than its LDS
+                // arrays): the move changed nothing, and the block takes the
+                // rebuild branch for its remaining moves of the step, building
+                // here (the same DT* from the same positions)
+                table_clear(S);
+                rc = dry_run_and_rebuild(s, S, b, mv, m, m1, applied, &S.st, false, dynx);
+                break;
+            }
             if (applied && lane == 0) applied[m] = (int8_t)app;
             if (rc != ST_OK) break;
         }

@@ -168,6 +168,48 @@ def test_hull_points_move_out_and_in():
     assert st["fast"] > 0 and st["applied"] > 0.8 * T * B, st
 
 
+def _circle_block(seed, cx, cy, extra):
+    """The 108 lattice points on the circle of radius 1105 = 5*13*17 around
+    (cx, cy), the centre itself, and `extra` uniform points outside it."""
+    r2 = 1105 * 1105
+    ring = [(cx + x, cy + y) for x in range(-1105, 1106) for y in (int(round((r2 - x * x) ** 0.5)),)
+            if y * y + x * x == r2 for y in ((y, -y) if y else (0,))]
+    assert len(ring) == 108
+    rng = np.random.default_rng(seed)
+    pts = set(ring) | {(cx, cy)}
+    out = []
+    while len(out) < extra:
+        p = (int(rng.integers(cx - 2000, cx + 2000)), int(rng.integers(cy - 2000, cy + 2000)))
+        if (p[0] - cx) ** 2 + (p[1] - cy) ** 2 > (1105 + 40) ** 2 and p not in pts:
+            pts.add(p)
+            out.append(p)
+    return np.array([(cx, cy)] + ring + out, np.int32)
+
+
+def test_capacity_overflow_takes_the_rebuild_branch():
+    """A centre point of degree 108 (cocircular lattice points around it) is
+    beyond the repair path's star capacity: moving it sends its block through
+    the rebuild branch, with the same DT* as the oracle's after every step;
+    the other block and the other moves are repaired as usual."""
+    _say("2 blocks with 108 cocircular points around a centre, the centre moves")
+    a = _circle_block(1, 2048, 2048, 120)
+    b = _circle_block(2, 6144, 2048, 120)
+    xy = np.concatenate([a, b])
+    n = len(a)
+    T = 6
+    mv = np.zeros((2 * T, 4), np.int32)
+    rng = np.random.default_rng(3)
+    for t in range(T):
+        # block 0 moves its centre (local id 0) on even steps, another point on odd ones
+        mv[2 * t] = (0 if t % 2 == 0 else int(rng.integers(1, n)), int(rng.integers(0, 4)), 1 + t, 0)
+        mv[2 * t + 1] = (int(rng.integers(1, n)), int(rng.integers(0, 4)), 3, 0)
+    w = dict(xy=xy, pt_off=np.array([0, n, 2 * n], np.int64),
+             frame=np.array([[0, 0, 4096, 4096], [4096, 0, 8192, 4096]], np.int32), mv=mv,
+             mv_off=(np.arange(T)[:, None] * 2 + np.arange(3)[None, :]).astype(np.int32))
+    dt, ref, st = run_compare(w)
+    assert st["rebuilt"] >= 1, st
+
+
 def test_dense_lattice_degenerate_moves():
     """Blocks that are nearly full lattices: every move lands on a cocircular
     or collinear configuration, many are blocked, hull points move."""
