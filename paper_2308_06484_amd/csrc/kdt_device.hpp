@@ -45,6 +45,7 @@ constexpr int WAVE = 64;
 constexpr int KMAX = 64;         // largest degree of a deleted vertex
 constexpr int TRIPLE_KMAX = 40;  // link-triple retriangulation limit
 constexpr int HT = 256;          // write-back table entries (power of two)
+static_assert(HT <= 256, "table entries are listed as bytes");
 constexpr int HT_LIMIT = 200;    // entries a move may use (keeps probe chains short)
 constexpr int CMAX = 160;        // largest Bowyer-Watson cavity
 constexpr int BMAX = CMAX + 2;   // cavity boundary
@@ -106,7 +107,7 @@ struct WaveLDS {
     int tkey[HT];  // slot, or -1
     int tflag[HT];
     Tri trec[HT];
-    int tused[HT];  // entries in use, in claim order
+    uint8_t tused[HT];  // entries in use, in claim order (HT <= 256)
     // the directed edges (u, w) of the hole triangles: 4 * triangle + edge
     int emat[EMK * EMK];
     // Bowyer-Watson cavity: table entries, boundary edges (a, b) with the
