@@ -283,8 +283,9 @@ def test_staged_moves_api():
 
 def test_grid1024_full_size_bench_config():
     """The benchmark's workload at full size (1024 blocks x 1024 points,
-    1000 steps, one launch per step): sampled blocks against the oracle,
-    the certificate on them, positions against the oracle's move rule."""
+    1000 steps, one launch per step): positions and applied flags against
+    the oracle's move rule, every block's DT* against the oracle's after the
+    last step, and the certificate on sampled blocks."""
     _say("grid1024 full: generating")
     w = W.grid1024(seed=1)
     KineticDT = _kdt()
@@ -308,6 +309,7 @@ def test_grid1024_full_size_bench_config():
         assert np.array_equal(canon, wt), f"block {b}"
         certificate.check(ref.xy[w["pt_off"][b]:w["pt_off"][b + 1]],
                           np.arange(w["pt_off"][b], w["pt_off"][b + 1]), seg)
-    # every block: 2n - 2 - h triangles
+    # every block, after the 1000 steps
+    assert np.array_equal(dt.query_canonical(), ref.all_dt(16)), "DT* differs after 1000 steps"
     st = dt.stats()
     assert st["errors"] == 0 and st["applied"] == int(app.sum())
