@@ -70,3 +70,36 @@ def test_multi2048_full_size_repair_and_rebuild():
         if policy == "rebuild":
             assert st["rebuilt"] > 0
         dt.close()
+
+
+@pytest.mark.timeout(900)
+def test_selector_mix_full_size_mlp_and_threshold():
+    """The selection workload at full size (512 blocks, half of them with most
+    points moving far every step): the network (random weights: any choice
+    of branch must give the same DT*) and the threshold rule both take both
+    branches; every block against the oracle after the last step."""
+    _say("selector_mix full size, 12 steps")
+    from paper_2308_06484_amd.kdt import MLP_PARAMS
+    w = W.selector_mix(seed=1)
+    ref, app = _oracle(w)
+    want = ref.all_dt(16)
+    g = torch.Generator().manual_seed(5)
+    wts = ((torch.rand(MLP_PARAMS, generator=g) - 0.5) * 0.5).to(DEV)
+    for policy, kw in (("mlp", dict(mlp_w=wts)), ("threshold", dict(tau=50.0))):
+        _say(f"selector_mix full size: policy {policy}")
+        from paper_2308_06484_amd.kdt import KineticDT
+        dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+        dt.set_policy(policy, **kw)
+        mv = torch.from_numpy(w["mv"]).to(DEV)
+        off = torch.from_numpy(np.ascontiguousarray(w["mv_off"])).to(DEV)
+        applied = torch.zeros(w["mv"].shape[0], dtype=torch.int8, device=DEV)
+        dt.run(mv, off, applied=applied)
+        dt.sync()
+        assert np.array_equal(applied.cpu().numpy().astype(bool), app), policy
+        assert np.array_equal(dt.positions(), ref.xy), policy
+        assert np.array_equal(dt.query_canonical(), want), policy
+        st = dt.stats()
+        assert st["errors"] == 0 and st["applied"] == int(app.sum())
+        if policy == "threshold":
+            assert 0 < st["rebuilt"] < 12 * 512, st
+        dt.close()
