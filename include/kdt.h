@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 #define KDT_OK 0
+#define KDT_BLOCKED 1       /* per-move status: the move rule blocked the move (a no-op, not an error) */
 #define KDT_E_ARG (-1)      /* bad argument (null pointer, size, index, dir, dist) */
 #define KDT_E_RANGE (-2)    /* coordinate outside [0, 2^24) or outside its frame */
 #define KDT_E_DUP (-3)      /* two points of a block on one lattice cell */
@@ -54,9 +55,13 @@ extern "C" {
 #define KDT_E_STATE (-7)    /* call out of order (e.g. use after an error) */
 #define KDT_E_INTERNAL (-8) /* a device-side invariant check failed */
 
-/* One move: `point` is the LOCAL index of the point in its block
- * (global id - block_off[block]); the block is implied by where the record
- * sits in a step's per-block offsets.  16 bytes. */
+/* One move (Sec. III, "movepoint"; Lemma 1 of Sec. V: one of four
+ * directions): `point` is the LOCAL index of the point in its block
+ * (global id - block_off[block]) -- the same convention for every per-block
+ * call (kdt_move, kdt_moves, kdt_run); the block is implied by where the
+ * record sits in a step's per-block offsets (kdt_run) or given beside it
+ * (kdt_move, kdt_moves).  The global mode (kdt_run_global) takes global ids,
+ * since it has one block.  16 bytes. */
 typedef struct kdt_move_s {
     int32_t point;
     int32_t dir;
@@ -91,6 +96,37 @@ typedef struct kdt_stats_t {
 
 typedef struct kdt_ctx kdt_ctx;
 
+/* Library-side partition (Sec. III, "Data structure"; Sec. IV,
+ * Quad-treeDvision): the smallest square covering the points -- lower-left
+ * corner at the coordinate minima, side rounded up to a power of two so
+ * that halving keeps lattice cells whole -- is cut into four equal squares,
+ * recursively.
+ *   KDT_PART_GRID      param = partition count P, a power of four (1 .. 4^12):
+ *                      every square cut log4(P) times; blocks = the cells
+ *                      that hold a point, row by row (y, then x)
+ *   KDT_PART_QUADTREE  param = threshold (>= 4): a square holding more than
+ *                      `param` points is cut into its four quarters, quarters
+ *                      holding no point are dropped; a square whose cut would
+ *                      leave a quarter with fewer than 4 points or all of
+ *                      them on one line stays whole (a block needs a
+ *                      triangulation); blocks = the leaves, depth first,
+ *                      quarters in the order (low x, low y), (high x, low y),
+ *                      (low x, high y), (high x, high y)
+ * Input: xy host int32 [n][2] in [0, 2^24), distinct.  Output (host):
+ *   perm       int64 [n]: row i of the partitioned set is input point
+ *              perm[i]; a block's points keep their input order
+ *   block_off  int64 [cap_blocks + 1], frames int32 [cap_blocks][4]: the
+ *              arguments kdt_init takes (a frame is the block's square,
+ *              half-open, clipped to [0, 2^24))
+ *   n_blocks   the number of blocks (written even when it exceeds
+ *              cap_blocks: then KDT_E_CAPACITY and nothing else is written)
+ * KDT_E_RANGE / KDT_E_DUP for bad points, KDT_E_ARG for a bad scheme or
+ * param.  Pure host computation; no context needed. */
+#define KDT_PART_GRID 0
+#define KDT_PART_QUADTREE 1
+int kdt_partition(const int32_t* xy, int64_t n, int32_t scheme, int64_t param, int64_t* perm,
+                  int64_t* block_off, int32_t* frames, int32_t cap_blocks, int32_t* n_blocks);
+
 /* Size in bytes of the device workspace kdt_init needs for n points in
  * n_blocks blocks with the given host block offsets (n_blocks + 1 entries,
  * block_off[0] = 0, block_off[n_blocks] = n) and room to stage up to
@@ -111,15 +147,36 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
              const int64_t* block_off, const int32_t* frames, int32_t max_staged,
              void* dev_ws, size_t ws_bytes, void* stream);
 
-/* Stage one move of the current step (host call; nothing runs yet).
- * `point` is the GLOBAL id; it must belong to `block`. */
+/* Stage one move of the current step (host call; nothing runs yet): block
+ * i's chosen point (Sec. III, "movepoint_i") jumps `dist` >= 1 lattice units
+ * in direction `dir` (Lemma 1, Sec. V).  `point` is the point's LOCAL index
+ * in `block` (0 .. size - 1), as in kdt_move_t.  KDT_E_ARG for a bad block,
+ * point, dir or dist; KDT_E_CAPACITY when max_staged moves are staged. */
 int kdt_move(kdt_ctx* ctx, int32_t block, int64_t point, int32_t dir, int32_t dist);
 
+/* Stage `count` moves at once (host arrays): moves[i] for block blocks[i],
+ * staged in array order.  status (host int32 [count] or NULL) receives
+ * KDT_OK, KDT_E_ARG or KDT_E_CAPACITY per move as kdt_move would return
+ * it; moves with an error are not staged.  Returns KDT_OK when all were
+ * staged, else the first error. */
+int kdt_moves(kdt_ctx* ctx, const int32_t* blocks, const kdt_move_t* moves, int64_t count,
+              int32_t* status);
+
 /* Apply the staged moves as one time step (one kernel launch) and clear the
- * stage.  Fig. 4: every block deletes its moved point and reinserts it. */
+ * stage.  Fig. 4: every block deletes its moved point (Delete) and inserts
+ * it at its new place (Insert), all blocks in parallel.  Asynchronous. */
 int kdt_step(kdt_ctx* ctx);
 
-/* Apply n_steps time steps from a move stream already in device memory:
+/* kdt_step, then wait for it and report what happened to every staged move,
+ * in staging order (host int32 [number staged]): KDT_OK if the move was
+ * applied, KDT_BLOCKED if the move rule blocked it (target outside the
+ * block's frame, or held by a point of the block at that moment).  A
+ * device error is returned (and is sticky) instead. */
+int kdt_step_status(kdt_ctx* ctx, int32_t* status);
+
+/* The main loop of Fig. 4 for n_steps time steps (every block deletes and
+ * reinserts its moved points, Sec. IV), from a move stream already in
+ * device memory:
  *   moves     dev kdt_move_t [M]
  *   step_off  dev int32 [n_steps][n_blocks + 1]: the moves of step t for
  *             block b are moves[step_off[t][b] .. step_off[t][b+1]-1]
@@ -152,14 +209,20 @@ int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
  * kdt_graph_launch (each replay applies the same move stream again, from the
  * state it finds).  The context's stream must not be the null stream.  The
  * graph records the given pointers: the move stream and `applied` must stay
- * valid while the graph lives.  kdt_graph_destroy releases it. */
+ * valid while the graph lives.  It also records the policy, the log and the
+ * launch shape of the moment: after kdt_set_policy, kdt_set_log or
+ * kdt_set_launch, kdt_graph_launch returns KDT_E_STATE (build the graph
+ * again); a replay writes the log rows of the steps it captured again.
+ * kdt_graph_destroy releases it. */
 typedef struct kdt_graph kdt_graph;
 int kdt_graph_build(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
                     int32_t n_steps, int8_t* applied, int32_t flags, kdt_graph** out);
 int kdt_graph_launch(kdt_ctx* ctx, kdt_graph* graph);
 void kdt_graph_destroy(kdt_graph* graph);
 
-/* Query the current triangulation (synchronises the stream).
+/* Query the current triangulation -- "return dataset(t)" of Fig. 4, the DT
+ * after the time step (Sec. III: only the triangulation after a step is
+ * valid) -- (synchronises the stream).
  *   tris      dev int32 [cap][3]: real triangles as global ids,
  *             counter-clockwise, each rotated to start at its smallest id,
  *             grouped by block
@@ -176,6 +239,25 @@ int kdt_query(kdt_ctx* ctx, int32_t* tris, int32_t* adj, int64_t* blk_off,
 /* Same triangles in canonical order (rows sorted lexicographically) written
  * to a HOST buffer int32 [cap][3]; used to compare with a reference. */
 int kdt_query_canonical(kdt_ctx* ctx, int32_t* host_tris, int64_t cap, int64_t* n_tri);
+
+/* Triangles of the listed blocks only (Fig. 4, "return dataset(t)", per
+ * block), canonical, written to HOST buffers; synchronises.
+ *   blocks     host int32 [count], distinct block indices (global mode: {0})
+ *   host_tris  host int32 [cap][3]: block blocks[i]'s real triangles in rows
+ *              host_off[i] .. host_off[i+1]-1, global ids, counter-clockwise,
+ *              each rotated to start at its smallest id, rows of a block
+ *              sorted lexicographically
+ *   host_adj   host int32 [cap][3] or NULL: the row (in host_tris) of the
+ *              triangle across the edge opposite column j's vertex, -1 on
+ *              the block's convex hull
+ *   host_off   host int64 [count + 1] (written even when the triangles do
+ *              not fit: then KDT_E_CAPACITY and nothing else is written)
+ * KDT_E_ARG for an empty list, an index out of range or a repeated block.
+ * Blocks are independent: after a block failed (its error is sticky for the
+ * context), the others can still be queried; listing the failed block
+ * returns its error. */
+int kdt_query_blocks(kdt_ctx* ctx, const int32_t* blocks, int32_t count, int32_t* host_tris,
+                     int32_t* host_adj, int64_t cap, int64_t* host_off);
 
 /* Order-independent 64-bit digest of every block's triangulation (host
  * uint64 [n_blocks]; synchronises): the wrapping sum over its real triangles,
@@ -235,8 +317,10 @@ int kdt_set_policy(kdt_ctx* ctx, int32_t policy, float tau, const float* mlp_w);
  * fields 0..15 the block's features for the step (log2 n, k, log2(1+k),
  * sum d/s, log2(1+sum d/s), max d/s, log2(1+max d/s), mean d/s, #(d>s),
  * #(d>4s), 100k/n, sum (d/s)^2/k, log2(1+sum d/s)*log2(1+k), log2 s,
- * log2(1+k)/log2 n, 1), 16 branch taken (0 repair, 1 rebuild), 17 device
- * clock ticks the branch took, 18 k.  Steps without moves are not logged. */
+ * log2(1+k)/log2 n, 1), 16 branch taken (0 repair, 1 rebuild, 2 repair that
+ * hit the repair path's capacity and finished the step by rebuilding: no
+ * clean cost of either branch), 17 device clock ticks the branch took,
+ * 18 k.  Steps without moves are not logged. */
 #define KDT_LOG_FIELDS 20
 int kdt_set_log(kdt_ctx* ctx, float* log, int64_t cap_steps);
 

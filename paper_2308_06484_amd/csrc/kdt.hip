@@ -596,9 +596,11 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
                 // KMAX triangles, a table or a cavity larger than its LDS
                 // arrays): the move changed nothing, and the block takes the
                 // rebuild branch for its remaining moves of the step, building
-                // here (the same DT* from the same positions)
+                // here (the same DT* from the same positions); the log marks
+                // the block-step as neither branch's clean cost
                 table_clear(S);
                 rc = dry_run_and_rebuild(s, S, b, mv, m, m1, applied, &S.st, false, dynx);
+                branch = 2;
                 break;
             }
             if (applied && lane == 0) applied[m] = (int8_t)app;
@@ -608,6 +610,10 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
         rc = dry_run_and_rebuild(s, S, b, mv, m0, m1, applied, &S.st, defer, dynx);
     }
     const long long c1 = wall_clock64();
+    // a failed move or dry run may leave the table (or the rebuild branch's
+    // arrays laid over it) in any state: the next block this wavefront takes
+    // (persistent launch) must find it empty
+    if (rc != ST_OK) table_clear(S);
     wsync();
     if (need_f && s.log && s.log_cap > 0 && lane < LOG_FIELDS) {
         const long long nb = (long long)(s.n_blocks);
@@ -1335,9 +1341,10 @@ __global__ void k_mlp_sgd(float* W, const float* g, float lr, float inv_n) {
     if (i < MLP_NPARAM) W[i] -= lr * g[i] * inv_n;
 }
 
-// query: number the real triangles of every block
-__global__ void __launch_bounds__(WAVE) k_qcount(DevState s, int* qmap, int* qcount) {
-    const int b = blockIdx.x;
+// query: number the real triangles of every block (list == null) or of the
+// listed blocks (workgroup i takes block list[i]); counts go to qcount[i]
+__global__ void __launch_bounds__(WAVE) k_qcount(DevState s, const int* list, int* qmap, int* qcount) {
+    const int b = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int lane = lane_id();
     BlockView B = view_of(s, b);
     int* map = qmap + s.tri_off[b];
@@ -1349,15 +1356,18 @@ __global__ void __launch_bounds__(WAVE) k_qcount(DevState s, int* qmap, int* qco
         if (i < B.ntri) map[i] = real ? base + lanes_below(m) : -1;
         base += __popcll(m);
     }
-    if (lane == 0) qcount[b] = base;
+    if (lane == 0) qcount[blockIdx.x] = base;
 }
 
-__global__ void __launch_bounds__(WAVE) k_qwrite(DevState s, const int* qmap, const long long* qoff,
-                                                 int* tris, int* adj) {
-    const int b = blockIdx.x;
+// ... and write them: block list[i] (or i) from row qoff[i] on, global ids,
+// each triangle rotated to start at its smallest id; adj[t][j] is the row of
+// the triangle across the edge opposite vertex j, -1 on the block's hull
+__global__ void __launch_bounds__(WAVE) k_qwrite(DevState s, const int* list, const int* qmap,
+                                                 const long long* qoff, int* tris, int* adj) {
+    const int b = list ? list[blockIdx.x] : (int)blockIdx.x;
     BlockView B = view_of(s, b);
     const int* map = qmap + s.tri_off[b];
-    const long long o = qoff[b];
+    const long long o = qoff[blockIdx.x];
     const int g0 = (int)s.pt_off[b];
     for (int i = lane_id(); i < B.ntri; i += WAVE) {
         const int idx = map[i];
@@ -1413,7 +1423,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
-        qtris, stage_mv, stage_off, sticky, lpt, total;
+        qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -1436,8 +1446,11 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.qcount = take(sizeof(int) * B);
     L.qoff = take(sizeof(long long) * (B + 1));
     L.qtris = take(sizeof(int) * 3 * ntri);
+    L.qadj = take(sizeof(int) * 3 * ntri);
+    L.qlist = take(sizeof(int) * B);
     L.stage_mv = take(sizeof(kdt_move_t) * (size_t)std::max(max_staged, 1));
     L.stage_off = take(sizeof(int) * (B + 1));
+    L.stage_app = take((size_t)std::max(max_staged, 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
     L.total = o;
@@ -1538,6 +1551,7 @@ struct kdt_ctx {
     int cus = 256;
     int wpc = 4;  // step workgroups (one wavefront each) that fit a compute unit's LDS
     long long step_count = 0;  // time steps launched so far (log index)
+    long long epoch = 0;       // changes of policy, log or launch shape (graphs record theirs)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     bool timing = false;
     int timing_period = 1;        // launches one event pair spans
@@ -1711,6 +1725,65 @@ int gbuild(kdt_ctx* c) {
     return sticky;
 }
 
+// ---- library-side partition (Sec. III, "Data structure"): the smallest
+// square with a power-of-two side covering the points, cut into four equal
+// squares again and again.
+struct PartBlock {
+    int64_t lo, hi;  // range in Morton order
+    int32_t x0, y0, side;
+};
+
+// Points of a Morton-ordered range [lo, hi) all on one line (or < 3 points).
+bool range_collinear(const int32_t* xy, const std::vector<int64_t>& ord, int64_t lo, int64_t hi) {
+    if (hi - lo < 3) return true;
+    const int32_t* a = xy + 2 * ord[lo];
+    const int32_t* b = xy + 2 * ord[lo + 1];
+    for (int64_t i = lo + 2; i < hi; ++i)
+        if (orient_h(a, b, xy + 2 * ord[i]) != 0) return false;
+    return true;
+}
+
+// Quad-tree leaves of node (x0, y0, side) holding Morton range [lo, hi): a
+// node with more than `thr` points is cut into its four quarters (in Morton
+// order: low x low y, high x low y, low x high y, high x high y), quarters
+// holding no point are dropped; a node whose cut would leave a quarter with
+// fewer than 4 points or with all its points on one line stays whole.
+void quad_leaves(const int32_t* xy, const std::vector<int64_t>& ord, const std::vector<uint64_t>& code,
+                 int64_t lo, int64_t hi, int32_t x0, int32_t y0, int32_t side, int bits, int64_t thr,
+                 std::vector<PartBlock>& out) {
+    if (hi - lo > thr && side > 1) {
+        const int h = bits - 1;  // the quarter is bits (2h+1, 2h) of the code
+        int64_t cut[5];
+        cut[0] = lo;
+        cut[4] = hi;
+        for (int q = 1; q < 4; ++q) {
+            const uint64_t key = (code[lo] >> (2 * h + 2) << (2 * h + 2)) | ((uint64_t)q << (2 * h));
+            cut[q] = std::lower_bound(code.begin() + lo, code.begin() + hi, key) - code.begin();
+        }
+        bool ok = true;
+        for (int q = 0; q < 4 && ok; ++q) {
+            const int64_t m = cut[q + 1] - cut[q];
+            if (m == 0) continue;
+            ok = m >= 4 && !range_collinear(xy, ord, cut[q], cut[q + 1]);
+        }
+        if (ok) {
+            const int32_t hs = side / 2;
+            for (int q = 0; q < 4; ++q)
+                if (cut[q + 1] > cut[q])
+                    quad_leaves(xy, ord, code, cut[q], cut[q + 1], x0 + (q & 1) * hs, y0 + (q >> 1) * hs, hs, h,
+                                thr, out);
+            return;
+        }
+    }
+    out.push_back(PartBlock{lo, hi, x0, y0, side});
+}
+
+uint64_t morton24(uint32_t x, uint32_t y) {
+    uint64_t m = 0;
+    for (int i = 0; i < 24; ++i) m |= ((uint64_t)((x >> i) & 1) << (2 * i)) | ((uint64_t)((y >> i) & 1) << (2 * i + 1));
+    return m;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1728,6 +1801,85 @@ const char* kdt_strerror(int code) {
     case KDT_E_INTERNAL: return "device invariant check failed";
     default: return "unknown status";
     }
+}
+
+int kdt_partition(const int32_t* xy, int64_t n, int32_t scheme, int64_t param, int64_t* perm,
+                  int64_t* block_off, int32_t* frames, int32_t cap_blocks, int32_t* n_blocks) {
+    if (!xy || !perm || !n_blocks || n < 1 || cap_blocks < 0 || (cap_blocks > 0 && (!block_off || !frames)))
+        return KDT_E_ARG;
+    if (scheme != KDT_PART_GRID && scheme != KDT_PART_QUADTREE) return KDT_E_ARG;
+    *n_blocks = 0;
+    int depth = 0;
+    if (scheme == KDT_PART_GRID) {
+        // param = number of cells, a power of four
+        int64_t p = 1;
+        while (p < param && depth < 12) { p *= 4; ++depth; }  // at most 4^12 cells
+        if (param < 1 || p != param) return KDT_E_ARG;
+    } else if (param < 4) {
+        return KDT_E_ARG;
+    }
+    int32_t mnx = INT32_MAX, mny = INT32_MAX, mxx = INT32_MIN, mxy = INT32_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t x = xy[2 * i], y = xy[2 * i + 1];
+        if (x < 0 || y < 0 || x >= KDT_COORD_LIMIT || y >= KDT_COORD_LIMIT) return KDT_E_RANGE;
+        mnx = std::min(mnx, x); mny = std::min(mny, y);
+        mxx = std::max(mxx, x); mxy = std::max(mxy, y);
+    }
+    // covering square: lower-left corner at the minima, power-of-two side
+    const int32_t ext = std::max(mxx - mnx, mxy - mny) + 1;
+    int bits = 0;
+    while ((1 << bits) < ext) ++bits;
+    bits = std::max(bits, depth);
+    std::vector<int64_t> ord(n);
+    std::vector<uint64_t> code(n);
+    {
+        std::vector<std::pair<uint64_t, int64_t>> key(n);
+        for (int64_t i = 0; i < n; ++i)
+            key[i] = {morton24((uint32_t)(xy[2 * i] - mnx), (uint32_t)(xy[2 * i + 1] - mny)), i};
+        std::sort(key.begin(), key.end());
+        for (int64_t i = 0; i < n; ++i) {
+            if (i > 0 && key[i].first == key[i - 1].first) return KDT_E_DUP;
+            ord[i] = key[i].second;
+            code[i] = key[i].first;
+        }
+    }
+    std::vector<PartBlock> leaves;
+    if (scheme == KDT_PART_QUADTREE) {
+        quad_leaves(xy, ord, code, 0, n, mnx, mny, 1 << bits, bits, param, leaves);
+    } else {
+        // every cell of the depth-`depth` grid that holds a point, row by row
+        const int cb = bits - depth;  // a cell's side is 2^cb
+        const int64_t cells = 1LL << depth;
+        std::vector<std::pair<int64_t, int64_t>> key(n);  // (row-major cell, point)
+        for (int64_t i = 0; i < n; ++i)
+            key[i] = {(((int64_t)(xy[2 * i + 1] - mny) >> cb) * cells) + ((xy[2 * i] - mnx) >> cb), i};
+        std::sort(key.begin(), key.end());
+        for (int64_t i = 0; i < n; ++i) {
+            ord[i] = key[i].second;
+            if (i == 0 || key[i].first != key[i - 1].first) {
+                const int64_t c = key[i].first;
+                leaves.push_back(PartBlock{i, i, mnx + (int32_t)((c % cells) << cb),
+                                           mny + (int32_t)((c / cells) << cb), 1 << cb});
+            }
+            leaves.back().hi = i + 1;
+        }
+    }
+    *n_blocks = (int32_t)leaves.size();
+    if ((int64_t)leaves.size() > cap_blocks) return KDT_E_CAPACITY;
+    block_off[0] = 0;
+    for (size_t b = 0; b < leaves.size(); ++b) {
+        const PartBlock& L = leaves[b];
+        // a block's points in input order (so local order follows global id order)
+        std::vector<int64_t> pts(ord.begin() + L.lo, ord.begin() + L.hi);
+        std::sort(pts.begin(), pts.end());
+        for (size_t k = 0; k < pts.size(); ++k) perm[L.lo + (int64_t)k] = pts[k];
+        block_off[b + 1] = L.hi;
+        frames[4 * b + 0] = L.x0;
+        frames[4 * b + 1] = L.y0;
+        frames[4 * b + 2] = (int32_t)std::min<int64_t>((int64_t)L.x0 + L.side, KDT_COORD_LIMIT);
+        frames[4 * b + 3] = (int32_t)std::min<int64_t>((int64_t)L.y0 + L.side, KDT_COORD_LIMIT);
+    }
+    return KDT_OK;
 }
 
 int kdt_workspace_size(int64_t n, int32_t n_blocks, const int64_t* block_off, int32_t max_staged,
@@ -1886,15 +2038,14 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     return KDT_OK;
 }
 
-int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist) {
-    if (!c) return KDT_E_ARG;
-    if (c->global) return KDT_E_STATE;
+// Validation of one staged move: KDT_OK, KDT_E_ARG or KDT_E_CAPACITY.
+static int stage_one(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist) {
     if (block < 0 || block >= c->B) return KDT_E_ARG;
-    if (point < c->pt_off[block] || point >= c->pt_off[block + 1]) return KDT_E_ARG;
+    if (point < 0 || point >= c->pt_off[block + 1] - c->pt_off[block]) return KDT_E_ARG;
     if (dir < 0 || dir > 3 || dist < 1) return KDT_E_ARG;
     if ((int64_t)c->staged.size() >= c->max_staged) return KDT_E_CAPACITY;
     kdt_move_t m;
-    m.point = (int32_t)(point - c->pt_off[block]);
+    m.point = (int32_t)point;
     m.dir = dir;
     m.dist = dist;
     m.pad = 0;
@@ -1903,11 +2054,32 @@ int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist
     return KDT_OK;
 }
 
-int kdt_step(kdt_ctx* c) {
+int kdt_move(kdt_ctx* c, int32_t block, int64_t point, int32_t dir, int32_t dist) {
     if (!c) return KDT_E_ARG;
     if (c->global) return KDT_E_STATE;
-    if (c->sticky != KDT_OK) return KDT_E_STATE;
-    // group the staged moves by block, keeping their order within a block
+    return stage_one(c, block, point, dir, dist);
+}
+
+int kdt_moves(kdt_ctx* c, const int32_t* blocks, const kdt_move_t* moves, int64_t count, int32_t* status) {
+    if (!c || count < 0 || (count > 0 && (!blocks || !moves))) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    int rc = KDT_OK;
+    for (int64_t i = 0; i < count; ++i) {
+        const int st = stage_one(c, blocks[i], moves[i].point, moves[i].dir, moves[i].dist);
+        if (status) status[i] = st;
+        if (st != KDT_OK && rc == KDT_OK) rc = st;
+    }
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Launch the staged moves as one time step: grouped by block (list order
+// kept within a block), copied to the workspace, one k_step launch; `order`
+// (if given) receives the staging index of each launched move.
+int launch_staged(kdt_ctx* c, int8_t* applied, std::vector<int>* order) {
     std::vector<int> idx(c->staged.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(),
@@ -1928,16 +2100,50 @@ int kdt_step(kdt_ctx* c) {
                                           hipMemcpyHostToDevice, c->stream));
     rc |= check_hip(c, hipMemcpyAsync(w + c->L.stage_off, off.data(), sizeof(int) * (c->B + 1),
                                       hipMemcpyHostToDevice, c->stream));
+    // the host vectors are pageable: wait before they go out of scope
+    rc |= check_hip(c, hipStreamSynchronize(c->stream));
     if (rc != KDT_OK) return KDT_E_DEVICE;
     hipEvent_t e0 = timing_begin(c);
     k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
-                                                       (const int*)(w + c->L.stage_off), nullptr, c->step_count);
+                                                       (const int*)(w + c->L.stage_off), applied, c->step_count);
     if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
         k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
                                                                           c->pb_lds_follow);
     c->step_count++;
     timing_end(c, e0);
+    if (order) order->swap(idx);
     return check_hip(c, hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int kdt_step(kdt_ctx* c) {
+    if (!c) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    return launch_staged(c, nullptr, nullptr);
+}
+
+int kdt_step_status(kdt_ctx* c, int32_t* status) {
+    if (!c) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    const size_t m = c->staged.size();
+    if (m > 0 && !status) return KDT_E_ARG;
+    int8_t* app = (int8_t*)(c->ws + c->L.stage_app);
+    std::vector<int> order;
+    int rc = KDT_OK;
+    if (m > 0) rc = check_hip(c, hipMemsetAsync(app, 0, m, c->stream));
+    if (rc == KDT_OK) rc = launch_staged(c, app, &order);
+    if (rc != KDT_OK) return rc;
+    rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    std::vector<int8_t> h(m);
+    if (m > 0 && check_hip(c, hipMemcpy(h.data(), app, m, hipMemcpyDeviceToHost))) return KDT_E_DEVICE;
+    for (size_t i = 0; i < m; ++i) status[order[i]] = h[i] ? KDT_OK : KDT_BLOCKED;
+    return KDT_OK;
 }
 
 }  // extern "C"
@@ -1982,6 +2188,7 @@ struct kdt_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;
     kdt_ctx* ctx;
+    long long epoch;  // the context's epoch when captured
 };
 
 extern "C" {
@@ -1998,6 +2205,7 @@ int kdt_run(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_
 int kdt_set_launch(kdt_ctx* c, int32_t persist_per_cu) {
     if (!c || persist_per_cu < 1 || persist_per_cu > 64) return KDT_E_ARG;
     c->persist_per_cu = persist_per_cu;
+    c->epoch++;
     return KDT_OK;
 }
 
@@ -2010,6 +2218,7 @@ int kdt_graph_build(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off
     kdt_graph* g = new (std::nothrow) kdt_graph();
     if (!g) return KDT_E_CAPACITY;
     g->ctx = c;
+    g->epoch = c->epoch;
     if (check_hip(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal))) {
         delete g;
         return KDT_E_DEVICE;
@@ -2035,7 +2244,7 @@ int kdt_graph_build(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off
 
 int kdt_graph_launch(kdt_ctx* c, kdt_graph* g) {
     if (!c || !g || g->ctx != c) return KDT_E_ARG;
-    if (c->sticky != KDT_OK) return KDT_E_STATE;
+    if (c->sticky != KDT_OK || g->epoch != c->epoch) return KDT_E_STATE;
     return check_hip(c, hipGraphLaunch(g->exec, c->stream));
 }
 
@@ -2052,6 +2261,7 @@ int kdt_set_policy(kdt_ctx* c, int32_t policy, float tau, const float* mlp_w) {
     c->dev.policy = policy;
     c->dev.tau = tau;
     c->dev.mlp_w = mlp_w;
+    c->epoch++;
     if (!c->global) plan_rebuild_lds(c);
     return KDT_OK;
 }
@@ -2061,6 +2271,7 @@ int kdt_set_log(kdt_ctx* c, float* log, int64_t cap_steps) {
     c->dev.log = cap_steps > 0 ? log : nullptr;
     c->dev.log_cap = cap_steps;
     c->step_count = 0;
+    c->epoch++;
     return KDT_OK;
 }
 
@@ -2113,7 +2324,7 @@ int kdt_query(kdt_ctx* c, int32_t* tris, int32_t* adj, int64_t* blk_off, int64_t
     char* w = c->ws;
     int* qmap = (int*)(w + c->L.qmap);
     int* qcount = (int*)(w + c->L.qcount);
-    k_qcount<<<c->B, WAVE, 0, c->stream>>>(c->dev, qmap, qcount);
+    k_qcount<<<c->B, WAVE, 0, c->stream>>>(c->dev, nullptr, qmap, qcount);
     if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
     std::vector<int> cnt(c->B);
     if (check_hip(c, hipMemcpyAsync(cnt.data(), qcount, sizeof(int) * c->B, hipMemcpyDeviceToHost, c->stream)) ||
@@ -2128,7 +2339,7 @@ int kdt_query(kdt_ctx* c, int32_t* tris, int32_t* adj, int64_t* blk_off, int64_t
     if (check_hip(c, hipMemcpyAsync(w + c->L.qoff, off.data(), sizeof(long long) * (c->B + 1),
                                     hipMemcpyHostToDevice, c->stream)))
         return KDT_E_DEVICE;
-    k_qwrite<<<c->B, WAVE, 0, c->stream>>>(c->dev, qmap, (const long long*)(w + c->L.qoff), tris, adj);
+    k_qwrite<<<c->B, WAVE, 0, c->stream>>>(c->dev, nullptr, qmap, (const long long*)(w + c->L.qoff), tris, adj);
     if (check_hip(c, hipGetLastError()) || check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
     return KDT_OK;
 }
@@ -2160,6 +2371,94 @@ int kdt_query_canonical(kdt_ctx* c, int32_t* host_tris, int64_t cap, int64_t* n_
     });
     for (int64_t i = 0; i < nt; ++i)
         for (int j = 0; j < 3; ++j) host_tris[3 * i + j] = h[3 * idx[i] + j];
+    return KDT_OK;
+}
+
+int kdt_query_blocks(kdt_ctx* c, const int32_t* blocks, int32_t count, int32_t* host_tris, int32_t* host_adj,
+                     int64_t cap, int64_t* host_off) {
+    if (!c || !blocks || !host_off || count < 1 || cap < 0 || (cap > 0 && !host_tris)) return KDT_E_ARG;
+    if (c->global ? count != 1 : count > c->B) return KDT_E_ARG;
+    {
+        std::vector<char> seen(c->B, 0);
+        for (int32_t i = 0; i < count; ++i) {
+            const int32_t b = blocks[i];
+            if (b < 0 || b >= c->B || seen[b]) return KDT_E_ARG;  // each block at most once
+            seen[b] = 1;
+        }
+    }
+    // blocks are independent: the listed ones can be read while another
+    // block has failed (its error is sticky for the context), unless one of
+    // them is the failed block or the runtime failed
+    if (check_hip(c, hipStreamSynchronize(c->stream))) return KDT_E_DEVICE;
+    int rc = kdt_sync(c);
+    if (rc == KDT_E_DEVICE || (rc != KDT_OK && c->global)) return rc;
+    if (rc != KDT_OK) {
+        std::vector<int32_t> bst(c->B);
+        if (check_hip(c, hipMemcpyAsync(bst.data(), c->dev.status, sizeof(int32_t) * c->B, hipMemcpyDeviceToHost,
+                                        c->stream)) ||
+            check_hip(c, hipStreamSynchronize(c->stream)))
+            return KDT_E_DEVICE;
+        for (int32_t i = 0; i < count; ++i)
+            if (bst[blocks[i]] != 0) return bst[blocks[i]];
+    }
+    char* w = c->ws;
+    int* qmap = (int*)(w + c->L.qmap);
+    int* qcount = (int*)(w + c->L.qcount);
+    int* qlist = (int*)(w + c->L.qlist);
+    int* dtris = (int*)(w + c->L.qtris);
+    int* dadj = (int*)(w + c->L.qadj);
+    std::vector<int> cnt(count);
+    if (check_hip(c, hipMemcpyAsync(qlist, blocks, sizeof(int) * count, hipMemcpyHostToDevice, c->stream)))
+        return KDT_E_DEVICE;
+    k_qcount<<<count, WAVE, 0, c->stream>>>(c->dev, qlist, qmap, qcount);
+    if (check_hip(c, hipGetLastError()) ||
+        check_hip(c, hipMemcpyAsync(cnt.data(), qcount, sizeof(int) * count, hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipStreamSynchronize(c->stream)))
+        return KDT_E_DEVICE;
+    std::vector<long long> off(count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) off[i + 1] = off[i] + cnt[i];
+    for (int32_t i = 0; i <= count; ++i) host_off[i] = off[i];
+    const int64_t nt = off[count];
+    if (nt > cap) return KDT_E_CAPACITY;
+    if (check_hip(c, hipMemcpyAsync(w + c->L.qoff, off.data(), sizeof(long long) * (count + 1),
+                                    hipMemcpyHostToDevice, c->stream)))
+        return KDT_E_DEVICE;
+    k_qwrite<<<count, WAVE, 0, c->stream>>>(c->dev, qlist, qmap, (const long long*)(w + c->L.qoff), dtris,
+                                            host_adj ? dadj : nullptr);
+    std::vector<int32_t> t(3 * (size_t)nt), a(host_adj ? 3 * (size_t)nt : 0);
+    if (check_hip(c, hipGetLastError()) ||
+        (nt > 0 && check_hip(c, hipMemcpyAsync(t.data(), dtris, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost,
+                                               c->stream))) ||
+        (nt > 0 && host_adj &&
+         check_hip(c, hipMemcpyAsync(a.data(), dadj, sizeof(int32_t) * 3 * nt, hipMemcpyDeviceToHost, c->stream))) ||
+        check_hip(c, hipStreamSynchronize(c->stream)))
+        return KDT_E_DEVICE;
+    // canonical order within every listed block; adjacency rows follow
+    std::vector<int64_t> idx, inv;
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t o0 = off[i], m = off[i + 1] - off[i];
+        idx.resize(m);
+        for (int64_t k = 0; k < m; ++k) idx[k] = o0 + k;
+        std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+            const int32_t* p = &t[3 * x];
+            const int32_t* q = &t[3 * y];
+            if (p[0] != q[0]) return p[0] < q[0];
+            if (p[1] != q[1]) return p[1] < q[1];
+            return p[2] < q[2];
+        });
+        if (host_adj) {
+            inv.resize(m);
+            for (int64_t k = 0; k < m; ++k) inv[idx[k] - o0] = o0 + k;
+        }
+        for (int64_t k = 0; k < m; ++k)
+            for (int j = 0; j < 3; ++j) {
+                host_tris[3 * (o0 + k) + j] = t[3 * idx[k] + j];
+                if (host_adj) {
+                    const int32_t r = a[3 * idx[k] + j];
+                    host_adj[3 * (o0 + k) + j] = r < 0 ? -1 : (int32_t)inv[r - o0];
+                }
+            }
+    }
     return KDT_OK;
 }
 

@@ -85,43 +85,4 @@ __device__ __forceinline__ float mlp_backward1(const float* W, const float* x, c
     return loss;
 }
 
-// Block features for one time step, computed from the block's size, frame
-// and this step's moves only (so they are the same whichever branch ran
-// before).  s = spacing sqrt(frame area / n); d = move distance.
-//   0 log2 n          1 k (moves)        2 log2(1+k)        3 sum d/s
-//   4 log2(1+sum d/s) 5 max d/s          6 log2(1+max d/s)  7 mean d/s
-//   8 #(d > s)        9 #(d > 4s)       10 100 k/n         11 sum (d/s)^2 / max(k,1)
-//  12 log2(1+sum d/s) * log2(1+k)       13 log2(spacing)   14 log2(1+k) / log2 n
-//  15 1
-__device__ __forceinline__ void block_features(int n, int4 fr, const int* dist, int k, float* f) {
-    const float area = (float)(fr.z - fr.x) * (float)(fr.w - fr.y);
-    const float s = sqrtf(area / (float)n);
-    float sum = 0.f, mx = 0.f, sq = 0.f, c1 = 0.f, c4 = 0.f;
-    for (int i = 0; i < k; ++i) {
-        const float r = (float)dist[i] / s;
-        sum += r;
-        mx = fmaxf(mx, r);
-        sq += r * r;
-        c1 += r > 1.f ? 1.f : 0.f;
-        c4 += r > 4.f ? 1.f : 0.f;
-    }
-    const float ln = log2f((float)n), lk = log2f(1.f + (float)k);
-    f[0] = ln;
-    f[1] = (float)k;
-    f[2] = lk;
-    f[3] = sum;
-    f[4] = log2f(1.f + sum);
-    f[5] = mx;
-    f[6] = log2f(1.f + mx);
-    f[7] = k ? sum / (float)k : 0.f;
-    f[8] = c1;
-    f[9] = c4;
-    f[10] = 100.f * (float)k / (float)n;
-    f[11] = sq / (float)(k > 0 ? k : 1);
-    f[12] = f[4] * lk;
-    f[13] = log2f(s);
-    f[14] = lk / ln;
-    f[15] = 1.f;
-}
-
 }  // namespace kdt

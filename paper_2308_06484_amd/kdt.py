@@ -16,6 +16,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkdt.so")
 
+BLOCKED = 1
 OK, E_ARG, E_RANGE, E_DUP, E_DEGEN, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 RUN_PER_STEP, RUN_FUSED, RUN_PERSISTENT = 0, 1, 2
 POLICY = {"repair": 0, "rebuild": 1, "threshold": 2, "mlp": 3}
@@ -28,7 +29,9 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_graph_build", "kdt_graph_launch", "kdt_graph_destroy", "kdt_digest",
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
-           "kdt_owner", "kdt_global_stats")
+           "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
+           "kdt_partition")
+PART = {"grid": 0, "quadtree": 1}
 
 # kdt_global_stats counters, in order
 GSTATS = ("interacting", "serial", "lost", "transfers", "overflow", "build_rounds")
@@ -67,6 +70,10 @@ def _lib():
         L.kdt_init.argtypes = [ctypes.POINTER(vp), vp, i64, i32, vp, vp, i32, vp, ctypes.c_size_t, vp]
         L.kdt_move.argtypes = [vp, i32, i64, i32, i32]
         L.kdt_step.argtypes = [vp]
+        L.kdt_moves.argtypes = [vp, vp, vp, i64, vp]
+        L.kdt_step_status.argtypes = [vp, vp]
+        L.kdt_query_blocks.argtypes = [vp, vp, i32, vp, vp, i64, vp]
+        L.kdt_partition.argtypes = [vp, i64, i32, i64, vp, vp, vp, i32, ctypes.POINTER(i32)]
         L.kdt_run.argtypes = [vp, vp, vp, i32, vp, i32]
         L.kdt_query.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
         L.kdt_query_canonical.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
@@ -120,6 +127,27 @@ def workspace_size(n, pt_off, max_staged=0):
     _check(_lib().kdt_workspace_size(int(n), len(pt_off) - 1, _ptr(pt_off), int(max_staged),
                                      ctypes.byref(out)), "kdt_workspace_size")
     return int(out.value)
+
+
+def partition(xy, scheme, param):
+    """Library-side partition (kdt_partition): scheme "grid" (param = number
+    of cells, a power of four) or "quadtree" (param = threshold).  Returns
+    (perm int64 [N], pt_off int64 [B + 1], frame int32 [B, 4]); row i of the
+    partitioned set is input point perm[i]."""
+    xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+    n = xy.shape[0]
+    perm = np.empty(n, dtype=np.int64)
+    nb = ctypes.c_int32(0)
+    L = _lib()
+    rc = L.kdt_partition(_ptr(xy), n, PART[scheme], int(param), _ptr(perm), None, None, 0, ctypes.byref(nb))
+    if rc not in (OK, E_CAPACITY):
+        _check(rc, "kdt_partition")
+    cap = int(nb.value)
+    off = np.zeros(cap + 1, dtype=np.int64)
+    fr = np.zeros((max(cap, 1), 4), dtype=np.int32)
+    _check(L.kdt_partition(_ptr(xy), n, PART[scheme], int(param), _ptr(perm), _ptr(off), _ptr(fr), cap,
+                           ctypes.byref(nb)), "kdt_partition")
+    return perm, off, fr[:cap]
 
 
 def _stream_arg(stream):
@@ -206,6 +234,23 @@ class KineticDT:
     def step(self):
         _check(_lib().kdt_step(self.ctx), "kdt_step")
 
+    def moves(self, blocks, moves):
+        """Stage a batch: blocks int32 [M], moves int32 [M, 4] (local point,
+        dir, dist, 0).  Returns the per-move staging status (int32 [M])."""
+        blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+        moves = np.ascontiguousarray(moves, dtype=np.int32).reshape(-1, 4)
+        st = np.zeros(len(blocks), dtype=np.int32)
+        rc = _lib().kdt_moves(self.ctx, _ptr(blocks), _ptr(moves), len(blocks), _ptr(st))
+        if rc not in (OK, E_ARG, E_CAPACITY):
+            _check(rc, "kdt_moves")
+        return st
+
+    def step_status(self, n_staged):
+        """Apply the staged step; per staged move OK (0) or BLOCKED (1)."""
+        st = np.full(max(1, n_staged), -100, dtype=np.int32)
+        _check(_lib().kdt_step_status(self.ctx, _ptr(st)), "kdt_step_status")
+        return st[:n_staged]
+
     def _check_stream(self, moves, step_off, applied):
         assert moves.dtype == torch.int32 and moves.is_cuda and moves.is_contiguous()
         assert step_off.dtype == torch.int32 and step_off.is_cuda and step_off.is_contiguous()
@@ -290,6 +335,23 @@ class KineticDT:
         nt = ctypes.c_int64(0)
         _check(_lib().kdt_query_canonical(self.ctx, _ptr(out), cap, ctypes.byref(nt)), "kdt_query_canonical")
         return out[:int(nt.value)].copy()
+
+    def query_blocks(self, blocks, adjacency=False):
+        """Canonical triangles of the listed blocks (kdt_query_blocks):
+        (tris int32 [T, 3], adj int32 [T, 3] or None, off int64 [len + 1]);
+        block blocks[i] holds rows off[i] .. off[i+1]-1."""
+        blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+        off = np.zeros(len(blocks) + 1, dtype=np.int64)
+        L = _lib()
+        rc = L.kdt_query_blocks(self.ctx, _ptr(blocks), len(blocks), None, None, 0, _ptr(off))
+        if rc not in (OK, E_CAPACITY):
+            _check(rc, "kdt_query_blocks")
+        cap = int(off[-1])
+        tris = np.empty((max(cap, 1), 3), dtype=np.int32)
+        adj = np.empty((max(cap, 1), 3), dtype=np.int32) if adjacency else None
+        _check(L.kdt_query_blocks(self.ctx, _ptr(blocks), len(blocks), _ptr(tris), _ptr(adj), cap, _ptr(off)),
+               "kdt_query_blocks")
+        return tris[:cap], (adj[:cap] if adjacency else None), off
 
     def digest(self):
         """uint64 [B]: order-independent digest of each block's triangulation."""

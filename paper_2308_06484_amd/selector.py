@@ -50,7 +50,9 @@ def collect(w, steps, device="cuda:0"):
     run of the same workload (identical states: DT* is unique)."""
     lr_, _, _ = run_policy(w, steps, "repair", device)
     lb_, _, _ = run_policy(w, steps, "rebuild", device)
-    valid = lr_[..., 18] > 0
+    # block-steps with moves; a repair that hit the repair path's capacity
+    # and finished by rebuilding (branch 2) has no clean cost: left out
+    valid = (lr_[..., 18] > 0) & (lr_[..., 16] != 2)
     X = lr_[..., :IN][valid].astype(np.float32)
     Y = np.stack([np.log2(np.maximum(lr_[..., 17][valid], 1.0)),
                   np.log2(np.maximum(lb_[..., 17][valid], 1.0))], axis=1).astype(np.float32)

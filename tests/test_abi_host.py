@@ -31,8 +31,8 @@ def test_strerror():
 def test_workspace_size_formula_grows_with_points():
     a = K.workspace_size(1024, [0, 1024])
     b = K.workspace_size(2048, [0, 1024, 2048])
-    # one 32-byte record per triangle dominates: 2n - 2B records
-    assert b - a >= 32 * (2 * 2048 - 4 - (2 * 1024 - 2)) and a > 32 * 2046
+    # one 64-byte record per triangle dominates: 2n - 2B records
+    assert b - a >= 64 * (2 * 2048 - 4 - (2 * 1024 - 2)) and a > 64 * 2046
     with pytest.raises(K.KDTError):
         K.workspace_size(10, [0, 5, 9])
 

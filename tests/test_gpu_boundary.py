@@ -1,0 +1,200 @@
+"""The boundary calls of the library on the device, against the oracle:
+batch staging with per-move status (KDT_BLOCKED), a point set partitioned
+by the library's quad-tree, per-block queries with adjacency, the digest,
+per-block isolation of a failed block in the persistent launch, and the
+graph's record of the policy."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dt_star
+from oracle.kinetic import Kinetic
+from paper_2308_06484_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _K():
+    from paper_2308_06484_amd import kdt as K
+    return K
+
+
+def test_batch_staging_reports_blocked_moves():
+    """kdt_moves + kdt_step_status: every staged move's status equals the
+    oracle's verdict (applied or blocked), every step, on a dense block where
+    many moves are blocked; bad moves are refused at staging."""
+    K = _K()
+    _say("batch staging: 2 blocks of 400 points on 24x24 lattices, 30 steps of 12 moves")
+    rng = np.random.default_rng(7)
+    xy = np.concatenate([W._distinct_uniform(rng, 400, 0, 0, 24, 24),
+                         W._distinct_uniform(rng, 400, 100, 100, 24, 24)])
+    off = np.array([0, 400, 800], np.int64)
+    fr = np.array([[0, 0, 24, 24], [100, 100, 124, 124]], np.int32)
+    dt = K.KineticDT(xy, off, fr, max_staged=64, device=DEV)
+    ref = Kinetic(xy, off, fr)
+    n_blocked = 0
+    for t in range(30):
+        blocks = rng.integers(0, 2, size=12).astype(np.int32)
+        mv = np.zeros((12, 4), np.int32)
+        mv[:, 0] = rng.integers(0, 400, size=12)
+        mv[:, 1] = rng.integers(0, 4, size=12)
+        mv[:, 2] = rng.integers(1, 3, size=12)
+        st = dt.moves(blocks, mv)
+        assert np.all(st == K.OK)
+        # the oracle takes a step as per-block lists in staging order
+        order = np.argsort(blocks, kind="stable")
+        ref_mv = mv[order]
+        ref_off = np.array([0, int((blocks == 0).sum()), 12], np.int64)
+        want = np.zeros(12, bool)
+        want[order] = ref.apply_step(ref_mv, ref_off)
+        got = dt.step_status(12)
+        assert np.array_equal(got, np.where(want, K.OK, K.BLOCKED)), t
+        n_blocked += int((~want).sum())
+        assert np.array_equal(dt.query_canonical(), ref.all_dt()), t
+    assert n_blocked > 20
+    bad = np.array([[400, 0, 1, 0], [3, 4, 1, 0], [3, 0, 0, 0], [3, 0, 1, 0]], np.int32)
+    st = dt.moves(np.array([0, 0, 0, 5], np.int32), bad)
+    assert st.tolist() == [K.E_ARG] * 4
+    assert dt.step_status(0).size == 0
+    dt.close()
+
+
+def test_quadtree_partitioned_set_every_step():
+    """Points partitioned by kdt_partition (threshold 512, uneven mixture
+    data); one move per block per step inside its square; the canonical list
+    against the oracle after every step."""
+    K = _K()
+    rng = np.random.default_rng(11)
+    pts = W._distinct_gmm(rng, 20000, 0, 65536)
+    perm, off, fr = K.partition(pts, "quadtree", 512)
+    xy = pts[perm]
+    B = len(off) - 1
+    _say(f"quad-tree partition: {B} blocks, sizes {np.diff(off).min()}..{np.diff(off).max()}; 25 steps")
+    mv, mv_off = W._one_move_per_block(rng, 25, np.diff(off), 1, 64)
+    dt = K.KineticDT(xy, off, fr, device=DEV)
+    ref = Kinetic(xy, off, fr)
+    assert np.array_equal(dt.query_canonical(), ref.all_dt(8))
+    mvd = torch.from_numpy(mv).to(DEV)
+    offd = torch.from_numpy(mv_off).to(DEV)
+    app = torch.zeros(len(mv), dtype=torch.int8, device=DEV)
+    for t in range(25):
+        dt.run(mvd, offd[t:t + 1].contiguous(), applied=app)
+        a = ref.apply_step(mv, mv_off[t])
+        lo, hi = int(mv_off[t, 0]), int(mv_off[t, -1])
+        assert np.array_equal(app[lo:hi].cpu().numpy().astype(bool), a), t
+        assert np.array_equal(dt.query_canonical(), ref.all_dt(8)), t
+    dt.close()
+
+
+def _splitmix(z):
+    z = z + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def _digest(tris):
+    t = tris.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        return int(np.sum(_splitmix(t[:, 0] ^ _splitmix(t[:, 1] ^ _splitmix(t[:, 2]))), dtype=np.uint64))
+
+
+def test_query_blocks_adjacency_and_digest():
+    """kdt_query_blocks on a shuffled subset of uneven blocks after 20 steps:
+    each block's rows equal the oracle's DT*, adjacency is consistent (the
+    row across an edge holds the reversed edge; -1 exactly on hull edges);
+    kdt_digest equals the digest of the oracle's list."""
+    K = _K()
+    w = W.subset_blocks(W.uneven4096(seed=3, steps=20), np.arange(0, 4096, 37), steps=20)
+    B = len(w["pt_off"]) - 1
+    _say(f"query_blocks / digest: {B} uneven blocks, 20 steps")
+    dt = K.KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+    dt.run(torch.from_numpy(w["mv"]).to(DEV), torch.from_numpy(w["mv_off"]).to(DEV))
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    for t in range(20):
+        ref.apply_step(w["mv"], w["mv_off"][t])
+    blocks = np.random.default_rng(0).permutation(B)[:40].astype(np.int32)
+    tris, adj, off = dt.query_blocks(blocks, adjacency=True)
+    for i, b in enumerate(blocks):
+        T = tris[off[i]:off[i + 1]]
+        A = adj[off[i]:off[i + 1]]
+        assert np.array_equal(T, ref.block_dt(b)), b
+        edges = {}
+        for r in range(len(T)):
+            for j in range(3):
+                edges[(int(T[r, (j + 1) % 3]), int(T[r, (j + 2) % 3]))] = r
+        hull = 0
+        for r in range(len(T)):
+            for j in range(3):
+                u, v = int(T[r, (j + 1) % 3]), int(T[r, (j + 2) % 3])
+                o = edges.get((v, u))
+                if o is None:
+                    assert A[r, j] == -1
+                    hull += 1
+                else:
+                    assert A[r, j] == off[i] + o, (b, r, j)
+        n = int(w["pt_off"][b + 1] - w["pt_off"][b])
+        assert len(T) == 2 * n - 2 - hull
+    dig = dt.digest()
+    for b in range(B):
+        assert int(dig[b]) == _digest(ref.block_dt(b)), b
+    with pytest.raises(K.KDTError):
+        dt.query_blocks(np.array([1, 1], np.int32))
+    dt.close()
+
+
+def test_persistent_failed_block_leaves_the_others_exact():
+    """A move with an out-of-range point index fails its block (KDT_E_ARG)
+    under the threshold policy in the persistent launch (the rebuild
+    branch's dry run returns after it laid its position hash over the
+    wavefront's scratch); the workgroups go on to other blocks, and every
+    other block still matches the oracle after every later step."""
+    K = _K()
+    w = W.selector_mix(seed=2, steps=4, small=768, large=768)
+    B = len(w["pt_off"]) - 1
+    mv = w["mv"].copy()
+    bad_b = int(np.nonzero(w["kind"] == 0)[0][3])  # a block whose points move far: rebuild branch
+    r = int(w["mv_off"][1, bad_b])
+    mv[r, 0] = 10 ** 6
+    _say(f"failed block {bad_b} of {B} in step 1, persistent launch, 1 workgroup per compute unit")
+    dt = K.KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+    dt.set_policy("threshold", tau=50.0)
+    dt.set_launch(1)
+    dt.run(torch.from_numpy(mv).to(DEV), torch.from_numpy(w["mv_off"]).to(DEV), mode="persistent")
+    with pytest.raises(K.KDTError):
+        dt.sync()
+    st = dt.block_status()
+    assert st[bad_b] == K.E_ARG and np.count_nonzero(st) == 1
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    for t in range(4):
+        ref.apply_step(w["mv"], w["mv_off"][t])
+    others = np.array([b for b in range(B) if b != bad_b], np.int32)
+    tris, _, off = dt.query_blocks(others)
+    for i, b in enumerate(others):
+        assert np.array_equal(tris[off[i]:off[i + 1]], ref.block_dt(b)), b
+    with pytest.raises(K.KDTError):
+        dt.query_blocks(np.array([bad_b], np.int32))
+    dt.close()
+
+
+def test_graph_refuses_a_changed_policy():
+    K = _K()
+    w = W.lattice256(seed=4, steps=5)
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        dt = K.KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV, stream=stream)
+        mv = torch.from_numpy(w["mv"]).to(DEV)
+        off = torch.from_numpy(w["mv_off"]).to(DEV)
+        g = dt.graph(mv, off)
+        g.launch()
+        dt.set_policy("rebuild")
+        with pytest.raises(K.KDTError) as e:
+            g.launch()
+        assert e.value.code == K.E_STATE
+        g.close()
+        dt.close()
