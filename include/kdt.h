@@ -329,7 +329,11 @@ int kdt_set_log(kdt_ctx* ctx, float* log, int64_t cap_steps);
  *   grad:    grad[0..1665] = sum over samples of d/dw 0.5*|f(x)-y|^2,
  *            grad[1666] = the summed loss (grad: dev float [1667])
  *   train:   epochs of mini-batch gradient descent on the mean gradient,
- *            w updated in place; scratch: dev float [1667] */
+ *            w updated in place; scratch: dev float [1667] (the batch's
+ *            gradient)
+ * Sums over samples are taken in a fixed order -- chunks of 64 samples in
+ * sample order, the chunks' sums added in chunk order -- with no atomics,
+ * so the results are the same floats on every run. */
 int kdt_mlp_forward(const float* w, const float* x, int64_t n, float* out, void* stream);
 int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, float* grad, void* stream);
 int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,

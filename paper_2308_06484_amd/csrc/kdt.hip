@@ -1305,38 +1305,49 @@ __global__ void k_mlp_forward(const float* __restrict__ W, const float* __restri
     for (int i = 0; i < MLP_OUT; ++i) out[s * MLP_OUT + i] = o[i];
 }
 
-// Sum over samples of the gradient of 0.5 * |out - y|^2, and of the loss,
-// added into g[0..MLP_NPARAM) and g[MLP_NPARAM].
-__global__ void k_mlp_grad(const float* __restrict__ W, const float* __restrict__ X,
-                           const float* __restrict__ Y, long long n, float* g) {
-    __shared__ float w[MLP_NPARAM];
-    __shared__ float acc[MLP_NPARAM + 1];
-    for (int i = threadIdx.x; i < MLP_NPARAM; i += blockDim.x) {
-        w[i] = W[i];
-        acc[i] = 0.f;
+// Gradient of the summed loss 0.5 * |out - y|^2 over samples [0, n), and
+// the loss: workgroup g takes chunks g, g + G, g + 2G, ... (G = gridDim.x)
+// and writes its sums, added in chunk order, to out[g * stride ..
+// g * stride + MLP_GRAD_N).  With one workgroup out holds the whole
+// gradient; with one workgroup per chunk, k_mlp_reduce adds the rows in
+// chunk order, which gives the same floats (kdt_mlp.hpp).
+__global__ void __launch_bounds__(MLP_THREADS) k_mlp_grad(const float* __restrict__ W, const float* __restrict__ X,
+                                                          const float* __restrict__ Y, long long n, float* out,
+                                                          long long stride) {
+#pragma clang fp contract(off)
+    __shared__ MlpChunkLDS L;
+    for (int i = threadIdx.x; i < MLP_NPARAM; i += MLP_THREADS) L.w[i] = W[i];
+    float acc[MLP_OWN];
+    for (int k = 0; k < MLP_OWN; ++k) acc[k] = 0.f;
+    const long long nch = (n + MLP_CHUNK - 1) / MLP_CHUNK;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        __syncthreads();  // the previous chunk's sums are done with L
+        mlp_chunk_pass(L, X, Y, n, c * MLP_CHUNK);
+        for (int k = 0; k < MLP_OWN; ++k) {
+            const int p = threadIdx.x + k * MLP_THREADS;
+            if (p < MLP_GRAD_N) acc[k] += mlp_chunk_term(L, p);
+        }
     }
-    if (threadIdx.x == 0) acc[MLP_NPARAM] = 0.f;
-    __syncthreads();
-    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) {
-        float x[MLP_IN], y[MLP_OUT];
-        for (int i = 0; i < MLP_IN; ++i) x[i] = X[s * MLP_IN + i];
-        for (int i = 0; i < MLP_OUT; ++i) y[i] = Y[s * MLP_OUT + i];
-        const float l = mlp_backward1(w, x, y, acc);
-        atomicAdd(&acc[MLP_NPARAM], l);
+    float* o = out + blockIdx.x * stride;
+    for (int k = 0; k < MLP_OWN; ++k) {
+        const int p = threadIdx.x + k * MLP_THREADS;
+        if (p < MLP_GRAD_N) o[p] = acc[k];
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= MLP_NPARAM; i += blockDim.x)
-        if (acc[i] != 0.f) atomicAdd(&g[i], acc[i]);
 }
 
-__global__ void k_fill(float* p, long long n, float v) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// total[p] = sum over rows r = 0 .. rows-1, in order, of part[r * stride + p]
+__global__ void k_mlp_reduce(const float* __restrict__ part, int rows, long long stride, float* total) {
+#pragma clang fp contract(off)
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_GRAD_N) return;
+    float a = 0.f;
+    for (int r = 0; r < rows; ++r) a += part[r * stride + p];
+    total[p] = a;
 }
 
 // W -= lr * g / n (mean gradient step)
 __global__ void k_mlp_sgd(float* W, const float* g, float lr, float inv_n) {
+#pragma clang fp contract(off)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < MLP_NPARAM) W[i] -= lr * g[i] * inv_n;
 }
@@ -2285,8 +2296,7 @@ int kdt_mlp_forward(const float* w, const float* x, int64_t n, float* out, void*
 int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, float* grad, void* stream) {
     if (!w || !grad || n < 1 || !x || !y) return KDT_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    k_fill<<<(KDT_MLP_PARAMS + 1 + 255) / 256, 256, 0, s>>>(grad, KDT_MLP_PARAMS + 1, 0.f);
-    k_mlp_grad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(w, x, y, n, grad);
+    k_mlp_grad<<<1, MLP_THREADS, 0, s>>>(w, x, y, n, grad, 0);
     return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;
 }
 
@@ -2297,9 +2307,7 @@ int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t e
     for (int32_t e = 0; e < epochs; ++e) {
         for (int64_t b0 = 0; b0 < n; b0 += batch) {
             const int64_t nb = std::min<int64_t>(batch, n - b0);
-            k_fill<<<(KDT_MLP_PARAMS + 1 + 255) / 256, 256, 0, s>>>(scratch, KDT_MLP_PARAMS + 1, 0.f);
-            k_mlp_grad<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT,
-                                                                   nb, scratch);
+            k_mlp_grad<<<1, MLP_THREADS, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT, nb, scratch, 0);
             k_mlp_sgd<<<(KDT_MLP_PARAMS + 255) / 256, 256, 0, s>>>(w, scratch, lr, 1.f / (float)nb);
         }
     }

@@ -51,38 +51,111 @@ __device__ __forceinline__ void mlp_forward1(const float* W, const float* x, flo
     }
 }
 
-// Gradient of 0.5 * sum_o (out_o - y_o)^2 for one sample, added into g
-// (shared-memory accumulator, float atomics).  Returns the sample's loss.
-__device__ __forceinline__ float mlp_backward1(const float* W, const float* x, const float* y,
-                                               float* g) {
-    float h1[MLP_H], h2[MLP_H], out[MLP_OUT], d2[MLP_H], d1[MLP_H];
-    mlp_forward1(W, x, h1, h2, out);
-    float loss = 0.f, dout[MLP_OUT];
-    for (int o = 0; o < MLP_OUT; ++o) {
-        dout[o] = out[o] - y[o];
-        loss += 0.5f * dout[o] * dout[o];
-        atomicAdd(&g[MLP_B3 + o], dout[o]);
-        for (int i = 0; i < MLP_H; ++i) atomicAdd(&g[MLP_W3 + o * MLP_H + i], dout[o] * h2[i]);
+// ---- gradient over many samples, in a fixed order (no atomics)
+//
+// The samples are taken in chunks of MLP_CHUNK.  A workgroup of
+// MLP_THREADS threads computes a chunk layer by layer in LDS (activations,
+// then the output error and the back-propagated errors), then every thread
+// sums, for the parameters it owns, the chunk's per-sample terms in sample
+// order.  A workgroup that takes several chunks adds their sums in chunk
+// order.  So the gradient of samples [0, n) is
+//   ((0 + G_0) + G_1) + ... ,  G_c = sum over the chunk's samples in order,
+// whether one workgroup runs every chunk or each chunk has its own
+// workgroup whose sums are added afterwards in chunk order: both give the
+// same floats.
+constexpr int MLP_CHUNK = 64;
+constexpr int MLP_THREADS = 256;
+constexpr int MLP_GRAD_N = MLP_NPARAM + 1;  // the gradient, then the loss
+constexpr int MLP_OWN = (MLP_GRAD_N + MLP_THREADS - 1) / MLP_THREADS;  // entries per thread
+
+struct MlpChunkLDS {
+    float w[MLP_NPARAM];
+    float x[MLP_CHUNK][MLP_IN];
+    float h1[MLP_CHUNK][MLP_H];
+    float h2[MLP_CHUNK][MLP_H];
+    float d1[MLP_CHUNK][MLP_H];
+    float d2[MLP_CHUNK][MLP_H];
+    float d3[MLP_CHUNK][MLP_OUT];
+    float y[MLP_CHUNK][MLP_OUT];
+};
+
+// The chunk starting at sample c0: per-sample activations and errors in L.
+// Samples past n contribute nothing (their errors are zero).
+__device__ __forceinline__ void mlp_chunk_pass(MlpChunkLDS& L, const float* __restrict__ X,
+                                               const float* __restrict__ Y, long long n, long long c0) {
+#pragma clang fp contract(off)
+    const int t = threadIdx.x;
+    for (int e = t; e < MLP_CHUNK * MLP_IN; e += MLP_THREADS) {
+        const long long s = c0 + e / MLP_IN;
+        L.x[e / MLP_IN][e % MLP_IN] = s < n ? X[s * MLP_IN + e % MLP_IN] : 0.f;
     }
-    for (int i = 0; i < MLP_H; ++i) {
+    for (int e = t; e < MLP_CHUNK * MLP_OUT; e += MLP_THREADS) {
+        const long long s = c0 + e / MLP_OUT;
+        L.y[e / MLP_OUT][e % MLP_OUT] = s < n ? Y[s * MLP_OUT + e % MLP_OUT] : 0.f;
+    }
+    __syncthreads();
+    for (int e = t; e < MLP_CHUNK * MLP_H; e += MLP_THREADS) {
+        const int s = e / MLP_H, j = e % MLP_H;
+        float a = L.w[MLP_B1 + j];
+        for (int i = 0; i < MLP_IN; ++i) a = fmaf(L.w[MLP_W1 + j * MLP_IN + i], L.x[s][i], a);
+        L.h1[s][j] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    for (int e = t; e < MLP_CHUNK * MLP_H; e += MLP_THREADS) {
+        const int s = e / MLP_H, j = e % MLP_H;
+        float a = L.w[MLP_B2 + j];
+        for (int i = 0; i < MLP_H; ++i) a = fmaf(L.w[MLP_W2 + j * MLP_H + i], L.h1[s][i], a);
+        L.h2[s][j] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    for (int e = t; e < MLP_CHUNK * MLP_OUT; e += MLP_THREADS) {
+        const int s = e / MLP_OUT, o = e % MLP_OUT;
+        float a = L.w[MLP_B3 + o];
+        for (int i = 0; i < MLP_H; ++i) a = fmaf(L.w[MLP_W3 + o * MLP_H + i], L.h2[s][i], a);
+        L.d3[s][o] = c0 + s < n ? a - L.y[s][o] : 0.f;
+    }
+    __syncthreads();
+    for (int e = t; e < MLP_CHUNK * MLP_H; e += MLP_THREADS) {
+        const int s = e / MLP_H, i = e % MLP_H;
         float a = 0.f;
-        for (int o = 0; o < MLP_OUT; ++o) a += W[MLP_W3 + o * MLP_H + i] * dout[o];
-        d2[i] = h2[i] > 0.f ? a : 0.f;
+        for (int o = 0; o < MLP_OUT; ++o) a = fmaf(L.w[MLP_W3 + o * MLP_H + i], L.d3[s][o], a);
+        L.d2[s][i] = L.h2[s][i] > 0.f ? a : 0.f;
     }
-    for (int j = 0; j < MLP_H; ++j) {
-        atomicAdd(&g[MLP_B2 + j], d2[j]);
-        for (int i = 0; i < MLP_H; ++i) atomicAdd(&g[MLP_W2 + j * MLP_H + i], d2[j] * h1[i]);
-    }
-    for (int i = 0; i < MLP_H; ++i) {
+    __syncthreads();
+    for (int e = t; e < MLP_CHUNK * MLP_H; e += MLP_THREADS) {
+        const int s = e / MLP_H, i = e % MLP_H;
         float a = 0.f;
-        for (int j = 0; j < MLP_H; ++j) a += W[MLP_W2 + j * MLP_H + i] * d2[j];
-        d1[i] = h1[i] > 0.f ? a : 0.f;
+        for (int j = 0; j < MLP_H; ++j) a = fmaf(L.w[MLP_W2 + j * MLP_H + i], L.d2[s][j], a);
+        L.d1[s][i] = L.h1[s][i] > 0.f ? a : 0.f;
     }
-    for (int j = 0; j < MLP_H; ++j) {
-        atomicAdd(&g[MLP_B1 + j], d1[j]);
-        for (int i = 0; i < MLP_IN; ++i) atomicAdd(&g[MLP_W1 + j * MLP_IN + i], d1[j] * x[i]);
+    __syncthreads();
+}
+
+// Sum over the chunk's samples (in order) of the term of gradient entry p
+// (p == MLP_NPARAM: the loss 0.5 |out - y|^2).
+__device__ __forceinline__ float mlp_chunk_term(const MlpChunkLDS& L, int p) {
+#pragma clang fp contract(off)
+    float a = 0.f;
+    if (p < MLP_B1) {
+        const int j = p / MLP_IN, i = p % MLP_IN;
+        for (int s = 0; s < MLP_CHUNK; ++s) a = fmaf(L.d1[s][j], L.x[s][i], a);
+    } else if (p < MLP_W2) {
+        for (int s = 0; s < MLP_CHUNK; ++s) a += L.d1[s][p - MLP_B1];
+    } else if (p < MLP_B2) {
+        const int j = (p - MLP_W2) / MLP_H, i = (p - MLP_W2) % MLP_H;
+        for (int s = 0; s < MLP_CHUNK; ++s) a = fmaf(L.d2[s][j], L.h1[s][i], a);
+    } else if (p < MLP_W3) {
+        for (int s = 0; s < MLP_CHUNK; ++s) a += L.d2[s][p - MLP_B2];
+    } else if (p < MLP_B3) {
+        const int o = (p - MLP_W3) / MLP_H, i = (p - MLP_W3) % MLP_H;
+        for (int s = 0; s < MLP_CHUNK; ++s) a = fmaf(L.d3[s][o], L.h2[s][i], a);
+    } else if (p < MLP_NPARAM) {
+        for (int s = 0; s < MLP_CHUNK; ++s) a += L.d3[s][p - MLP_B3];
+    } else {
+        for (int s = 0; s < MLP_CHUNK; ++s)
+            for (int o = 0; o < MLP_OUT; ++o) a = fmaf(0.5f * L.d3[s][o], L.d3[s][o], a);
     }
-    return loss;
+    return a;
 }
 
 }  // namespace kdt
