@@ -339,6 +339,23 @@ int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, floa
 int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
                   float lr, float* scratch, void* stream);
 
+/* kdt_mlp_train for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same training with no scratch argument and no allocation
+ * of any kind.  Its working memory is a fixed array inside the library,
+ * ~449 KB per GPU, held by each GPU it runs on until the process ends: the
+ * sums of every chunk of 64 samples of a batch (one workgroup per chunk, so
+ * a batch spreads over the GPU) and the batch's gradient.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (two streams,
+ * two threads) race.  Nothing in it needs clearing: every call writes what
+ * it reads.  The weights are the same floats kdt_mlp_train gives (the sums
+ * are added in the same order).  Arguments as for kdt_mlp_train; the stream
+ * must belong to the current device.  KDT_E_CAPACITY when batch exceeds
+ * KDT_MLP_NOALLOC_BATCH, KDT_E_ARG for a bad argument. */
+#define KDT_MLP_NOALLOC_BATCH 4096
+int kdt_mlp_train_noalloc(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                          float lr, void* stream);
+
 /* ---- Global mode: one DT* over every point ------------------------------
  * The paper lets a moved point leave its block and be sent to the
  * neighbouring block that now holds it (Sec. IV, Fig. 4), with at most one

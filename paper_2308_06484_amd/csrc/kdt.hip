@@ -16,6 +16,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1797,6 +1798,40 @@ uint64_t morton24(uint32_t x, uint32_t y) {
 
 }  // namespace
 
+// ---- scratch of kdt_mlp_train_noalloc: the per-chunk gradient sums of one
+// batch (one row of NOALLOC_ROW floats per chunk of MLP_CHUNK samples, up to
+// NOALLOC_ROWS rows: batches of at most KDT_MLP_NOALLOC_BATCH samples), then
+// the batch's gradient.  Each GPU holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel: it uses the address
+// hipGetSymbolAddress gives on the device (noalloc_scratch).
+constexpr int NOALLOC_ROWS = KDT_MLP_NOALLOC_BATCH / MLP_CHUNK;
+constexpr long long NOALLOC_ROW = (MLP_GRAD_N + 63) / 64 * 64;  // 256-byte rows
+static_assert(NOALLOC_ROWS * MLP_CHUNK == KDT_MLP_NOALLOC_BATCH, "batch limit is whole chunks");
+static __device__ __align__(256) float scratch[(NOALLOC_ROWS + 1) * NOALLOC_ROW];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+float* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current).
+int noalloc_scratch(float** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return KDT_E_DEVICE;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KDT_E_DEVICE;
+        noalloc_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = noalloc_ptr[dev];
+    return KDT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* kdt_strerror(int code) {
@@ -2301,14 +2336,35 @@ int kdt_mlp_grad(const float* w, const float* x, const float* y, int64_t n, floa
 }
 
 int kdt_mlp_train(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
-                  float lr, float* scratch, void* stream) {
-    if (!w || !x || !y || !scratch || n < 1 || epochs < 0 || batch < 1) return KDT_E_ARG;
+                  float lr, float* gbuf, void* stream) {
+    if (!w || !x || !y || !gbuf || n < 1 || epochs < 0 || batch < 1) return KDT_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     for (int32_t e = 0; e < epochs; ++e) {
         for (int64_t b0 = 0; b0 < n; b0 += batch) {
             const int64_t nb = std::min<int64_t>(batch, n - b0);
-            k_mlp_grad<<<1, MLP_THREADS, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT, nb, scratch, 0);
-            k_mlp_sgd<<<(KDT_MLP_PARAMS + 255) / 256, 256, 0, s>>>(w, scratch, lr, 1.f / (float)nb);
+            k_mlp_grad<<<1, MLP_THREADS, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT, nb, gbuf, 0);
+            k_mlp_sgd<<<(KDT_MLP_PARAMS + 255) / 256, 256, 0, s>>>(w, gbuf, lr, 1.f / (float)nb);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;
+}
+
+int kdt_mlp_train_noalloc(float* w, const float* x, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                          float lr, void* stream) {
+    if (!w || !x || !y || n < 1 || epochs < 0 || batch < 1) return KDT_E_ARG;
+    if (batch > KDT_MLP_NOALLOC_BATCH) return KDT_E_CAPACITY;
+    float* S = nullptr;
+    const int rc = noalloc_scratch(&S);
+    if (rc != KDT_OK) return rc;
+    float* total = S + (long long)NOALLOC_ROWS * NOALLOC_ROW;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t e = 0; e < epochs; ++e) {
+        for (int64_t b0 = 0; b0 < n; b0 += batch) {
+            const int64_t nb = std::min<int64_t>(batch, n - b0);
+            const int rows = (int)((nb + MLP_CHUNK - 1) / MLP_CHUNK);  // one workgroup per chunk
+            k_mlp_grad<<<rows, MLP_THREADS, 0, s>>>(w, x + b0 * MLP_IN, y + b0 * MLP_OUT, nb, S, NOALLOC_ROW);
+            k_mlp_reduce<<<(MLP_GRAD_N + 255) / 256, 256, 0, s>>>(S, rows, NOALLOC_ROW, total);
+            k_mlp_sgd<<<(KDT_MLP_PARAMS + 255) / 256, 256, 0, s>>>(w, total, lr, 1.f / (float)nb);
         }
     }
     return hipGetLastError() == hipSuccess ? KDT_OK : KDT_E_DEVICE;

@@ -30,7 +30,8 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition")
+           "kdt_partition", "kdt_mlp_train_noalloc")
+MLP_NOALLOC_BATCH = 4096
 PART = {"grid": 0, "quadtree": 1}
 
 # kdt_global_stats counters, in order
@@ -84,6 +85,7 @@ def _lib():
         L.kdt_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.kdt_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp]
         L.kdt_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, vp, vp]
+        L.kdt_mlp_train_noalloc.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, vp]
         L.kdt_stats.argtypes = [vp, ctypes.POINTER(Stats)]
         L.kdt_block_status.argtypes = [vp, vp]
         L.kdt_sync.argtypes = [vp]
@@ -180,6 +182,15 @@ def mlp_train(w, x, y, epochs, batch, lr, stream=None):
                                 ctypes.c_void_p(y.data_ptr()), x.shape[0], int(epochs), int(batch),
                                 float(lr), ctypes.c_void_p(scratch.data_ptr()), _stream_arg(stream)),
            "kdt_mlp_train")
+    return w
+
+
+def mlp_train_noalloc(w, x, y, epochs, batch, lr, stream=None):
+    """mlp_train with no device allocation (the library's fixed scratch;
+    batch <= MLP_NOALLOC_BATCH); w updated in place."""
+    _check(_lib().kdt_mlp_train_noalloc(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(y.data_ptr()), x.shape[0], int(epochs), int(batch),
+                                        float(lr), _stream_arg(stream)), "kdt_mlp_train_noalloc")
     return w
 
 
