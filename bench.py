@@ -1,19 +1,25 @@
 """Benchmark: point moves per second of the kinetic Delaunay repair on one GPU.
 
-Workload (the measured configuration): 1024 blocks -- the 32 x 32 square
-cells of side 2048 tiling [0, 65536)^2, i.e. a depth-5 quad-tree -- with
-1024 distinct uniform lattice points each (1,048,576 points), and in every
-time step one move per block of 1..8 units in one of four directions.  One
-kernel launch per time step; inputs (points, triangulations, the whole move
-stream) are resident in device memory before the timed region.
+Measured configuration (the largest single-GPU workload): multi2048 --
+2048 blocks of 4096 distinct uniform lattice points on [0,16384)^2
+(8,388,608 points); in every time step each block moves
+k = clip(Poisson(lambda_b), 1, 64) distinct points (lambda_b log-uniform
+on [1, 64], fixed per block) by Pareto(1.2) distances capped at 4096
+units, in one of four directions.  Per block and step the learned FP32
+selector (trained on the device on another seed) picks repair (delete +
+reinsert of every moved point) or rebuild; the launch form is the
+autotuner's pick on that calibration workload.  Inputs (points,
+triangulations, the whole move stream) are resident in device memory
+before the timed region.
 
-A "step" is one time step: every block deletes its moved point and
-reinserts it (Fig. 4).  `value` counts applied moves (blocked moves are not
-counted) per second of the timed region.
+A "step" is one time step of Fig. 4 over all blocks.  `value` counts
+applied moves (blocked moves are not counted) per second of the timed
+region.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-    python bench.py --copy-probe     # plain copy kernel for counter scaling
-    python bench.py --workload global4m   # global mode vs full rebuild (report)
+    python bench.py --copy-probe          # plain copy kernel for counter scaling
+    python bench.py --workload grid1024   # secondary reports (also lattice256,
+                                          # uneven4096, selector_mix, global4m)
 """
 from __future__ import annotations
 
@@ -35,11 +41,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None if the kernel sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_grid1024_traffic.json")
+    name = kernel.replace("<", "").replace(">", "")
+    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -62,23 +69,40 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes_each_way": n, "launches": 3}), flush=True)
 
 
-def cpu_baseline(w, threads, budget_s=12.0, max_steps=16):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, threads, budget_s=12.0, max_steps=16, blocks=None):
     """The CPU oracle as it stands: apply the same moves, rebuild every block
-    whose points changed from scratch; applied moves per second."""
+    (or every listed block) whose points changed from scratch, on `threads`
+    host threads; applied moves per second of the listed blocks."""
     from oracle.kinetic import Kinetic
+    from paper_2308_06484_amd import workloads as W
+    if blocks is not None:
+        w = W.subset_blocks(w, blocks, steps=max_steps)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
     t0 = time.perf_counter()
     applied, steps = 0, 0
-    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+    T = w["mv_off"].shape[0]
+    while steps < min(max_steps, T) and time.perf_counter() - t0 < budget_s:
         a = ref.apply_step(w["mv"], w["mv_off"][steps])
         ref.all_dt(threads)
         applied += int(a.sum())
         steps += 1
     dt = time.perf_counter() - t0
+    B = len(w["pt_off"]) - 1
     return dict(value=applied / dt, unit="point moves/s", cores=threads, kind="oracle",
-                sample=f"first {steps} time steps of the same stream ({applied} applied moves), "
+                sample=f"first {steps} time steps of the same stream on {B} blocks ({applied} applied moves), "
                        f"every block rebuilt from scratch by Bowyer-Watson after each step, "
-                       f"{threads} host threads over blocks")
+                       f"{threads} host thread{'s' if threads > 1 else ''} over blocks",
+                cpu_model=cpu_model())
 
 
 def time_form(w, steps, mode, graph, per_cu, dev):
@@ -128,7 +152,7 @@ def other_workload(args):
     if name == "global4m":
         global_report(args)
         return
-    if name in ("multi2048", "selector_mix"):
+    if name == "selector_mix":
         gen = W.multi2048 if name == "multi2048" else W.selector_mix
         cal_steps = 8
         ev_steps = args.other_steps or 10
@@ -232,40 +256,16 @@ def global_report(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=980)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fused", action="store_true", help="time the fused multi-step launch instead")
-    ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms")
-    ap.add_argument("--workload", default="grid1024",
-                    choices=["grid1024", "lattice256", "uneven4096", "multi2048", "selector_mix", "global4m"],
-                    help="grid1024 is the measured configuration; the others print a secondary report")
-    ap.add_argument("--other-steps", type=int, default=0, help="steps for --workload other than grid1024")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(blocks are independent: sharding them over GPUs needs no exchange)",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.copy_probe:
-        copy_probe()
-        return
-    if args.workload != "grid1024":
-        other_workload(args)
-        return
-
+def grid_report(args):
+    """grid1024 (1024 blocks x 1024 points, one move per block per step): the
+    launch forms, one kernel launch per step by default (secondary report)."""
     import numpy as np
     import torch
 
     from paper_2308_06484_amd import workloads as W
     from paper_2308_06484_amd.kdt import KineticDT
 
-    K, Wu = args.steps, args.warmup
+    K, Wu = args.other_steps or 980, args.warmup
     log(f"generating grid1024 with {K + Wu} steps")
     w = W.grid1024(seed=args.seed, steps=K + Wu)
     dev = torch.device("cuda:0")
@@ -416,7 +416,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_run_fused" if args.fused else "k_step"),
+            "traffic": measured_traffic("k_run_fused" if args.fused else "k_step", "grid1024"),
             "kernel": "k_run_fused" if args.fused else "k_step",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg / n_launch,
@@ -428,6 +428,228 @@ def main():
         log(f"cpu baseline (oracle) on {threads} threads")
         res["cpu_baseline"] = cpu_baseline(w, threads)
     print(json.dumps(res), flush=True)
+
+
+
+HEADLINE_FORMS = (
+    {"mode": "step", "graph": False},
+    {"mode": "step", "graph": True},
+    *({"mode": "step", "graph": g, "waves": nw} for nw in (2, 4) for g in (False, True)),
+    *({"mode": "persistent", "graph": False, "per_cu": pc} for pc in (2, 4, 8)),
+    {"mode": "fused", "graph": False},
+)
+CAL_STEPS = 6
+
+
+def form_name(f):
+    n = {"step": "per_step", "persistent": "persistent", "fused": "fused"}[f["mode"]]
+    if f.get("per_cu"):
+        n += f"_{f['per_cu']}wg"
+    if f.get("waves", 1) > 1:
+        n += f"_{f['waves']}waves"
+    return n + ("_graph" if f.get("graph") else "")
+
+
+def timed_run(w, mv, off_warm, off_timed, form, policy, dev, period=0):
+    """One fresh context: warm-up steps, then the timed steps under one
+    launch form and policy ((name, tau, mlp_w)), HIP events on the
+    library's stream around the timed region.  Returns the region's
+    milliseconds and the counters before and after."""
+    import torch
+
+    from paper_2308_06484_amd.kdt import KineticDT
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev, stream=stream)
+        dt.set_policy(*policy)
+        if form.get("per_cu"):
+            dt.set_launch(form["per_cu"])
+        if form.get("waves", 1) > 1:
+            dt.set_block_waves(form["waves"])
+        if off_warm is not None and off_warm.shape[0]:
+            dt.run(mv, off_warm, mode=form["mode"])
+        dt.sync()
+        g = dt.graph(mv, off_timed, mode=form["mode"]) if form.get("graph") else None
+        stream.synchronize()
+        s0 = dt.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if g is not None:
+            g.launch()
+        else:
+            dt.run(mv, off_timed, mode=form["mode"])
+        e1.record(stream)
+        stream.synchronize()
+        dt.sync()
+        s1 = dt.stats()
+        if g is not None:
+            g.close()
+        dt.close()
+    return e0.elapsed_time(e1), s0, s1
+
+
+def headline(args):
+    import numpy as np
+    import torch
+
+    from paper_2308_06484_amd import autotune as A
+    from paper_2308_06484_amd import selector as S
+    from paper_2308_06484_amd import workloads as W
+    dev = "cuda:0"
+    K, Wu = args.steps, args.warmup
+    # the selector: trained on the device on a calibration workload of
+    # another seed (forced-repair and forced-rebuild runs give both costs)
+    t0 = time.perf_counter()
+    cal = W.multi2048(seed=100 + args.seed, steps=CAL_STEPS)
+    X, Y = S.collect(cal, CAL_STEPS, dev)
+    mlp = torch.from_numpy(S.train(X, Y, epochs=200, batch=2048, lr=0.02, device=dev)).to(dev)
+    tau = S.calibrate_threshold(X, Y)
+    log(f"selector trained on {len(X)} block-steps of seed {100 + args.seed} "
+        f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.2f}")
+    pol_mlp = ("mlp", 0.0, mlp)
+    best = A.autotune(cal, steps=CAL_STEPS, candidates=HEADLINE_FORMS, device=dev, use_cache=False,
+                      policy=pol_mlp)
+    form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves") if k in best}
+    log("autotuner (calibration workload, MLP policy): " + ", ".join(
+        f"{form_name(r)} {r['s_per_step'] * 1e3:.3f} ms" for r in best["table"]) + f" -> {form_name(form)}")
+    del cal
+    t0 = time.perf_counter()
+    w = W.multi2048(seed=args.seed, steps=Wu + K)
+    log(f"multi2048 seed {args.seed}, {Wu} warm-up + {K} timed steps generated in {time.perf_counter() - t0:.1f} s")
+    mv = torch.from_numpy(w["mv"]).to(dev)
+    off_all = torch.from_numpy(w["mv_off"]).to(dev)
+    off_warm = off_all[:Wu].contiguous()
+    off_timed = off_all[Wu:Wu + K].contiguous()
+
+    ms, s0, s1 = timed_run(w, mv, off_warm, off_timed, form, pol_mlp, dev)
+    applied = s1["applied"] - s0["applied"]
+    blocked = s1["blocked"] - s0["blocked"]
+    alg = s1["alg_bytes"] - s0["alg_bytes"]
+    touched = s1["tri_touched"] - s0["tri_touched"]
+    rebuilt = s1["rebuilt"] - s0["rebuilt"]
+    value = applied / (ms / 1e3)
+    log(f"headline ({form_name(form)}, MLP): {ms:.2f} ms for {K} steps, {value:.4e} moves/s, "
+        f"{applied} applied, {blocked} blocked, {rebuilt} block-steps rebuilt")
+
+    variants = {}
+    if not args.no_variants:
+        runs = [(form_name(f) + "_mlp", f, pol_mlp, K) for f in HEADLINE_FORMS if f != form]
+        runs += [(form_name(form) + "_repair_only", form, ("repair", 0.0, None), K),
+                 ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
+                 (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
+                 ("per_step_rebuild_only", {"mode": "step", "graph": False}, ("rebuild", 0.0, None), min(10, K))]
+        for name, f, pol, steps in runs:
+            if name in variants:
+                continue
+            vms, a0, a1 = timed_run(w, mv, off_warm, off_timed[:steps].contiguous(), f, pol, dev)
+            napp = a1["applied"] - a0["applied"]
+            variants[name] = {"moves_per_s": napp / (vms / 1e3), "ms_per_step": vms / steps, "steps": steps,
+                              "rebuilt_block_steps": a1["rebuilt"] - a0["rebuilt"]}
+            log(f"variant {name}: {vms / steps:.3f} ms/step, {napp / (vms / 1e3):.4e} moves/s")
+
+    # roofline of the step: the timed region spans K launches of the form's
+    # step kernel (one launch in the fused form), so its average duration is
+    # the region over the launches, gaps and the selector's follow-up
+    # launches included: an upper bound of the kernel's own duration
+    n_launch = 1 if form["mode"] == "fused" else K
+    kernel = {"step": "k_step", "persistent": "k_step_persist", "fused": "k_run_fused"}[form["mode"]]
+    if form.get("waves", 1) > 1:
+        kernel = f"k_step_mw<{form['waves']}>"
+    avg_launch_s = ms / 1e3 / n_launch
+    achieved = alg / n_launch / avg_launch_s / 1e9
+    khz = max(1, s1["clock_khz"])
+    phases = {ph: (s1["t_" + ph] - s0["t_" + ph]) / khz * 1e3 / max(1, applied)
+              for ph in ("star", "locate", "hole", "insert")}
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point moves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wu,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "multi2048: 2048 blocks x 4096 distinct uniform lattice points on [0,16384)^2, "
+                        "per block and time step k = clip(Poisson(lambda_b), 1, 64) movers (lambda_b "
+                        "log-uniform on [1,64]) by Pareto(1.2) distances capped at 4096, 4 directions; "
+                        "per-block repair-or-rebuild choice by the FP32 MLP 16-32-32-2 trained on the "
+                        f"device on seed {100 + args.seed}; launch form {form_name(form)} (autotuner)",
+            "blocks": 2048,
+            "points_per_block": 4096,
+            "moves_per_step": round((applied + blocked) / K),
+            "seed": args.seed,
+        },
+        "applied_moves": applied,
+        "blocked_moves": blocked,
+        "rebuilt_block_steps": rebuilt,
+        "variants": variants,
+        "phase_us_per_move": phases,
+        "mtri_touched_per_s": touched / (ms / 1e3) / 1e6,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kernel, "multi2048"),
+            "kernel": kernel,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "alg_bytes_per_launch": alg / n_launch,
+            "timed_launches": n_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        log(f"cpu baseline (oracle) on {threads} threads, all blocks")
+        res["cpu_baseline"] = cpu_baseline(w, threads, budget_s=12.0, max_steps=16)
+        # the paper's comparison with the serial form: one thread against
+        # all of them, on the same 64 blocks
+        sub = np.arange(0, 2048, 32)
+        log("cpu baseline: serial form (1 thread) and all threads on 64 blocks")
+        ser = cpu_baseline(w, 1, budget_s=6.0, max_steps=16, blocks=sub)
+        par = cpu_baseline(w, threads, budget_s=6.0, max_steps=16, blocks=sub)
+        res["cpu_baseline"]["serial_form"] = {"value": ser["value"], "cores": 1, "sample": ser["sample"]}
+        res["cpu_baseline"]["parallel_same_sample"] = {"value": par["value"], "cores": threads,
+                                                       "sample": par["sample"]}
+        log(f"cpu: {res['cpu_baseline']['value']:.4e} moves/s on {threads} threads; serial form "
+            f"{ser['value']:.4e}, {threads} threads {par['value']:.4e} on 64 blocks")
+    print(json.dumps(res), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused", action="store_true", help="grid1024 report: time the fused launch instead")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other launch forms and policies")
+    ap.add_argument("--workload", default="multi2048",
+                    choices=["multi2048", "grid1024", "lattice256", "uneven4096", "selector_mix", "global4m"],
+                    help="multi2048 is the measured configuration; the others print a secondary report")
+    ap.add_argument("--other-steps", type=int, default=0, help="steps for the secondary reports")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(blocks are independent: sharding them over GPUs needs no exchange)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.workload == "multi2048":
+        headline(args)
+    elif args.workload == "grid1024":
+        grid_report(args)
+    else:
+        other_workload(args)
 
 
 if __name__ == "__main__":

@@ -205,6 +205,24 @@ int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
  * the LDS of an MI355X compute unit holds 5 step workgroups). */
 int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
 
+/* Wavefronts per block of the per-step launch (KDT_RUN_PER_STEP): 1
+ * (default: one wavefront applies the block's moves one after another), 2
+ * or 4.  With more than one, the wavefronts of a block's workgroup share
+ * its moves (Fig. 4, Update/Delete/Insert per block; several moves per
+ * block at once, as many moves per step allow): the moves whose source and
+ * target cells no other move of the block's step names commute with every
+ * move, and run in reservation rounds -- each wavefront plans one without
+ * writing, claims every triangle its plan read, and the plans whose claims
+ * no lower move index contests are written; the others plan again -- and
+ * the remaining moves (sharing a cell with another, beyond the rounds'
+ * capacities, or of a block taking the rebuild branch, or all of a block
+ * whose step moves some point more than once) follow one after another in
+ * list order, in a second launch.  Same triangulations and
+ * applied flags as one wavefront.  The per-step log then records, for a
+ * block, the rounds' ticks; the rest launch logs blocks all of whose moves
+ * it ran.  KDT_E_ARG for another count, KDT_E_STATE in global mode. */
+int kdt_set_block_waves(kdt_ctx* ctx, int32_t waves);
+
 /* The same n_steps steps captured once as a HIP graph and replayed by
  * kdt_graph_launch (each replay applies the same move stream again, from the
  * state it finds).  The context's stream must not be the null stream.  The
@@ -372,7 +390,8 @@ int kdt_mlp_train_noalloc(float* w, const float* x, const float* y, int64_t n, i
  * by any point at that moment.  Moves with no cell in common with another
  * move of the step run concurrently (reservation rounds on the triangles
  * their plans read); the others, and moves still contended after the
- * rounds, run afterwards in list order.  The triangulation after each step
+ * rounds, run afterwards in list order; a step that moves some point more
+ * than once runs wholly in list order.  The triangulation after each step
  * is DT* of the positions the sequential rule gives.
  *
  * Query, digest, positions, stats and sync work as for one block holding

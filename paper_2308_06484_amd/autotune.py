@@ -1,7 +1,8 @@
 """Launch-shape autotuner for the per-step paths of libkdt.
 
 Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
-one kernel per step, the persistent launch with 1..8 workgroups per
+one kernel per step with 1, 2 or 4 wavefronts per block (the workgroup
+size), the persistent launch with 1..8 workgroups per
 compute unit (the LDS of an MI355X compute unit holds 5), each either launched step by step or captured as a HIP graph,
 and the fused multi-step launch.  Every candidate computes the same
 triangulations (tests check this bit for bit), so the choice only changes
@@ -23,6 +24,7 @@ from .kdt import KineticDT
 DEFAULT_CANDIDATES = (
     {"mode": "step", "graph": False},
     {"mode": "step", "graph": True},
+    *({"mode": "step", "graph": g, "waves": nw} for nw in (2, 4) for g in (False, True)),
     *({"mode": "persistent", "graph": g, "per_cu": pc} for pc in (1, 2, 4, 5, 8) for g in (False, True)),
     {"mode": "fused", "graph": False},
 )
@@ -40,13 +42,18 @@ def signature(w):
             f"|moves_per_step={mps:.0f}")
 
 
-def time_candidate(w, cand, steps, device="cuda:0"):
-    """Seconds per time step of one candidate on a fresh context."""
+def time_candidate(w, cand, steps, device="cuda:0", policy=None):
+    """Seconds per time step of one candidate on a fresh context (policy:
+    None, or (name, tau, mlp_w) as for KineticDT.set_policy)."""
     stream = torch.cuda.Stream(device=device)
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=device)
+        if policy is not None:
+            dt.set_policy(*policy)
         if cand.get("per_cu"):
             dt.set_launch(cand["per_cu"])
+        if cand.get("waves", 1) > 1:
+            dt.set_block_waves(cand["waves"])
         mv = torch.from_numpy(w["mv"]).to(device)
         off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:steps])).to(device)
         g = dt.graph(mv, off, mode=cand["mode"]) if cand["graph"] else None
@@ -65,11 +72,12 @@ def time_candidate(w, cand, steps, device="cuda:0"):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def autotune(w, steps=100, candidates=DEFAULT_CANDIDATES, device="cuda:0", use_cache=True):
+def autotune(w, steps=100, candidates=DEFAULT_CANDIDATES, device="cuda:0", use_cache=True, policy=None):
     """Best launch form for workloads shaped like `w` (a calibration
-    workload).  Returns {"mode", "graph", "per_cu"?, "s_per_step", "table"}."""
+    workload), under `policy` (None: repair; else (name, tau, mlp_w)).
+    Returns {"mode", "graph", "per_cu"?, "s_per_step", "table"}."""
     name = torch.cuda.get_device_name(torch.device(device))
-    key = f"{name}|{signature(w)}|steps={steps}"
+    key = f"{name}|{signature(w)}|steps={steps}|policy={policy[0] if policy else 'repair'}"
     path = cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -81,7 +89,7 @@ def autotune(w, steps=100, candidates=DEFAULT_CANDIDATES, device="cuda:0", use_c
             return cache[key]
     table = []
     for cand in candidates:
-        table.append(dict(cand, s_per_step=time_candidate(w, cand, steps, device)))
+        table.append(dict(cand, s_per_step=time_candidate(w, cand, steps, device, policy)))
     best = dict(min(table, key=lambda r: r["s_per_step"]))
     best["table"] = table
     if use_cache:

@@ -537,6 +537,41 @@ __device__ __forceinline__ int choose_branch(const DevState& s, const float* f) 
     return o1 < o0 ? 1 : 0;
 }
 
+// The block's 16 features for this step (whole wavefront; every lane gets
+// them), from its size, frame and the distances of moves m0 .. m1-1:
+//   0 log2 n          1 k (moves)        2 log2(1+k)        3 sum d/s
+//   4 log2(1+sum d/s) 5 max d/s          6 log2(1+max d/s)  7 mean d/s
+//   8 #(d > s)        9 #(d > 4s)       10 100 k/n         11 sum (d/s)^2 / k
+//  12 log2(1+sum d/s) * log2(1+k)       13 log2 s          14 log2(1+k) / log2 n
+//  15 1                                  (s = sqrt(frame area / n), d = distance)
+__device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t* mv, int m0, int m1, float* f) {
+    const int lane = lane_id();
+    const int k = m1 - m0;
+    const float area = (float)(fr.z - fr.x) * (float)(fr.w - fr.y);
+    const float sp = sqrtf(area / (float)n);
+    float sum = 0.f, mx = 0.f, sq = 0.f, c1 = 0.f, c4 = 0.f;
+    for (int m = m0 + lane; m < m1; m += WAVE) {
+        const float r = (float)mv[m].dist / sp;
+        sum += r;
+        mx = fmaxf(mx, r);
+        sq += r * r;
+        c1 += r > 1.f ? 1.f : 0.f;
+        c4 += r > 4.f ? 1.f : 0.f;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+        sq += __shfl_xor(sq, off);
+        c1 += __shfl_xor(c1, off);
+        c4 += __shfl_xor(c4, off);
+    }
+    const float ln = log2f((float)n), lk = log2f(1.f + (float)k);
+    f[0] = ln; f[1] = (float)k; f[2] = lk; f[3] = sum; f[4] = log2f(1.f + sum);
+    f[5] = mx; f[6] = log2f(1.f + mx); f[7] = sum / (float)k; f[8] = c1; f[9] = c4;
+    f[10] = 100.f * (float)k / (float)n; f[11] = sq / (float)k; f[12] = f[4] * lk;
+    f[13] = log2f(sp); f[14] = lk / ln; f[15] = 1.f;
+}
+
 __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
                                 const BlockHead& h, int8_t* applied, long long step, bool defer, char* dynx) {
     BlockView B;
@@ -558,30 +593,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     float f[MLP_IN];
     int branch = 0;
     if (need_f) {
-        // features from this step's move distances (wave reduction)
-        const float area = (float)(fr.z - fr.x) * (float)(fr.w - fr.y);
-        const float sp = sqrtf(area / (float)B.n);
-        float sum = 0.f, mx = 0.f, sq = 0.f, c1 = 0.f, c4 = 0.f;
-        for (int m = m0 + lane; m < m1; m += WAVE) {
-            const float r = (float)mv[m].dist / sp;
-            sum += r;
-            mx = fmaxf(mx, r);
-            sq += r * r;
-            c1 += r > 1.f ? 1.f : 0.f;
-            c4 += r > 4.f ? 1.f : 0.f;
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            sum += __shfl_xor(sum, off);
-            mx = fmaxf(mx, __shfl_xor(mx, off));
-            sq += __shfl_xor(sq, off);
-            c1 += __shfl_xor(c1, off);
-            c4 += __shfl_xor(c4, off);
-        }
-        const float ln = log2f((float)B.n), lk = log2f(1.f + (float)k);
-        f[0] = ln; f[1] = (float)k; f[2] = lk; f[3] = sum; f[4] = log2f(1.f + sum);
-        f[5] = mx; f[6] = log2f(1.f + mx); f[7] = sum / (float)k; f[8] = c1; f[9] = c4;
-        f[10] = 100.f * (float)k / (float)B.n; f[11] = sq / (float)k; f[12] = f[4] * lk;
-        f[13] = log2f(sp); f[14] = lk / ln; f[15] = 1.f;
+        block_features(B.n, fr, mv, m0, m1, f);
         branch = choose_branch(s, f);
         if (k > DRYMAX) branch = 0;  // more moves than the dry run holds: repair
     }
@@ -702,7 +714,10 @@ __global__ void __launch_bounds__(WAVE) k_step_persist(DevState s, const kdt_mov
 //      hash of the step's cells.  A move whose cells are named by no other
 //      move of the step commutes with all of them: its target is held at its
 //      turn in list order exactly when it is held at the start of the step.
-//      The other ("interacting") moves wait for the ordered pass;
+//      The other ("interacting") moves wait for the ordered pass.  This holds
+//      when every point moves at most once in the step (a second move of a
+//      point starts at a cell no start-of-step position names): a step that
+//      moves a point twice goes wholly to the ordered pass;
 //   2. rounds of k_g_plan / k_g_commit (deterministic reservations): a
 //      wavefront plans its move without writing (apply_move, MV_PLAN) and
 //      claims every triangle slot the plan read with an atomic maximum of
@@ -725,8 +740,8 @@ constexpr int GB_CHUNK = 1 << 17;     // points the grid-wide builder plans at o
 constexpr int GB_BIG = 1 << 14;       // cavity capacity of a deferred point's attempt
 constexpr int GB_DEFER = 1 << 16;     // deferred points of one build
 constexpr int GB_ROUNDS = 64;         // rounds of one chunk before its points are deferred
-// g.ctr entries (entry 1 unused)
-constexpr int GC_STAMP = 0, GC_SERIAL = 2, GC_USED = 3, GC_PEND = 4, GC_DEFER = 5,
+// g.ctr entries
+constexpr int GC_STAMP = 0, GC_REPEAT = 1, GC_SERIAL = 2, GC_USED = 3, GC_PEND = 4, GC_DEFER = 5,
               GC_KIDX = 6, GC_N = 16;
 
 struct GlobalDev {
@@ -780,6 +795,9 @@ __device__ __forceinline__ unsigned long long stamp_of(int round, int prio) {
 __device__ __forceinline__ unsigned long long cell_key(int2 p) {
     return (((unsigned long long)(unsigned)p.x << 24) | (unsigned)p.y) + 1ull;
 }
+// A point's key in the same hash (above every cell key): counts the moves
+// of the step that move it.
+__device__ __forceinline__ unsigned long long point_key(int p) { return (1ull << 56) + (unsigned)p + 1ull; }
 __device__ __forceinline__ int cell_slot(unsigned long long k, int mask) {
     return (int)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask;
 }
@@ -881,6 +899,7 @@ __global__ void k_g_prep(DevState s, GlobalDev g, const kdt_move_t* __restrict__
         int2 q;
         cell_add(g, cell_key(o));
         if (move_target(o, r.dir, r.dist, s.frame[0], &q)) cell_add(g, cell_key(q));
+        cell_add(g, point_key(r.point));
     }
     g.rsn[m] = 0;
     if (applied) applied[m] = 0;
@@ -892,6 +911,10 @@ __global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restri
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || g.mstate[m] != MS_PEND) return;
     const kdt_move_t r = mv[m];
+    // a point moved twice in the step: its second move starts where the
+    // first ended, a cell the hash does not name -- the whole step runs in
+    // list order (the ordered pass)
+    if (cell_count(g, point_key(r.point)) > 1) g.ctr[GC_REPEAT] = 1;
     const int2 o = s.xy[r.point];
     int2 q;
     if (!move_target(o, r.dir, r.dist, s.frame[0], &q)) {  // outside the domain: blocked
@@ -917,6 +940,9 @@ __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
             g.hcnt[h] = 0;
         }
     }
+    // a step that moves a point twice runs wholly in the ordered pass: no
+    // plan, so the last round hands every pending move on
+    if (g.ctr[GC_REPEAT]) return;
     // a fixed grid strides over the step's moves (later rounds have few left)
     for (int m = blockIdx.x; m < M; m += gridDim.x) {
         if (g.mstate[m] != MS_PEND || s.status[0] != 0) continue;
@@ -1148,8 +1174,342 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
     stats_flush(s, S);
     if (lane == 0) {
         g.ctr[GC_SERIAL] = 0;
+        g.ctr[GC_REPEAT] = 0;
         g.ctr[GC_STAMP] += G_ROUNDS;  // past this step's rounds
     }
+}
+
+// ------------------------------------------------------------------ several wavefronts per block
+// A block's moves in one time step, shared by the NW wavefronts of one
+// workgroup (per-step launch with block_waves = NW > 1).  A step of a block
+// with k moves is otherwise as long as k moves one after another on one
+// wavefront, and the blocks with the most moves set the step's length.
+//
+// When no point moves twice in the block's step, the moves whose source and
+// target cells are named by no other move of the step commute with every
+// other move: each is blocked exactly when its target cell is held at the
+// start of the step, whatever the order, and changes no cell another move
+// names.  (A point that moves twice starts its second move where the first
+// ended, which no start-of-step cell tells: such a block runs its moves in
+// list order.)
+// They are applied in reservation rounds: each wavefront takes the next
+// pending one (in list order), plans it without writing (apply_move in plan
+// mode: the star, every record the repair reads, the walk's path, all in
+// the wavefront's table), and claims every slot it read in an LDS hash with
+// its move index; after a barrier, a plan whose every slot is claimed by no
+// lower move index commits (its table goes to memory) -- the winners have
+// disjoint read sets, and every record a move writes is one it read, so
+// nothing a winner read has changed -- and the others plan again in the next
+// round.  The lowest pending move always wins.  Every other move (moves that
+// share a cell with another, a plan beyond the plan or table capacities,
+// every move of a block that takes the rebuild branch or has more moves than
+// DRYMAX) goes, in list order, to the block's rest list, which k_step_rest
+// applies after the rounds one after another (the sequential path).  The
+// commuting moves commute with them too, so the result is the sequential
+// rule's, and DT* (unique) is the same triangulation.
+constexpr int MW_MAX_WAVES = 4;
+constexpr int MW_HASH = 2048;  // claim hash entries: holds every slot of MW_MAX_WAVES plans
+static_assert(MW_HASH >= MW_MAX_WAVES * RSMAX, "claim hash smaller than the plans of one round");
+constexpr int MWS_PEND = 0, MWS_DONE = 1, MWS_REST = 2;
+constexpr int REST_ALL = -1;  // rest count of a block deferred whole
+
+// The rest lists: per block up to DRYMAX moves (copies, list order) with
+// their index in the step's move array; applied flags land in rest_app.
+struct RestBuf {
+    kdt_move_t* mv;  // [B][DRYMAX]
+    int* idx;        // [B][DRYMAX]
+    int8_t* app;     // [B][DRYMAX]
+    int* cnt;        // [B]
+};
+
+template <int NW>
+struct MwLDS {
+    WaveLDS S[NW];
+    BlockStats pst[NW];        // the counters of each wavefront's current plan
+    int hkey[MW_HASH];         // slot, or -1
+    int hprio[MW_HASH];        // lowest move index claiming it
+    int mstate[DRYMAX];        // MWS_* per move of the step (offset from m0)
+    int list[DRYMAX];          // pending commuting moves, list order
+    int2 cs[DRYMAX], ct[DRYMAX];  // source and target cells (ct.x < 0: target outside the frame)
+    int pt[DRYMAX];            // moved point
+    int outcome[NW];
+    int np, defer_all, fail, nrest;
+    float f[MLP_IN];
+};
+
+__device__ __forceinline__ int mw_home(int slot) { return (int)(((unsigned)slot * 0x9E3779B1u) >> 21); }
+
+// Slot i of a plan's read set: the star, then the table's entries, then the
+// walk's path.
+__device__ __forceinline__ int mw_read_slot(const WaveLDS& S, const MovePlan& pl, int i) {
+    return i < pl.k ? S.star_slot[i] : (i < pl.k + pl.used ? S.tkey[S.tused[i - pl.k]] : S.wpath[i - pl.k - pl.used]);
+}
+
+static_assert(sizeof(MwLDS<4>) <= 160 * 1024, "four wavefronts' scratch exceeds a compute unit's LDS");
+
+template <int NW>
+__global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_move_t* __restrict__ mv,
+                                                       const int* __restrict__ off, int8_t* applied,
+                                                       long long step, RestBuf rb) {
+    extern __shared__ __align__(16) char dyn[];
+    MwLDS<NW>& M = *reinterpret_cast<MwLDS<NW>*>(dyn);
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    constexpr int NT = NW * WAVE;
+    const BlockHead h = load_head(s, b, off);
+    if (head_skip(h)) return;  // uniform over the workgroup
+    BlockView B;
+    B.tri = s.tri + h.toff;
+    B.xy = s.xy + h.p0;
+    B.vtri = s.vtri + h.p0;
+    B.n = (int)(h.p1 - h.p0);
+    B.ntri = 2 * B.n - 2;
+    const int4 fr = h.fr;
+    const int m0 = h.m0, k = h.m1 - h.m0;
+    constexpr int NF = sizeof(BlockStats) / sizeof(long long);
+    WaveLDS& S = M.S[w];
+    table_clear(S);
+    if (lane < NF) reinterpret_cast<long long*>(&S.st)[lane] = 0;
+    if (tid == 0) {
+        M.defer_all = k > DRYMAX ? 1 : 0;
+        M.fail = ST_OK;
+    }
+    for (int i = tid; i < MW_HASH; i += NT) {
+        M.hkey[i] = -1;
+        M.hprio[i] = 0x7fffffff;
+    }
+    const bool need_f = s.policy != KDT_POLICY_REPAIR || s.log;
+    __syncthreads();
+    if (need_f && !M.defer_all && w == 0) {
+        float f[MLP_IN];
+        block_features(B.n, fr, mv, m0, h.m1, f);
+        const int br = choose_branch(s, f);
+        if (lane == 0) {
+            if (br != 0) M.defer_all = 1;  // the rebuild branch runs in k_step_rest
+            for (int i = 0; i < MLP_IN; ++i) M.f[i] = f[i];
+        }
+    }
+    __syncthreads();
+    const long long c0 = wall_clock64();
+    if (!M.defer_all) {
+        // the moves' cells at the start of the step
+        for (int i = tid; i < k; i += NT) {
+            const kdt_move_t r = mv[m0 + i];
+            const bool bad = r.point < 0 || r.point >= B.n || r.dir < 0 || r.dir > 3 || r.dist < 1;
+            int2 o = make_int2(-1, -1 - i), q = make_int2(-1, -1);
+            if (!bad) {
+                o = B.xy[r.point];
+                if (!move_target(o, r.dir, r.dist, fr, &q)) q = make_int2(-1, -1);
+            } else {
+                M.defer_all = 1;  // the sequential path reports the error
+            }
+            M.pt[i] = bad ? -1 - i : r.point;
+            M.cs[i] = o;
+            M.ct[i] = q;
+        }
+        __syncthreads();
+        for (int i = tid; i < k; i += NT) {
+            const int2 a = M.cs[i], t = M.ct[i];
+            bool inter = false, again = false;
+            for (int j = 0; j < k; ++j) {
+                if (j == i) continue;
+                const int2 a2 = M.cs[j], t2 = M.ct[j];
+                again |= M.pt[j] == M.pt[i];
+                inter |= same(a, a2) || (t.x >= 0 && (same(t, a2) || same(t, t2))) || (t2.x >= 0 && same(a, t2));
+            }
+            M.mstate[i] = inter ? MWS_REST : MWS_PEND;
+            // a point that moves twice starts its second move where the first
+            // ended, a cell the cells above do not name: the block's moves all
+            // run in list order
+            if (again) M.defer_all = 1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int np = 0;
+            for (int i = 0; i < k; ++i)
+                if (M.mstate[i] == MWS_PEND) M.list[np++] = i;
+            M.np = np;
+        }
+    }
+    __syncthreads();
+    // reservation rounds over the commuting moves
+    while (!M.defer_all && M.np > 0 && M.fail == ST_OK) {
+        const int np = M.np;
+        const int i = w < np ? M.list[w] : -1;  // offset of this wavefront's move
+        MovePlan pl{};
+        int app = 0, rc = ST_OK, total = 0;
+        if (i >= 0) {
+            if (lane < NF) reinterpret_cast<long long*>(&M.pst[w])[lane] = 0;
+            wsync();
+            rc = apply_move(B, S, mv[m0 + i], fr, &M.pst[w], &app, MV_PLAN, &pl);
+            if (rc == ST_OK && app == 2) {
+                total = pl.k + pl.used + pl.npath;
+                if (pl.npath > WPMAX || total > RSMAX) {
+                    rc = ST_CAPACITY;  // too large to reserve: the sequential path takes it
+                } else {
+                    for (int e = lane; e < total; e += WAVE) {
+                        const int slot = mw_read_slot(S, pl, e);
+                        int hh = mw_home(slot);
+                        for (int t = 0; t < MW_HASH; ++t) {
+                            const int old = atomicCAS(&M.hkey[hh], -1, slot);
+                            if (old == -1 || old == slot) {
+                                atomicMin(&M.hprio[hh], i);
+                                break;
+                            }
+                            hh = (hh + 1) & (MW_HASH - 1);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        int outc = -1;  // 0 blocked, 1 won, 2 lost, 3 rest, < 0 error
+        if (i >= 0) {
+            if (rc == ST_CAPACITY) {
+                outc = 3;
+            } else if (rc != ST_OK) {
+                outc = rc;
+            } else if (app == 0) {
+                outc = 0;
+            } else {
+                bool held = true;
+                for (int e = lane; e < total; e += WAVE) {
+                    const int slot = mw_read_slot(S, pl, e);
+                    int hh = mw_home(slot);
+                    for (int t = 0; t < MW_HASH && M.hkey[hh] != slot; ++t) hh = (hh + 1) & (MW_HASH - 1);
+                    held &= M.hprio[hh] == i;
+                }
+                outc = ballot(!held) ? 2 : 1;
+            }
+        }
+        __syncthreads();  // every wavefront has read the claims
+        for (int e = tid; e < MW_HASH; e += NT) {
+            M.hkey[e] = -1;
+            M.hprio[e] = 0x7fffffff;
+        }
+        if (outc == 1) {
+            commit(B, S, pl.used, pl.nvt_del, pl.nvt);
+            if (lane == 0) {
+                B.xy[mv[m0 + i].point] = pl.q;
+                if (applied) applied[m0 + i] = 1;
+                const BlockStats& P = M.pst[w];
+                S.st.star_sum += P.star_sum;
+                S.st.cavity_sum += P.cavity_sum;
+                S.st.walk_sum += P.walk_sum;
+                S.st.tri_touched += P.tri_touched + pl.npath;
+                // move record, own position read and written, walk records
+                S.st.alg_bytes += P.alg_bytes + 32 + 64LL * pl.npath;
+                S.st.applied += 1;
+                S.st.fast += pl.fast;
+            }
+        } else if (i >= 0) {
+            if (app == 2) table_drop(S, pl.used);
+            else table_clear(S);
+            if (outc == 0 && lane == 0) {
+                if (applied) applied[m0 + i] = 0;
+                S.st.blocked += M.pst[w].blocked;
+                S.st.walk_sum += M.pst[w].walk_sum;
+            }
+        }
+        if (lane == 0) M.outcome[w] = i >= 0 ? outc : 2;
+        __syncthreads();  // commits done, outcomes known
+        if (tid == 0) {
+            int n = 0;
+            for (int j = 0; j < np; ++j) {
+                const int mi = M.list[j];
+                const int o = j < NW ? M.outcome[j] : 2;
+                if (o == 2) {
+                    M.list[n++] = mi;
+                } else if (o == 3) {
+                    M.mstate[mi] = MWS_REST;
+                } else if (o < 0) {
+                    if (M.fail == ST_OK) M.fail = o;
+                } else {
+                    M.mstate[mi] = MWS_DONE;
+                }
+            }
+            M.np = n;
+        }
+        __syncthreads();
+    }
+    const long long c1 = wall_clock64();
+    // the rest list, in list order (a block deferred whole keeps its moves
+    // where they are: REST_ALL)
+    if (tid == 0) {
+        int n = 0;
+        if (M.fail == ST_OK && !M.defer_all)
+            for (int i = 0; i < k; ++i)
+                if (M.mstate[i] == MWS_REST) {
+                    rb.idx[(long long)b * DRYMAX + n] = m0 + i;
+                    ++n;
+                }
+        M.nrest = n;
+        rb.cnt[b] = M.fail == ST_OK && M.defer_all ? REST_ALL : n;
+    }
+    __syncthreads();
+    for (int j = tid; j < M.nrest; j += NT) {
+        const int m = rb.idx[(long long)b * DRYMAX + j];
+        rb.mv[(long long)b * DRYMAX + j] = mv[m];
+    }
+    if (M.fail != ST_OK && tid == 0) {
+        s.status[b] = M.fail;
+        atomicMin(s.sticky, M.fail);
+    }
+    // counters: each wavefront adds its own
+    wsync();
+    if (lane < NF) {
+        const long long v = reinterpret_cast<const long long*>(&S.st)[lane];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b]) + lane, (unsigned long long)v);
+    }
+    if (M.fail != ST_OK && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b].errors), 1ull);
+    // the log: features, branch (repair) and the rounds' ticks; a block whose
+    // moves all went to the rest list is logged by k_step_rest
+    if (need_f && s.log && s.log_cap > 0 && !M.defer_all && k > 0 && tid < LOG_FIELDS) {
+        float* rec = s.log + ((step % s.log_cap) * (long long)s.n_blocks + b) * LOG_FIELDS;
+        float v = 0.f;
+        if (tid < MLP_IN) v = M.f[tid];
+        else if (tid == 17) v = (float)(c1 - c0);
+        else if (tid == 18) v = (float)k;
+        rec[tid] = v;
+    }
+}
+
+// The rest lists of a step (one wavefront per block): the moves the rounds
+// left, in list order, by the sequential path (repair or rebuild branch); a
+// block deferred whole runs its step's moves from the move array itself.
+__global__ void __launch_bounds__(WAVE) k_step_rest(DevState s, const kdt_move_t* __restrict__ mv,
+                                                    const int* __restrict__ off, RestBuf rb, int8_t* applied,
+                                                    long long step) {
+    __shared__ WaveLDS S;
+    extern __shared__ __align__(16) char dynx[];
+    const int b = blockIdx.x;
+    const int cnt = rb.cnt[b];
+    if (cnt == 0) return;
+    if (cnt == REST_ALL) {
+        const BlockHead h = load_head(s, b, off);
+        if (!head_skip(h)) {
+            scratch_init(S);
+            run_block_moves(s, S, b, mv, h, applied, step, true, dynx);
+        }
+    } else {
+        BlockHead h;
+        h.status = s.status[b];
+        h.m0 = b * DRYMAX;
+        h.m1 = h.m0 + cnt;
+        h.p0 = s.pt_off[b];
+        h.p1 = s.pt_off[b + 1];
+        h.toff = s.tri_off[b];
+        h.fr = s.frame[b];
+        if (!head_skip(h)) {
+            scratch_init(S);
+            run_block_moves(s, S, b, rb.mv, h, rb.app, step, true, dynx);
+            gsync();
+            if (applied)
+                for (int j = lane_id(); j < cnt; j += WAVE)
+                    applied[rb.idx[(long long)b * DRYMAX + j]] = rb.app[(long long)b * DRYMAX + j];
+        }
+    }
+    if (lane_id() == 0) rb.cnt[b] = 0;
 }
 
 // ---- grid-wide builder: the rounds of the block builder with every chunk
@@ -1435,7 +1795,8 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
-        qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, total;
+        qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, rest_mv, rest_idx, rest_app, rest_cnt,
+        total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -1465,6 +1826,10 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_app = take((size_t)std::max(max_staged, 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
+    L.rest_mv = take(sizeof(kdt_move_t) * (size_t)B * DRYMAX);
+    L.rest_idx = take(sizeof(int) * (size_t)B * DRYMAX);
+    L.rest_app = take((size_t)B * DRYMAX);
+    L.rest_cnt = take(sizeof(int) * B);
     L.total = o;
     return L;
 }
@@ -1565,6 +1930,8 @@ struct kdt_ctx {
     long long step_count = 0;  // time steps launched so far (log index)
     long long epoch = 0;       // changes of policy, log or launch shape (graphs record theirs)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
+    int block_waves = 1;     // wavefronts per block of the per-step launch (1, 2 or 4)
+    RestBuf rest{};          // rest lists of the multi-wavefront launch
     bool timing = false;
     int timing_period = 1;        // launches one event pair spans
     long long timing_count = 0;   // launches covered by closed pairs since timing was enabled
@@ -1657,13 +2024,28 @@ int step_lds_limit() {
     static int bytes = -1;
     if (bytes < 0) {
         bool ok = true;
-        for (const void* k : {(const void*)k_step, (const void*)k_step_persist, (const void*)k_run_fused})
+        for (const void* k : {(const void*)k_step, (const void*)k_step_persist, (const void*)k_run_fused,
+                              (const void*)k_step_rest})
             ok = ok && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, STEP_LDS_EXTRA_MAX) ==
                            hipSuccess;
         (void)hipGetLastError();
         bytes = ok ? STEP_LDS_EXTRA_MAX : 0;
     }
     return bytes;
+}
+
+// The multi-wavefront step kernels take more than the default 64 KB of
+// dynamic LDS: allowed once per process.
+bool mw_lds_ok() {
+    static int ok = -1;
+    if (ok < 0) {
+        ok = hipFuncSetAttribute((const void*)k_step_mw<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(MwLDS<4>)) == hipSuccess &&
+             hipFuncSetAttribute((const void*)k_step_mw<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sizeof(MwLDS<2>)) == hipSuccess;
+        (void)hipGetLastError();
+    }
+    return ok == 1;
 }
 
 // Largest LDS need of a block build above `above` and within `limit` (0 if none).
@@ -2052,6 +2434,11 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     rc |= check_hip(c, hipMemsetAsync(w + L.rb_flag, 0, sizeof(int) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.rest_cnt, 0, sizeof(int) * n_blocks, s));
+    c->rest.mv = (kdt_move_t*)(w + L.rest_mv);
+    c->rest.idx = (int*)(w + L.rest_idx);
+    c->rest.app = (int8_t*)(w + L.rest_app);
+    c->rest.cnt = (int*)(w + L.rest_cnt);
     {
         // block order of the persistent launch: largest blocks first
         std::vector<int> lpt(n_blocks);
@@ -2212,11 +2599,21 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
     for (int32_t t = 0; t < n_steps; ++t) {
         const int32_t* off = step_off + (int64_t)t * (c->B + 1);
         hipEvent_t e0 = timed ? timing_begin(c) : nullptr;
-        if (flags == KDT_RUN_PERSISTENT)
+        if (flags == KDT_RUN_PERSISTENT) {
             k_step_persist<<<grid, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
                                                                        c->B, applied, c->step_count);
-        else
+        } else if (c->block_waves > 1) {
+            if (c->block_waves == 4)
+                k_step_mw<4><<<c->B, 4 * WAVE, sizeof(MwLDS<4>), c->stream>>>(c->dev, moves, off, applied,
+                                                                             c->step_count, c->rest);
+            else
+                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), c->stream>>>(c->dev, moves, off, applied,
+                                                                             c->step_count, c->rest);
+            k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, c->rest, applied,
+                                                                    c->step_count);
+        } else {
             k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count);
+        }
         if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
             k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
                                                                               c->pb_lds_follow);
@@ -2251,6 +2648,15 @@ int kdt_run(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, int32_
 int kdt_set_launch(kdt_ctx* c, int32_t persist_per_cu) {
     if (!c || persist_per_cu < 1 || persist_per_cu > 64) return KDT_E_ARG;
     c->persist_per_cu = persist_per_cu;
+    c->epoch++;
+    return KDT_OK;
+}
+
+int kdt_set_block_waves(kdt_ctx* c, int32_t waves) {
+    if (!c || (waves != 1 && waves != 2 && waves != 4)) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    if (waves > 1 && !mw_lds_ok()) return KDT_E_DEVICE;
+    c->block_waves = waves;
     c->epoch++;
     return KDT_OK;
 }

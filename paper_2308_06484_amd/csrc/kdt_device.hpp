@@ -144,7 +144,7 @@ __device__ __forceinline__ int* pb_lds_of(WaveLDS& S) { return reinterpret_cast<
 
 // ---------------------------------------------------------------- wave ops
 
-__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 __device__ __forceinline__ int lanes_below(uint64_t m) { return __popcll(m & lanemask_lt()); }

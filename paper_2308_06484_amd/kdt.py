@@ -30,7 +30,7 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc")
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves")
 MLP_NOALLOC_BATCH = 4096
 PART = {"grid": 0, "quadtree": 1}
 
@@ -94,6 +94,7 @@ def _lib():
         L.kdt_timing.argtypes = [vp, i32]
         L.kdt_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.kdt_set_launch.argtypes = [vp, i32]
+        L.kdt_set_block_waves.argtypes = [vp, i32]
         L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
         L.kdt_graph_launch.argtypes = [vp, vp]
         L.kdt_graph_destroy.argtypes = [vp]
@@ -310,6 +311,10 @@ class KineticDT:
 
     def set_launch(self, persist_per_cu):
         _check(_lib().kdt_set_launch(self.ctx, int(persist_per_cu)), "kdt_set_launch")
+
+    def set_block_waves(self, waves):
+        """Wavefronts per block of the per-step launch (1, 2 or 4)."""
+        _check(_lib().kdt_set_block_waves(self.ctx, int(waves)), "kdt_set_block_waves")
 
     def graph(self, moves, step_off, applied=None, mode="step"):
         """Capture the move stream's steps as a HIP graph (needs a non-null

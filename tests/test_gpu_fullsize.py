@@ -25,7 +25,7 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label=""):
+def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label="", waves=1):
     """Run w's first T steps one step per call; after every step compare the
     applied flags and a rotating subset of SUBSET blocks; at the end, all."""
     from paper_2308_06484_amd.kdt import KineticDT
@@ -33,6 +33,8 @@ def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0,
     dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
     if policy:
         dt.set_policy(policy, tau, mlp_w)
+    if waves > 1:
+        dt.set_block_waves(waves)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
     perm = np.random.default_rng(seed).permutation(B).astype(np.int32)
     mv = torch.from_numpy(w["mv"]).to(DEV)

@@ -144,3 +144,21 @@ def test_global4m_full_size():
     assert np.array_equal(G.positions(), K.xy)
     assert np.array_equal(G.owner(), K.owner())
     assert np.array_equal(G.query_canonical(), K.dt())
+
+
+def test_global_point_moved_twice_in_a_step():
+    """A point that moves twice in one step starts its second move where the
+    first ended: here that cell is the start of another point's move that
+    shares no start-of-step cell with any move.  In list order the second
+    move is blocked (the cell is still held); the step must run in list
+    order to see it."""
+    rng = np.random.default_rng(8)
+    core = [(4, 2), (2, 1), (7, 7)]
+    pts = set(core)
+    while len(pts) < 40:
+        pts.add((int(rng.integers(0, 16)), int(rng.integers(0, 16))))
+    xy = np.array(core + sorted(pts - set(core)), np.int32)
+    mv = np.array([[0, 3, 1, 0], [0, 1, 2, 0], [1, 2, 3, 0], [5, 0, 1, 0]], np.int32)
+    w = dict(xy=xy, side=16, depth=1, mv=mv, step_off=np.array([0, 4], np.int64))
+    G, K = run_compare(w, 1)
+    assert K.xy[0].tolist() == [4, 1] and K.xy[1].tolist() == [2, 4]
