@@ -457,10 +457,12 @@ def timed_run(w, mv, off_warm, off_timed, form, policy, dev, period=0):
     milliseconds and the counters before and after."""
     import torch
 
+    from paper_2308_06484_amd import selector as S
     from paper_2308_06484_amd.kdt import KineticDT
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev, stream=stream)
+        dt.dcalc(S.DCALC_N)  # d of the initial positions: the selector's feature 15, the d-limit rule
         dt.set_policy(*policy)
         if form.get("per_cu"):
             dt.set_launch(form["per_cu"])
@@ -537,6 +539,7 @@ def headline(args):
         runs += [(form_name(form) + "_repair_only", form, ("repair", 0.0, None), K),
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
+                 (form_name(form) + "_dlimit", form, ("dlimit", 1.0, None), K),
                  ("per_step_rebuild_only", {"mode": "step", "graph": False}, ("rebuild", 0.0, None), min(10, K))]
         for name, f, pol, steps in runs:
             if name in variants:
@@ -546,6 +549,28 @@ def headline(args):
             variants[name] = {"moves_per_s": napp / (vms / 1e3), "ms_per_step": vms / steps, "steps": steps,
                               "rebuilt_block_steps": a1["rebuilt"] - a0["rebuilt"]}
             log(f"variant {name}: {vms / steps:.3f} ms/step, {napp / (vms / 1e3):.4e} moves/s")
+
+    # the paper's d-calculation and N-spread (Sec. III) of the evaluation
+    # workload's initial and final positions, with the kernel's time
+    dcal = {}
+    if not args.no_variants:
+        from paper_2308_06484_amd.kdt import KineticDT
+        stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(stream):
+            dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev, stream=stream)
+            first = dt.dcalc(S.DCALC_N)
+            dt.run(mv, off_all)
+            t0 = time.perf_counter()
+            last = dt.dcalc(S.DCALC_N)
+            secs = time.perf_counter() - t0
+            dt.close()
+        dcal = {"N": S.DCALC_N, "mindistance_start": float(np.sqrt(first["d2_now"])),
+                "mindistance_end": float(np.sqrt(last["d2_now"])), "d": float(np.sqrt(last["d2"])),
+                "max_n_spread": float(last["spread"].max()), "median_n_spread": float(np.median(last["spread"])),
+                "dcalc_ms": secs * 1e3}
+        log(f"d-calculation (N = {S.DCALC_N}): mindistance {dcal['mindistance_start']:.2f} at the start, "
+            f"{dcal['mindistance_end']:.2f} after {Wu + K} steps, d = {dcal['d']:.2f}, N-spread up to "
+            f"{dcal['max_n_spread']:.1f}; {secs * 1e3:.2f} ms per call")
 
     # roofline of the step: the timed region spans K launches of the form's
     # step kernel (one launch in the fused form), so its average duration is
@@ -588,6 +613,7 @@ def headline(args):
         "blocked_moves": blocked,
         "rebuilt_block_steps": rebuilt,
         "variants": variants,
+        "d_calculation": dcal,
         "phase_us_per_move": phases,
         "mtri_touched_per_s": touched / (ms / 1e3) / 1e6,
         "roofline": {

@@ -286,6 +286,25 @@ int kdt_query_blocks(kdt_ctx* ctx, const int32_t* blocks, int32_t count, int32_t
  * give equal digests; used to compare runs cheaply. */
 int kdt_digest(kdt_ctx* ctx, uint64_t* host_per_block);
 
+/* d-calculation (Sec. III, "Notation and definitions"; Sec. IV; Sec. V):
+ * for the current positions and a constant N (1 .. 8), the squared distance
+ * of every point to its N-th nearest neighbour among the points of its
+ * block (the blocks are independent), and its minimum over the block --
+ * mindistance(P_i)^2 -- written to host_mind2 (host int64 [n_blocks] or
+ * NULL; INT64_MAX for a block of at most N points); the block's squared
+ * diameter to host_diam2 (host int64 [n_blocks] or NULL); the minimum over
+ * all blocks, mindistance(P_t)^2, to *d2_now (taken on the device, one
+ * atomic minimum per block: the paper's tree minimum); d^2, the minimum of
+ * mindistance(P_t)^2 over the calls made with this N, to *d2_min; and every
+ * block's N-spread diam(P_i) / mindistance(P_t), kept at its largest over
+ * those calls, to host_spread (host double [n_blocks] or NULL).  A new N
+ * starts a new history.  Every comparison is of exact integer squared
+ * distances.  Synchronises.  KDT_E_ARG for N outside 1 .. 8; KDT_E_CAPACITY
+ * when a point's search needs more than 64 candidates (a vertex of very
+ * high degree). */
+int kdt_dcalc(kdt_ctx* ctx, int32_t N, int64_t* host_mind2, int64_t* host_diam2, int64_t* d2_now,
+              int64_t* d2_min, double* host_spread);
+
 /* Current positions: host int32 [n][2] (synchronises). */
 int kdt_positions(kdt_ctx* ctx, int32_t* host_xy);
 
@@ -319,6 +338,10 @@ int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
  *   MLP        rebuild iff the network's predicted log2 cost of rebuilding is
  *              below that of repairing; mlp_w: dev float [KDT_MLP_PARAMS],
  *              must stay valid while used
+ *   DLIMIT     rebuild iff some move of the block goes farther than tau * d,
+ *              d the paper's limited distance (Sec. III: points are assumed
+ *              to move at most d per step, else rebuilding is better) as the
+ *              latest kdt_dcalc left it; repair while no kdt_dcalc was made
  * A block with more than 256 moves in one step is repaired whatever the
  * policy (the rebuild branch checks at most 256 moves per block and step).
  * The network: 16 features -> 32 ReLU -> 32 ReLU -> 2, parameters laid out
@@ -327,6 +350,7 @@ int kdt_timing_read(kdt_ctx* ctx, double* total_ms, int64_t* launches);
 #define KDT_POLICY_REBUILD 1
 #define KDT_POLICY_THRESHOLD 2
 #define KDT_POLICY_MLP 3
+#define KDT_POLICY_DLIMIT 4
 #define KDT_MLP_PARAMS 1666
 int kdt_set_policy(kdt_ctx* ctx, int32_t policy, float tau, const float* mlp_w);
 
@@ -335,7 +359,7 @@ int kdt_set_policy(kdt_ctx* ctx, int32_t policy, float tau, const float* mlp_w);
  * fields 0..15 the block's features for the step (log2 n, k, log2(1+k),
  * sum d/s, log2(1+sum d/s), max d/s, log2(1+max d/s), mean d/s, #(d>s),
  * #(d>4s), 100k/n, sum (d/s)^2/k, log2(1+sum d/s)*log2(1+k), log2 s,
- * log2(1+k)/log2 n, 1), 16 branch taken (0 repair, 1 rebuild, 2 repair that
+ * log2(1+k)/log2 n, max d / d of the latest kdt_dcalc (0 if none)), 16 branch taken (0 repair, 1 rebuild, 2 repair that
  * hit the repair path's capacity and finished the step by rebuilding: no
  * clean cost of either branch), 17 device clock ticks the branch took,
  * 18 k.  Steps without moves are not logged. */

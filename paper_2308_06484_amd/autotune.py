@@ -49,6 +49,8 @@ def time_candidate(w, cand, steps, device="cuda:0", policy=None):
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=device)
         if policy is not None:
+            from .selector import DCALC_N
+            dt.dcalc(DCALC_N)  # as in the runs the selector was trained on
             dt.set_policy(*policy)
         if cand.get("per_cu"):
             dt.set_launch(cand["per_cu"])

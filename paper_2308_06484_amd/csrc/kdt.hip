@@ -1,9 +1,10 @@
 // libkdt: kinetic Delaunay triangulation of moving lattice points on MI355X.
 //
 // Kernels (one 64-lane wavefront per block of the partition, Sec. IV):
-//   k_build_blocks  every block's DT* from scratch (or the blocks flagged
-//                for the rebuild branch), the threads of a workgroup inserting
-//                in parallel (kdt_pbuild.hpp); the starting state of Fig. 4
+//   k_build_blocks  every block's DT* from scratch, the threads of a
+//                workgroup inserting in parallel (kdt_pbuild.hpp); the
+//                starting state of Fig. 4 (k_build_listed: the blocks the
+//                rebuild branch left for after a step)
 //   k_step       one time step: for each block, its moves in order, each a
 //                walk to the target, Delete, Insert (Fig. 4)
 //   k_run_fused  all steps of a move stream; blocks are independent, so each
@@ -13,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -51,10 +53,11 @@ struct DevState {
     const int* order;  // per-block insertion order (Hilbert order at init)
     int* owner;        // one int per triangle slot: cavity claims of the parallel build
     int* own2;         // one int per triangle slot: boundary claims of the parallel build
-    int* rb_flag;      // per block: rebuild after this step (set by the dry run)
+    int* rb_list;      // blocks to rebuild after this step: [0] count, [1] finished builders, [2..] blocks
     const float* mlp_w;  // MLP parameters (policy MLP)
     long long log_cap;   // steps the log holds (ring)
     float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
+    float dlim;          // d of the latest d-calculation (0: none yet): feature 15, the d-limit rule
     int n_blocks;
     BlockStats* stats;
     float* log;  // per step and block: LOG_FIELDS floats, or null
@@ -119,15 +122,12 @@ __host__ __device__ constexpr size_t pb_block_lds(long long n) {
     return (size_t)(2 * n - 2) * (sizeof(Tri) + 2 * sizeof(int)) + sizeof(int) * (size_t)n;
 }
 
-// Build every block's DT* (only_flagged = 0: the starting state) or those
-// the rebuild branch flagged in this step (only_flagged = 1), one workgroup
-// per block.  A block whose working state fits in `lds_bytes` of dynamic
-// LDS is built there and written back; a larger one is built in place.
-__global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int only_flagged, long long step,
-                                                             int lds_bytes) {
-    extern __shared__ __align__(16) char dyn[];
-    const int b = blockIdx.x;
-    if (only_flagged && s.rb_flag[b] == 0) return;
+// Build block b's DT* with the PB_THREADS threads of a workgroup: in
+// `lds_bytes` of dynamic LDS when its working state fits there (written
+// back at the end), else in place.  flagged: a block the rebuild branch
+// left for after the step (its cost goes into the step log).
+__device__ __forceinline__ void build_block(const DevState& s, int b, bool flagged, long long step, int lds_bytes,
+                                            char* dyn) {
     const long long c0 = wall_clock64();
     BlockView G = view_of(s, b);
     int* lds = reinterpret_cast<int*>(dyn);
@@ -146,11 +146,36 @@ __global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int onl
     }
     const int rc = pbuild_block(G, s.order + s.pt_off[b], M, lds);
     if (rc != ST_OK) fail_block(s, b, rc);
-    if (only_flagged && threadIdx.x == 0) {
-        s.rb_flag[b] = 0;
+    if (flagged && threadIdx.x == 0) {
         // the branch's cost in the step log includes the build
         if (s.log && s.log_cap > 0)
             s.log[((step % s.log_cap) * (long long)s.n_blocks + b) * LOG_FIELDS + 17] += (float)(wall_clock64() - c0);
+    }
+}
+
+// Every block's DT* from scratch (the starting state), one workgroup each.
+__global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int lds_bytes) {
+    extern __shared__ __align__(16) char dyn[];
+    build_block(s, blockIdx.x, false, 0, lds_bytes, dyn);
+}
+
+// The blocks the rebuild branch of this step listed (too large to build in
+// the step kernel): a fixed grid (a few workgroups per compute unit) strides
+// over the list; the last workgroup to finish empties it for the next step.
+__global__ void __launch_bounds__(PB_THREADS) k_build_listed(DevState s, long long step, int lds_bytes) {
+    extern __shared__ __align__(16) char dyn[];
+    const int cnt = s.rb_list[0];
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        build_block(s, s.rb_list[2 + i], true, step, lds_bytes, dyn);
+        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&s.rb_list[1], 1) == (int)gridDim.x - 1) {
+            s.rb_list[0] = 0;
+            s.rb_list[1] = 0;
+        }
     }
 }
 
@@ -390,7 +415,7 @@ __device__ void ph_build(unsigned long long* T, const int2* xy, int n) {
 // DT* is rebuilt from scratch.
 // The build: here, by this one wavefront, with the block's working state in
 // the kernel's dynamic LDS `dynx` when it fits (s.step_lds bytes); else left
-// to k_build_blocks (defer: the block is flagged) or done here in place.
+// to k_build_listed (defer: the block is listed) or done here in place.
 __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv, int m0,
                                    int m1, int8_t* applied, BlockStats* st, bool defer, char* dynx) {
     BlockView B = view_of(s, b);
@@ -483,7 +508,7 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
     }
     const bool in_lds = pb_block_lds(B.n) <= (size_t)s.step_lds;
     if (defer && !in_lds) {
-        if (lane == 0) s.rb_flag[b] = 1;
+        if (lane == 0) s.rb_list[2 + atomicAdd(&s.rb_list[0], 1)] = b;
         table_clear(S);
         return ST_OK;
     }
@@ -511,6 +536,9 @@ __device__ __forceinline__ int dry_run_and_rebuild(const DevState& s, WaveLDS& S
 __device__ __forceinline__ int choose_branch(const DevState& s, const float* f) {
     if (s.policy == KDT_POLICY_REBUILD) return 1;
     if (s.policy == KDT_POLICY_THRESHOLD) return f[3] > s.tau ? 1 : 0;
+    // the paper's limited distance (Sec. III): a block whose move goes
+    // farther than tau * d is rebuilt
+    if (s.policy == KDT_POLICY_DLIMIT) return f[15] > s.tau ? 1 : 0;
     if (s.policy != KDT_POLICY_MLP || !s.mlp_w) return 0;
     // 16 -> 32 -> 32 -> 2: hidden unit j on lane j, inputs broadcast
     const int lane = lane_id();
@@ -543,8 +571,10 @@ __device__ __forceinline__ int choose_branch(const DevState& s, const float* f) 
 //   4 log2(1+sum d/s) 5 max d/s          6 log2(1+max d/s)  7 mean d/s
 //   8 #(d > s)        9 #(d > 4s)       10 100 k/n         11 sum (d/s)^2 / k
 //  12 log2(1+sum d/s) * log2(1+k)       13 log2 s          14 log2(1+k) / log2 n
-//  15 1                                  (s = sqrt(frame area / n), d = distance)
-__device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t* mv, int m0, int m1, float* f) {
+//  15 max distance / d, d of the latest d-calculation (0 if none)
+//                                        (s = sqrt(frame area / n), d = distance)
+__device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t* mv, int m0, int m1, float dlim,
+                                               float* f) {
     const int lane = lane_id();
     const int k = m1 - m0;
     const float area = (float)(fr.z - fr.x) * (float)(fr.w - fr.y);
@@ -569,7 +599,7 @@ __device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t*
     f[0] = ln; f[1] = (float)k; f[2] = lk; f[3] = sum; f[4] = log2f(1.f + sum);
     f[5] = mx; f[6] = log2f(1.f + mx); f[7] = sum / (float)k; f[8] = c1; f[9] = c4;
     f[10] = 100.f * (float)k / (float)n; f[11] = sq / (float)k; f[12] = f[4] * lk;
-    f[13] = log2f(sp); f[14] = lk / ln; f[15] = 1.f;
+    f[13] = log2f(sp); f[14] = lk / ln; f[15] = dlim > 0.f ? mx * sp / dlim : 0.f;
 }
 
 __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
@@ -593,7 +623,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     float f[MLP_IN];
     int branch = 0;
     if (need_f) {
-        block_features(B.n, fr, mv, m0, m1, f);
+        block_features(B.n, fr, mv, m0, m1, s.dlim, f);
         branch = choose_branch(s, f);
         if (k > DRYMAX) branch = 0;  // more moves than the dry run holds: repair
     }
@@ -1282,7 +1312,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     __syncthreads();
     if (need_f && !M.defer_all && w == 0) {
         float f[MLP_IN];
-        block_features(B.n, fr, mv, m0, h.m1, f);
+        block_features(B.n, fr, mv, m0, h.m1, s.dlim, f);
         const int br = choose_branch(s, f);
         if (lane == 0) {
             if (br != 0) M.defer_all = 1;  // the rebuild branch runs in k_step_rest
@@ -1760,6 +1790,124 @@ __global__ void __launch_bounds__(WAVE) k_qwrite(DevState s, const int* list, co
     }
 }
 
+// ------------------------------------------------------------------ d-calculation
+// Sec. III ("Notation and definitions"), Sec. IV: for a constant N, the
+// distance of every point to its N-th nearest neighbour, its minimum over
+// the block (mindistance), the minimum over all blocks; and the block's
+// diameter for its N-spread.  One wavefront per block, one point per lane.
+//
+// The N nearest neighbours come from the triangulation: the (i+1)-th
+// nearest neighbour of p is a DT neighbour of p or of one of its i nearest
+// (the nearest-neighbour search along Delaunay edges of Dickerson, Drysdale
+// and Sack), so a best-first search -- take the closest candidate not yet
+// taken, add its DT neighbours -- takes them in order; every comparison is
+// of exact integer squared distances.
+constexpr int DC_CAP = 64;   // candidates one point's search holds
+constexpr int DC_NMAX = 8;   // largest N
+constexpr long long DC_NONE = 0x7fffffffffffffffll;
+
+__device__ __forceinline__ long long d2_of(int2 a, int2 b) {
+    const long long dx = (long long)a.x - b.x, dy = (long long)a.y - b.y;
+    return dx * dx + dy * dy;
+}
+
+struct DcLDS {
+    int id[DC_CAP][WAVE];        // candidate points (lane-contiguous)
+    long long d2[DC_CAP][WAVE];  // their squared distances (-1: taken)
+    int hull[1024];              // hull vertices of the block (diameter)
+    int nhull;
+};
+
+__global__ void __launch_bounds__(WAVE) k_dcalc(DevState s, int N, long long* mind2, long long* diam2,
+                                                unsigned long long* gmin, int* err) {
+    __shared__ DcLDS L;
+    const int b = blockIdx.x, lane = lane_id();
+    const BlockView B = view_of(s, b);
+    long long best = DC_NONE;
+    bool over = false;
+    for (int p = lane; p < B.n && N < B.n; p += WAVE) {
+        const int2 pp = B.xy[p];
+        int nc = 0;
+        long long last = DC_NONE;
+        int v = p;
+        for (int it = 0; it < N; ++it) {
+            // the DT neighbours of v (a closed fan: ghosts close it at the hull)
+            const int t0 = B.vtri[v];
+            int cur = t0;
+            for (int g = 0; g < 4 * KMAX && !over; ++g) {
+                if (bad_slot(B, cur)) { over = true; break; }
+                const Tri t = load_tri(B.tri + cur);
+                const int i = t.v.x == v ? 0 : (t.v.y == v ? 1 : 2);
+                const int u = vget(t.v, (i + 1) % 3);
+                if (u != GHOST && u != p) {
+                    bool seen = false;
+                    for (int c = 0; c < nc && !seen; ++c) seen = L.id[c][lane] == u;
+                    if (!seen) {
+                        if (nc == DC_CAP) {
+                            over = true;
+                        } else {
+                            L.id[nc][lane] = u;
+                            L.d2[nc][lane] = d2_of(pp, cget(t, (i + 1) % 3));
+                            ++nc;
+                        }
+                    }
+                }
+                cur = vget(t.n, (i + 2) % 3) >> 2;
+                if (cur == t0) break;
+            }
+            if (over) break;
+            // the closest candidate not taken yet (ties: smaller id) is the
+            // (it+1)-th nearest neighbour: a neighbour of p or of one of the
+            // it nearest, whose neighbours are all candidates by now
+            int j = -1;
+            for (int c = 0; c < nc; ++c) {
+                const long long dc = L.d2[c][lane];
+                if (dc < 0) continue;
+                if (j < 0 || dc < L.d2[j][lane] || (dc == L.d2[j][lane] && L.id[c][lane] < L.id[j][lane])) j = c;
+            }
+            if (j < 0) { over = true; break; }
+            last = L.d2[j][lane];
+            L.d2[j][lane] = -1;
+            v = L.id[j][lane];
+        }
+        if (!over) best = min(best, last);
+    }
+    for (int off = 32; off > 0; off >>= 1) best = min(best, (long long)__shfl_xor(best, off));
+    // diameter: the farthest pair lies on the convex hull; hull vertices are
+    // the finite corners of the ghosts
+    if (lane == 0) L.nhull = 0;
+    wsync();
+    for (int i = lane; i < B.ntri; i += WAVE) {
+        const Tri t = load_tri(B.tri + i);
+        if (t.v.z == GHOST) {
+            const int h = atomicAdd(&L.nhull, 1);
+            if (h < 1024) L.hull[h] = t.v.x;
+        }
+    }
+    wsync();
+    const int nh = L.nhull;
+    long long dmax = 0;
+    if (nh <= 1024) {
+        for (int a = lane; a < nh; a += WAVE) {
+            const int2 pa = B.xy[L.hull[a]];
+            for (int c = 0; c < nh; ++c) dmax = max(dmax, d2_of(pa, B.xy[L.hull[c]]));
+        }
+    } else {  // more hull vertices than the list holds: every pair of points
+        for (int a = lane; a < B.n; a += WAVE) {
+            const int2 pa = B.xy[a];
+            for (int c = 0; c < B.n; ++c) dmax = max(dmax, d2_of(pa, B.xy[c]));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (long long)__shfl_xor(dmax, off));
+    const bool bad = ballot(over) != 0;
+    if (lane == 0) {
+        mind2[b] = bad ? DC_NONE : best;
+        diam2[b] = dmax;
+        if (bad) atomicAdd(err, 1);
+        else if (best != DC_NONE) atomicMin(gmin, (unsigned long long)best);
+    }
+}
+
 // Order-independent digest of a block's triangulation: the wrapping sum,
 // over its real triangles rotated to start at their smallest global id
 // (a, b, c), of mix(a ^ mix(b ^ mix(c))), mix = splitmix64's finaliser.
@@ -1796,7 +1944,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
         qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, rest_mv, rest_idx, rest_app, rest_cnt,
-        total;
+        dc_mind2, dc_diam2, dc_g, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -1815,7 +1963,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stats = take(sizeof(BlockStats) * B);
     L.qmap = take(sizeof(int) * ntri);
     L.own2 = take(sizeof(int) * ntri);
-    L.rb_flag = take(sizeof(int) * B);
+    L.rb_flag = take(sizeof(int) * (B + 2));
     L.qcount = take(sizeof(int) * B);
     L.qoff = take(sizeof(long long) * (B + 1));
     L.qtris = take(sizeof(int) * 3 * ntri);
@@ -1830,6 +1978,9 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.rest_idx = take(sizeof(int) * (size_t)B * DRYMAX);
     L.rest_app = take((size_t)B * DRYMAX);
     L.rest_cnt = take(sizeof(int) * B);
+    L.dc_mind2 = take(sizeof(long long) * B);
+    L.dc_diam2 = take(sizeof(long long) * B);
+    L.dc_g = take(sizeof(unsigned long long) * 2);
     L.total = o;
     return L;
 }
@@ -1932,6 +2083,11 @@ struct kdt_ctx {
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     int block_waves = 1;     // wavefronts per block of the per-step launch (1, 2 or 4)
     RestBuf rest{};          // rest lists of the multi-wavefront launch
+    // d-calculation over time (kdt_dcalc): running minimum of the squared
+    // mindistance, every block's running maximum N-spread, for one N
+    int dc_n = 0;
+    long long dc_d2 = 0x7fffffffffffffffll;
+    std::vector<double> dc_spread;
     bool timing = false;
     int timing_period = 1;        // launches one event pair spans
     long long timing_count = 0;   // launches covered by closed pairs since timing was enabled
@@ -2008,7 +2164,9 @@ int pb_lds_bytes() {
     static int bytes = -1;
     if (bytes < 0) {
         bytes = hipFuncSetAttribute((const void*)k_build_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    PB_LDS_BYTES) == hipSuccess
+                                    PB_LDS_BYTES) == hipSuccess &&
+                        hipFuncSetAttribute((const void*)k_build_listed, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            PB_LDS_BYTES) == hipSuccess
                     ? PB_LDS_BYTES
                     : 64 * 1024;
         (void)hipGetLastError();
@@ -2060,7 +2218,7 @@ size_t max_block_need(const kdt_ctx* c, size_t above, size_t limit) {
 
 // Launch sizes for the rebuild branch under the current policy: the step
 // kernels get room to build the largest block that fits their extra LDS;
-// larger blocks are built by k_build_blocks after the step.
+// larger blocks are built by k_build_listed after the step.
 void plan_rebuild_lds(kdt_ctx* c) {
     c->dev.step_lds = 0;
     c->follow = false;
@@ -2415,9 +2573,10 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->dev.order = (const int*)(w + L.order);
     c->dev.owner = (int*)(w + L.qmap);
     c->dev.own2 = (int*)(w + L.own2);
-    c->dev.rb_flag = (int*)(w + L.rb_flag);
+    c->dev.rb_list = (int*)(w + L.rb_flag);
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.tau = 0.f;
+    c->dev.dlim = 0.f;
     c->dev.mlp_w = nullptr;
     c->dev.log = nullptr;
     c->dev.log_cap = 0;
@@ -2431,7 +2590,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     rc |= check_hip(c, hipMemcpyAsync(w + L.tri_off, c->tri_off.data(), sizeof(long long) * (n_blocks + 1), hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemcpyAsync(w + L.frame, fr.data(), sizeof(int4) * n_blocks, hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int) * n_blocks, s));
-    rc |= check_hip(c, hipMemsetAsync(w + L.rb_flag, 0, sizeof(int) * n_blocks, s));
+    rc |= check_hip(c, hipMemsetAsync(w + L.rb_flag, 0, sizeof(int) * (n_blocks + 2), s));
     rc |= check_hip(c, hipMemsetAsync(w + L.stats, 0, sizeof(BlockStats) * n_blocks, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.sticky, 0, sizeof(int) * 4, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.rest_cnt, 0, sizeof(int) * n_blocks, s));
@@ -2456,7 +2615,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     if (rc != KDT_OK) { delete c; return KDT_E_DEVICE; }
     c->pb_lds = (int)(pb_fixed_lds() + max_block_need(c, 0, pb_lds_bytes() - pb_fixed_lds()));
     c->dev.step_lds = 0;
-    k_build_blocks<<<n_blocks, PB_THREADS, c->pb_lds, s>>>(c->dev, 0, 0, c->pb_lds);
+    k_build_blocks<<<n_blocks, PB_THREADS, c->pb_lds, s>>>(c->dev, c->pb_lds);
     if (check_hip(c, hipGetLastError()) != KDT_OK) { delete c; return KDT_E_DEVICE; }
     rc = check_hip(c, hipStreamSynchronize(s));
     if (rc != KDT_OK) { delete c; return rc; }
@@ -2539,9 +2698,9 @@ int launch_staged(kdt_ctx* c, int8_t* applied, std::vector<int>* order) {
     hipEvent_t e0 = timing_begin(c);
     k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, (const kdt_move_t*)(w + c->L.stage_mv),
                                                        (const int*)(w + c->L.stage_off), applied, c->step_count);
-    if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
-        k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
-                                                                          c->pb_lds_follow);
+    if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch listed
+        k_build_listed<<<std::min(c->B, 8 * c->cus), PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, c->step_count,
+                                                                                            c->pb_lds_follow);
     c->step_count++;
     timing_end(c, e0);
     if (order) order->swap(idx);
@@ -2614,9 +2773,9 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
         } else {
             k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count);
         }
-        if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch flagged
-            k_build_blocks<<<c->B, PB_THREADS, c->pb_lds_follow, c->stream>>>(c->dev, 1, c->step_count,
-                                                                              c->pb_lds_follow);
+        if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch listed
+            k_build_listed<<<std::min(c->B, 8 * c->cus), PB_THREADS, c->pb_lds_follow, c->stream>>>(
+                c->dev, c->step_count, c->pb_lds_follow);
         c->step_count++;
         if (timed) timing_end(c, e0);
     }
@@ -2708,7 +2867,7 @@ void kdt_graph_destroy(kdt_graph* g) {
 }
 
 int kdt_set_policy(kdt_ctx* c, int32_t policy, float tau, const float* mlp_w) {
-    if (!c || policy < KDT_POLICY_REPAIR || policy > KDT_POLICY_MLP) return KDT_E_ARG;
+    if (!c || policy < KDT_POLICY_REPAIR || policy > KDT_POLICY_DLIMIT) return KDT_E_ARG;
     if (policy == KDT_POLICY_MLP && !mlp_w) return KDT_E_ARG;
     c->dev.policy = policy;
     c->dev.tau = tau;
@@ -2945,6 +3104,50 @@ int kdt_digest(kdt_ctx* c, uint64_t* host_per_block) {
     return KDT_OK;
 }
 
+int kdt_dcalc(kdt_ctx* c, int32_t N, int64_t* host_mind2, int64_t* host_diam2, int64_t* d2_now, int64_t* d2_min,
+              double* host_spread) {
+    if (!c || N < 1 || N > DC_NMAX) return KDT_E_ARG;
+    int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    char* w = c->ws;
+    long long* mind2 = (long long*)(w + c->L.dc_mind2);
+    long long* diam2 = (long long*)(w + c->L.dc_diam2);
+    unsigned long long* g = (unsigned long long*)(w + c->L.dc_g);
+    const unsigned long long init[2] = {(unsigned long long)DC_NONE, 0ull};
+    if (check_hip(c, hipMemcpyAsync(g, init, sizeof(init), hipMemcpyHostToDevice, c->stream))) return KDT_E_DEVICE;
+    k_dcalc<<<c->B, WAVE, 0, c->stream>>>(c->dev, N, mind2, diam2, g, (int*)(g + 1));
+    std::vector<long long> m(c->B), d(c->B);
+    unsigned long long gh[2];
+    if (check_hip(c, hipGetLastError()) ||
+        check_hip(c, hipMemcpyAsync(m.data(), mind2, sizeof(long long) * c->B, hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipMemcpyAsync(d.data(), diam2, sizeof(long long) * c->B, hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipMemcpyAsync(gh, g, sizeof(gh), hipMemcpyDeviceToHost, c->stream)) ||
+        check_hip(c, hipStreamSynchronize(c->stream)))
+        return KDT_E_DEVICE;
+    if (gh[1] != 0) return KDT_E_CAPACITY;  // a search beyond its candidate capacity
+    if (N != c->dc_n) {  // a new N starts a new history
+        c->dc_n = N;
+        c->dc_d2 = DC_NONE;
+        c->dc_spread.assign(c->B, 0.0);
+    }
+    const long long now = (long long)gh[0];
+    c->dc_d2 = std::min(c->dc_d2, now);
+    if (now != DC_NONE)
+        for (int32_t b = 0; b < c->B; ++b)
+            c->dc_spread[b] = std::max(c->dc_spread[b], std::sqrt((double)d[b] / (double)now));
+    if (host_mind2) std::memcpy(host_mind2, m.data(), sizeof(long long) * c->B);
+    if (host_diam2) std::memcpy(host_diam2, d.data(), sizeof(long long) * c->B);
+    if (d2_now) *d2_now = now;
+    if (d2_min) *d2_min = c->dc_d2;
+    if (host_spread) std::memcpy(host_spread, c->dc_spread.data(), sizeof(double) * c->B);
+    // the selector's view of d (feature 15, the d-limit rule): the running d
+    if (c->dc_d2 != DC_NONE) {
+        c->dev.dlim = (float)std::sqrt((double)c->dc_d2);
+        c->epoch++;
+    }
+    return KDT_OK;
+}
+
 int kdt_positions(kdt_ctx* c, int32_t* host_xy) {
     if (!c || !host_xy) return KDT_E_ARG;
     int rc = kdt_sync(c);
@@ -3110,7 +3313,7 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->dev.order = (const int*)(w + L.order);
     c->dev.owner = (int*)(w + L.qmap);
     c->dev.own2 = (int*)(w + L.own2);
-    c->dev.rb_flag = (int*)(w + L.rb_flag);
+    c->dev.rb_list = (int*)(w + L.rb_flag);
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.n_blocks = 1;
     c->g.claim = (unsigned long long*)(w + G.claim);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libkdt.so")
 BLOCKED = 1
 OK, E_ARG, E_RANGE, E_DUP, E_DEGEN, E_CAPACITY, E_DEVICE, E_STATE, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 RUN_PER_STEP, RUN_FUSED, RUN_PERSISTENT = 0, 1, 2
-POLICY = {"repair": 0, "rebuild": 1, "threshold": 2, "mlp": 3}
+POLICY = {"repair": 0, "rebuild": 1, "threshold": 2, "mlp": 3, "dlimit": 4}
 MLP_PARAMS = 1666
 LOG_FIELDS = 20
 
@@ -30,7 +30,7 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves")
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc")
 MLP_NOALLOC_BATCH = 4096
 PART = {"grid": 0, "quadtree": 1}
 
@@ -95,6 +95,7 @@ def _lib():
         L.kdt_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.kdt_set_launch.argtypes = [vp, i32]
         L.kdt_set_block_waves.argtypes = [vp, i32]
+        L.kdt_dcalc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
         L.kdt_graph_launch.argtypes = [vp, vp]
         L.kdt_graph_destroy.argtypes = [vp]
@@ -374,6 +375,18 @@ class KineticDT:
         out = np.zeros(self.B, dtype=np.uint64)
         _check(_lib().kdt_digest(self.ctx, _ptr(out)), "kdt_digest")
         return out
+
+    def dcalc(self, N):
+        """d-calculation (kdt_dcalc): dict of per-block mindistance^2 and
+        diameter^2, mindistance(P_t)^2 now, d^2 over the calls so far, and
+        every block's running N-spread."""
+        mind2 = np.zeros(self.B, dtype=np.int64)
+        diam2 = np.zeros(self.B, dtype=np.int64)
+        spread = np.zeros(self.B, dtype=np.float64)
+        now, dmin = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib().kdt_dcalc(self.ctx, int(N), _ptr(mind2), _ptr(diam2), ctypes.byref(now), ctypes.byref(dmin),
+                                _ptr(spread)), "kdt_dcalc")
+        return dict(mind2=mind2, diam2=diam2, d2_now=int(now.value), d2=int(dmin.value), spread=spread)
 
     def positions(self):
         out = np.empty((self.n, 2), dtype=np.int32)

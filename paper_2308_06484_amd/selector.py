@@ -23,11 +23,15 @@ from .kdt import LOG_FIELDS, MLP_PARAMS, KineticDT, mlp_train
 H, IN = 32, 16
 
 
+DCALC_N = 4  # N of the d-calculation whose d feeds feature 15 and the d-limit rule
+
+
 def run_policy(w, steps, policy, device="cuda:0", tau=0.0, mlp_w=None, log=True):
     """Run the workload's first `steps` steps under one policy from its
-    initial state.  Returns (log [steps, B, LOG_FIELDS] numpy or None,
-    seconds, stats)."""
+    initial state (after one d-calculation of the initial positions).
+    Returns (log [steps, B, LOG_FIELDS] numpy or None, seconds, stats)."""
     dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=device)
+    dt.dcalc(DCALC_N)
     dt.set_policy(policy, tau, mlp_w)
     lg = dt.set_log(steps) if log else None
     mv = torch.from_numpy(w["mv"]).to(device)
