@@ -447,6 +447,8 @@ def form_name(f):
         n += f"_{f['per_cu']}wg"
     if f.get("waves", 1) > 1:
         n += f"_{f['waves']}waves"
+    if f.get("repair"):
+        n += "_" + f["repair"]
     return n + ("_graph" if f.get("graph") else "")
 
 
@@ -468,6 +470,8 @@ def timed_run(w, mv, off_warm, off_timed, form, policy, dev, period=0):
             dt.set_launch(form["per_cu"])
         if form.get("waves", 1) > 1:
             dt.set_block_waves(form["waves"])
+        if form.get("repair"):
+            dt.set_repair(form["repair"])
         if off_warm is not None and off_warm.shape[0]:
             dt.run(mv, off_warm, mode=form["mode"])
         dt.sync()
@@ -540,6 +544,7 @@ def headline(args):
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
                  (form_name(form) + "_dlimit", form, ("dlimit", 1.0, None), K),
+                (form_name(dict(form, repair="flip")) + "_mlp", dict(form, repair="flip"), pol_mlp, K),
                  ("per_step_rebuild_only", {"mode": "step", "graph": False}, ("rebuild", 0.0, None), min(10, K))]
         for name, f, pol, steps in runs:
             if name in variants:

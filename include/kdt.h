@@ -92,6 +92,8 @@ typedef struct kdt_stats_t {
      * destroyed no triangle around it (the star polygon alone changed) */
     int64_t fast;
     int64_t rebuilt;  /* block steps done by the rebuild branch */
+    int64_t flipped;  /* moves done by move-and-flip (kdt_set_repair) */
+    int64_t flips;    /* edge flips of those moves */
 } kdt_stats_t;
 
 typedef struct kdt_ctx kdt_ctx;
@@ -204,6 +206,23 @@ int kdt_run(kdt_ctx* ctx, const kdt_move_t* moves, const int32_t* step_off,
 /* Workgroups per compute unit of the persistent launch (1..64, default 4;
  * the LDS of an MI355X compute unit holds 5 step workgroups). */
 int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
+
+/* Repair variant of the per-block modes.
+ *   KDT_REPAIR_DELINS (default)  every move deletes the point and inserts it
+ *              at its new place (Fig. 4; Sec. IV, "Insertion and Deletion")
+ *   KDT_REPAIR_FLIP  move-and-flip, the other update De Berg et al. give for
+ *              points moving in discrete steps (Sec. II): when the new place
+ *              lies strictly inside the kernel of the point's star (the point
+ *              not on the hull, every triangle of its star still
+ *              counter-clockwise with the point there), the point moves in
+ *              place and Lawson flips with the perturbed incircle test make
+ *              the triangulation Delaunay again; other moves delete and
+ *              insert.  Same DT*, different work (kdt_stats: flipped,
+ *              flips).
+ * KDT_E_ARG for another value, KDT_E_STATE in global mode. */
+#define KDT_REPAIR_DELINS 0
+#define KDT_REPAIR_FLIP 1
+int kdt_set_repair(kdt_ctx* ctx, int32_t variant);
 
 /* Wavefronts per block of the per-step launch (KDT_RUN_PER_STEP): 1
  * (default: one wavefront applies the block's moves one after another), 2

@@ -59,6 +59,7 @@ struct DevState {
     float tau;           // threshold rule: rebuild iff sum of d / spacing > tau
     float dlim;          // d of the latest d-calculation (0: none yet): feature 15, the d-limit rule
     int n_blocks;
+    int repair;    // repair variant: KDT_REPAIR_*
     BlockStats* stats;
     float* log;  // per step and block: LOG_FIELDS floats, or null
 };
@@ -201,7 +202,8 @@ struct MovePlan {
 };
 
 __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
-                          BlockStats* st, int* applied, int mode = MV_APPLY, MovePlan* plan = nullptr) {
+                          BlockStats* st, int* applied, int mode = MV_APPLY, MovePlan* plan = nullptr,
+                          bool flip = false) {
     const int lane = lane_id();
     *applied = 0;
     const int p = mv.point, dir = mv.dir, dist = mv.dist;
@@ -227,6 +229,43 @@ __device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_mo
     const long long c1 = wall_clock64();
     bool in_star, on_vertex;
     locate_in_star(S, k, o, q, &in_star, &on_vertex);
+    if (flip && in_star && !on_vertex) {
+        // move-and-flip when q lies inside the kernel of p's star
+        int nf = 0;
+        const int r = move_and_flip(B, S, k, p, q, &used, &nvt, &nf);
+        if (r < 0) return r;  // memory unchanged
+        if (r == 1) {
+            if (mode == MV_PLAN) {
+                if (lane == 0 && st) {  // the plan's counters (kept if it commits)
+                    st->flipped += 1;
+                    st->flips += nf;
+                }
+                *plan = MovePlan{k, used, npath, nvt, nvt, q, 0};
+                *applied = 2;
+                return ST_OK;
+            }
+            int ndirty = 0;
+            for (int base = 0; base < used; base += WAVE)
+                ndirty += __popcll(ballot(base + lane < used && (S.tflag[S.tused[base + lane]] & F_DIRTY)));
+            commit(B, S, used, nvt, nvt);
+            if (lane == 0) B.xy[p] = q;
+            const long long c4 = wall_clock64();
+            if (lane == 0 && st) {
+                const long long dt = c4 - c0;
+                st->hist[dt <= 1 ? 0 : min(15, 63 - __clzll(dt))] += 1;
+                st->t_star += c1 - c0;
+                st->t_hole += c4 - c1;
+                st->applied += 1;
+                st->flipped += 1;
+                st->flips += nf;
+                st->tri_touched += used - k;  // records read beyond the star's ring
+                // records read and written, incident-triangle updates, move record, position
+                st->alg_bytes += 64LL * (used - k) + 64LL * ndirty + 4LL * nvt + 32;
+            }
+            *applied = 1;
+            return ST_OK;
+        }
+    }
     int hops = 0, tq = -1, kr = k;
     bool in_ring = false;
     if (!in_star) {
@@ -633,7 +672,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
         for (int m = m0; m < m1; ++m) {
             int app = 0;
             if (m > m0) gsync();  // the previous move's stores are visible
-            rc = apply_move(B, S, mv[m], fr, &S.st, &app);
+            rc = apply_move(B, S, mv[m], fr, &S.st, &app, MV_APPLY, nullptr, s.repair == KDT_REPAIR_FLIP);
             if (rc == ST_CAPACITY) {
                 // beyond the move path's fixed capacities (a star of more than
                 // KMAX triangles, a table or a cavity larger than its LDS
@@ -1371,7 +1410,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
         if (i >= 0) {
             if (lane < NF) reinterpret_cast<long long*>(&M.pst[w])[lane] = 0;
             wsync();
-            rc = apply_move(B, S, mv[m0 + i], fr, &M.pst[w], &app, MV_PLAN, &pl);
+            rc = apply_move(B, S, mv[m0 + i], fr, &M.pst[w], &app, MV_PLAN, &pl, s.repair == KDT_REPAIR_FLIP);
             if (rc == ST_OK && app == 2) {
                 total = pl.k + pl.used + pl.npath;
                 if (pl.npath > WPMAX || total > RSMAX) {
@@ -1431,6 +1470,8 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
                 S.st.alg_bytes += P.alg_bytes + 32 + 64LL * pl.npath;
                 S.st.applied += 1;
                 S.st.fast += pl.fast;
+                S.st.flipped += P.flipped;
+                S.st.flips += P.flips;
             }
         } else if (i >= 0) {
             if (app == 2) table_drop(S, pl.used);
@@ -2811,6 +2852,14 @@ int kdt_set_launch(kdt_ctx* c, int32_t persist_per_cu) {
     return KDT_OK;
 }
 
+int kdt_set_repair(kdt_ctx* c, int32_t variant) {
+    if (!c || (variant != KDT_REPAIR_DELINS && variant != KDT_REPAIR_FLIP)) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    c->dev.repair = variant;
+    c->epoch++;
+    return KDT_OK;
+}
+
 int kdt_set_block_waves(kdt_ctx* c, int32_t waves) {
     if (!c || (waves != 1 && waves != 2 && waves != 4)) return KDT_E_ARG;
     if (c->global) return KDT_E_STATE;
@@ -3179,6 +3228,8 @@ int kdt_stats(kdt_ctx* c, kdt_stats_t* out) {
         for (int i = 0; i < 16; ++i) out->hist[i] += s.hist[i];
         out->fast += s.fast;
         out->rebuilt += s.rebuilt;
+        out->flipped += s.flipped;
+        out->flips += s.flips;
     }
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess) out->clock_khz = khz;

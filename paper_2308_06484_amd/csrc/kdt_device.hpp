@@ -90,6 +90,8 @@ struct BlockStats {
     long long hist[16];
     long long fast;     // moves done by the star-only path
     long long rebuilt;  // block steps done by the rebuild branch
+    long long flipped;  // moves done by move-and-flip
+    long long flips;    // edge flips of those moves
 };
 
 // per-wavefront scratch in LDS
@@ -1242,6 +1244,132 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WaveLDS& S, int k, 
         st->alg_bytes += 64LL * nh + 4LL * (k + (with_q ? 1 : 0));
     }
     return ST_OK;
+}
+
+// ---------------------------------------------------------------- move and flip
+// The move-and-flip repair, the other way to update a triangulation of
+// points moved in discrete steps beside delete + insert (De Berg et al.;
+// Sec. II).  When the new place q lies strictly inside the kernel of p's
+// star -- p not on the hull, every star triangle (p, q_s, q_s+1) still
+// counter-clockwise with p at q -- p moves there in place: the
+// triangulation stays valid and the hull is unchanged.  Lawson flips then
+// restore the Delaunay property: an edge whose opposite vertex lies inside
+// the perturbed circle of a triangle is flipped, and the four edges around
+// the flipped pair are checked again.  Only edges whose two triangles hold
+// p can fail at first: the spokes and the link edges.  Flipping ends (each
+// flip lowers the lifted surface) at a triangulation every edge of which is
+// locally Delaunay under the perturbed test, i.e. DT*, the result of delete
+// + insert.  All of it happens in the write-back table; commit() writes it.
+// Returns 1 when taken, 0 when q is not inside the kernel (nothing read or
+// changed), or ST_CAPACITY (too many flips, or the table is full; memory
+// unchanged).
+constexpr int FLIP_MAX = (VTMAX - 1) / 2;  // flips one move may do: two incident-triangle updates each
+__device__ __forceinline__ int move_and_flip(const BlockView& B, WaveLDS& S, int k, int p, int2 q, int* used,
+                                             int* nvt, int* nflips) {
+    const int lane = lane_id();
+    *nflips = 0;
+    *nvt = 0;
+    bool ok = true;
+    if (lane < k) {
+        const int a = S.link[lane], b = S.link[(lane + 1) % k];
+        ok = a != GHOST && b != GHOST && orient(S.lxy[lane], S.lxy[(lane + 1) % k], q) > 0;
+    }
+    if (k < 3 || ballot(!ok)) return 0;
+    // the star triangles into the table with p's position copies at q; the
+    // queue of edges to check (4 * slot + index of the opposite vertex): the
+    // link edge opposite p and the spoke (q_s+1, p) opposite q_s of each
+    const int se = tget(B, S, lane < k, S.star_slot[lane < k ? lane : 0], used);
+    if (ballot(lane < k && se < 0)) return ST_CAPACITY;
+    int* queue = S.cav_ent;  // a ring of CMAX edges (the cavity arrays are unused here)
+    if (lane < k) {
+        Tri& t = S.trec[se];
+        const int pi = t.v.x == p ? 0 : (t.v.y == p ? 1 : 2);
+        cset(t, pi, q);
+        S.tflag[se] |= F_DIRTY;
+        const int ss = S.star_slot[lane];
+        queue[2 * lane] = 4 * ss + pi;
+        queue[2 * lane + 1] = 4 * ss + (pi + 1) % 3;
+    }
+    wsync();
+    int head = 0, tail = 2 * k;
+    while (head < tail) {
+        const int ref = queue[head % CMAX];
+        ++head;
+        const int ts = ref >> 2, te = ref & 3;
+        if (bad_slot(B, ts)) return ST_INTERNAL;
+        const int et = tget(B, S, true, ts, used);
+        if (et < 0) return ST_CAPACITY;
+        const Tri t = S.trec[et];
+        if (t.v.z == GHOST) continue;
+        const int nref = vget(t.n, te);
+        const int us = nref >> 2, ue = nref & 3;
+        if (bad_slot(B, us)) return ST_INTERNAL;
+        const int eu = tget(B, S, true, us, used);
+        if (eu < 0) return ST_CAPACITY;
+        const Tri u = S.trec[eu];
+        if (u.v.z == GHOST) continue;  // a hull edge: never flipped
+        // t = (A, B, C) from te, u = (D, C, B) from ue; the shared edge is BC
+        const int iA = te, iB = (te + 1) % 3, iC = (te + 2) % 3;
+        const int vA = vget(t.v, iA), vB = vget(t.v, iB), vC = vget(t.v, iC), vD = vget(u.v, ue);
+        const int2 pA = cget(t, iA), pB = cget(t, iB), pC = cget(t, iC), pD = cget(u, ue);
+        if (incircle_star(pA, vA, pB, vB, pC, vC, pD, vD) <= 0) continue;
+        if (++*nflips > FLIP_MAX || tail - head + 4 > CMAX) return ST_CAPACITY;
+        const int rAB = vget(t.n, iC), rCA = vget(t.n, iB);
+        const int rBD = vget(u.n, (ue + 1) % 3), rDC = vget(u.n, (ue + 2) % 3);
+        // t becomes (A, B, D), u becomes (A, D, C); their shared edge AD
+        if (lane == 0) {
+            Tri nt, nu;
+            nt.v = make_int4(vA, vB, vD, 0);
+            nt.n = make_int4(rBD, 4 * us + 2, rAB, 0);
+            nt.c01 = make_int4(pA.x, pA.y, pB.x, pB.y);
+            nt.c2 = make_int4(pD.x, pD.y, 0, 0);
+            nu.v = make_int4(vA, vD, vC, 0);
+            nu.n = make_int4(rDC, rCA, 4 * ts + 1, 0);
+            nu.c01 = make_int4(pA.x, pA.y, pD.x, pD.y);
+            nu.c2 = make_int4(pC.x, pC.y, 0, 0);
+            S.trec[et] = nt;
+            S.trec[eu] = nu;
+            S.tflag[et] |= F_DIRTY;
+            S.tflag[eu] |= F_DIRTY;
+            // B left u and C left t: their incident triangles are found again
+            // at the end
+            S.vt_v[*nvt] = vB;
+            S.vt_v[*nvt + 1] = vC;
+            queue[tail % CMAX] = 4 * ts + 0;      // BD
+            queue[(tail + 1) % CMAX] = 4 * ts + 2;  // AB
+            queue[(tail + 2) % CMAX] = 4 * us + 0;  // DC
+            queue[(tail + 3) % CMAX] = 4 * us + 1;  // CA
+        }
+        *nvt += 2;
+        tail += 4;
+        wsync();
+        // the four outside neighbours point into the new pair
+        const int oref = lane == 0 ? rBD : (lane == 1 ? rAB : (lane == 2 ? rDC : rCA));
+        const int oval = lane == 0 ? 4 * ts + 0 : (lane == 1 ? 4 * ts + 2 : (lane == 2 ? 4 * us + 0 : 4 * us + 1));
+        if (ballot(lane < 4 && bad_slot(B, oref >> 2))) return ST_INTERNAL;
+        const int eo = tget(B, S, lane < 4, oref >> 2, used);
+        if (ballot(lane < 4 && eo < 0)) return ST_CAPACITY;
+        if (lane < 4) {
+            reinterpret_cast<int*>(&S.trec[eo].n)[oref & 3] = oval;
+            S.tflag[eo] |= F_DIRTY;
+        }
+        wsync();
+    }
+    // an incident triangle for every vertex that lost one (the same answer
+    // for a vertex listed twice): the first changed real record holding it
+    for (int i = lane; i < *nvt; i += WAVE) {
+        const int v = S.vt_v[i];
+        int found = -1;
+        for (int u2 = 0; u2 < *used && found < 0; ++u2) {
+            const int h = S.tused[u2];
+            const Tri& r = S.trec[h];
+            if ((S.tflag[h] & F_DIRTY) && r.v.z != GHOST && (r.v.x == v || r.v.y == v || r.v.z == v)) found = S.tkey[h];
+        }
+        S.vt_s[i] = found;
+        if (found < 0) S.vt_v[i] = GHOST;  // cannot happen: v is in a changed triangle
+    }
+    wsync();
+    return 1;
 }
 
 }  // namespace kdt

@@ -30,7 +30,8 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc")
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair")
+REPAIR = {"delins": 0, "flip": 1}
 MLP_NOALLOC_BATCH = 4096
 PART = {"grid": 0, "quadtree": 1}
 
@@ -49,7 +50,8 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("applied", "blocked", "star_sum", "cavity_sum", "walk_sum", "tri_touched",
                  "alg_bytes", "errors", "t_star", "t_locate", "t_hole", "t_insert", "clock_khz")] + \
-               [("hist", ctypes.c_int64 * 16), ("fast", ctypes.c_int64), ("rebuilt", ctypes.c_int64)]
+               [("hist", ctypes.c_int64 * 16), ("fast", ctypes.c_int64), ("rebuilt", ctypes.c_int64),
+                ("flipped", ctypes.c_int64), ("flips", ctypes.c_int64)]
 
     def as_dict(self):
         d = {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "hist"}
@@ -95,6 +97,7 @@ def _lib():
         L.kdt_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.kdt_set_launch.argtypes = [vp, i32]
         L.kdt_set_block_waves.argtypes = [vp, i32]
+        L.kdt_set_repair.argtypes = [vp, i32]
         L.kdt_dcalc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
         L.kdt_graph_launch.argtypes = [vp, vp]
@@ -312,6 +315,10 @@ class KineticDT:
 
     def set_launch(self, persist_per_cu):
         _check(_lib().kdt_set_launch(self.ctx, int(persist_per_cu)), "kdt_set_launch")
+
+    def set_repair(self, variant):
+        """Repair variant: "delins" (delete + insert) or "flip" (move-and-flip)."""
+        _check(_lib().kdt_set_repair(self.ctx, REPAIR[variant]), "kdt_set_repair")
 
     def set_block_waves(self, waves):
         """Wavefronts per block of the per-step launch (1, 2 or 4)."""

@@ -25,7 +25,8 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label="", waves=1):
+def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label="", waves=1,
+                    repair=None):
     """Run w's first T steps one step per call; after every step compare the
     applied flags and a rotating subset of SUBSET blocks; at the end, all."""
     from paper_2308_06484_amd.kdt import KineticDT
@@ -35,6 +36,8 @@ def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0,
         dt.set_policy(policy, tau, mlp_w)
     if waves > 1:
         dt.set_block_waves(waves)
+    if repair:
+        dt.set_repair(repair)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
     perm = np.random.default_rng(seed).permutation(B).astype(np.int32)
     mv = torch.from_numpy(w["mv"]).to(DEV)
