@@ -452,6 +452,50 @@ int kdt_workspace_size_global(int64_t n, int32_t depth, int32_t max_moves, size_
 int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, const int32_t* domain,
                     int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream);
 
+/* The global mode with the paper's own partition (Sec. III, "Data
+ * structure"; Fig. 2, 3): the cells are the leaves of a quad-tree of the
+ * initial points -- the root is the smallest power-of-two square at the
+ * domain's lower-left corner covering the domain; a square holding more than
+ * `threshold` points is cut into its four quarters (empty ones kept, so the
+ * leaves tile the root) -- and every leaf is linked to the node across each
+ * of its four sides (equal or larger).  A moved point that leaves its cell
+ * is handed to the block holding its new place ("new-block", Fig. 4): found
+ * through the direct link on the side it moved across when the neighbour
+ * holds it (O(1), Sec. V after Theorem 1), else down from the root
+ * (O(log4 B), Theorem 1); kdt_global_stats counts both (KDT_GSTAT_LINK,
+ * KDT_GSTAT_TREE).  The tree is the initial points' unless re-partitioned
+ * (kdt_repartition, kdt_set_repartition).
+ * Arguments and errors as for kdt_workspace_size_global / kdt_init_global,
+ * with threshold >= 1 in place of depth; the workspace size needs the
+ * points (the tree's size depends on them).  kdt_owner returns the leaf's
+ * node index (kdt_quadtree). */
+int kdt_workspace_size_global_qt(const int32_t* xy, int64_t n, const int32_t* domain, int64_t threshold,
+                                 int32_t max_moves, size_t* dev_bytes);
+int kdt_init_global_qt(kdt_ctx** out, const int32_t* xy, int64_t n, const int32_t* domain, int64_t threshold,
+                       int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream);
+
+/* The quad-tree of a context made by kdt_init_global_qt (host; KDT_E_STATE
+ * otherwise): host_nodes int32 [cap][8], node k = (x0, y0, side, first of
+ * its four children or -1 for a leaf, then for a leaf the node across its
+ * +x, -x, +y and -y sides or -1 at the root's border, -1 for inner nodes);
+ * node 0 is the root; the children of a node are its quarters (low x low y,
+ * high x low y, low x high y, high x high y).  *n_nodes is written even
+ * when it exceeds cap (then KDT_E_CAPACITY and nothing else). */
+int kdt_quadtree(kdt_ctx* ctx, int32_t* host_nodes, int32_t cap, int32_t* n_nodes);
+
+/* Quad-treeDvision of the current positions (Fig. 4, step 5: the partition
+ * is made again for the dataset of every time step): the quad-tree is
+ * computed from scratch on the device -- the same definition as at init,
+ * with the nodes numbered breadth first -- with its links, and every
+ * point's cell is its new leaf.  Synchronises (the host waits for each
+ * level's count of cut cells).  KDT_E_STATE unless made by
+ * kdt_init_global_qt; KDT_E_CAPACITY if the tree outgrows its arrays
+ * (cannot happen for points in the domain).
+ * kdt_set_repartition(ctx, 1) makes kdt_run_global re-partition after
+ * every step, 0 stops it. */
+int kdt_repartition(kdt_ctx* ctx);
+int kdt_set_repartition(kdt_ctx* ctx, int32_t every_step);
+
 /* Run n_steps steps.  moves: dev kdt_move_t [*] with point = global id;
  * step_off: HOST int64 [n_steps + 1], step t = moves step_off[t] ..
  * step_off[t+1]-1 (at most max_moves).  applied: dev int8 indexed like
@@ -474,6 +518,8 @@ int kdt_owner(kdt_ctx* ctx, int32_t* host_owner);
 #define KDT_GSTAT_TRANSFERS 3    /* applied moves that changed the point's kd cell */
 #define KDT_GSTAT_OVERFLOW 4     /* plans too large for a reservation (ordered pass) */
 #define KDT_GSTAT_BUILD_ROUNDS 5 /* reservation rounds of the builds so far */
+#define KDT_GSTAT_LINK 6         /* quad-tree cells: transfers whose new cell came through a direct link */
+#define KDT_GSTAT_TREE 7         /* quad-tree cells: transfers whose new cell came down from the root */
 #define KDT_GSTAT_N 8
 int kdt_global_stats(kdt_ctx* ctx, uint64_t* host_counters);
 

@@ -167,3 +167,68 @@ class KineticGlobal:
         yy = np.where(strip % 2 == 0, y, (1 << 24) - 1 - y)
         order = np.lexsort((x, yy, strip))
         return dt_star(self.xy[order], order.astype(np.int64))
+
+
+def quadtree(xy, domain, thr):
+    """Quad-tree of a point set (Sec. III, "Data structure"), by its
+    definition: the root is the smallest power-of-two square at the domain's
+    lower-left corner that covers the domain; a square holding more than
+    `thr` points (and wider than one lattice cell) is cut into its four
+    quarters -- (low x, low y), (high x, low y), (low x, high y), (high x,
+    high y), empty ones kept.  Nodes are numbered depth first (a node's four
+    children get the next numbers when it is cut).  Returns the nodes as
+    [x0, y0, side, first child or -1] and the leaf of every point."""
+    xy = np.asarray(xy, dtype=np.int64).reshape(-1, 2)
+    x0, y0, x1, y1 = (int(v) for v in domain)
+    side = 1
+    while side < max(x1 - x0, y1 - y0):
+        side *= 2
+    nodes = [[x0, y0, side, -1]]
+    cell = np.zeros(len(xy), dtype=np.int64)
+
+    def node(k, idx):
+        nx, ny, s, _ = nodes[k]
+        if len(idx) <= thr or s == 1:
+            cell[idx] = k
+            return
+        h = s // 2
+        c0 = len(nodes)
+        nodes[k][3] = c0
+        for q in range(4):
+            nodes.append([nx + (q & 1) * h, ny + (q >> 1) * h, h, -1])
+        p = xy[idx]
+        quarter = (p[:, 0] >= nx + h).astype(np.int64) + 2 * (p[:, 1] >= ny + h)
+        for q in range(4):
+            node(c0 + q, idx[quarter == q])
+
+    node(0, np.arange(len(xy)))
+    return nodes, cell
+
+
+def quadtree_leaf(nodes, x, y):
+    """The leaf holding the lattice point (x, y)."""
+    k = 0
+    while nodes[k][3] >= 0:
+        nx, ny, s, c = nodes[k]
+        h = s // 2
+        k = c + (1 if x >= nx + h else 0) + (2 if y >= ny + h else 0)
+    return k
+
+
+class KineticGlobalQT(KineticGlobal):
+    """Global mode with quad-tree cells (fixed by the initial points): the
+    same triangulation and move rule, a point's cell is the leaf holding
+    its current position."""
+
+    def __init__(self, xy, side, thr):
+        super().__init__(xy, side, 0)
+        self.thr = thr
+        self.nodes, _ = quadtree(self.xy, (0, 0, side, side), thr)
+
+    def owner(self):
+        return np.array([quadtree_leaf(self.nodes, int(x), int(y)) for x, y in self.xy.tolist()], dtype=np.int64)
+
+    def repartition(self):
+        """Quad-treeDvision of the current positions (Fig. 4): the tree made
+        again, by the same definition."""
+        self.nodes, _ = quadtree(self.xy, (0, 0, self.side, self.side), self.thr)

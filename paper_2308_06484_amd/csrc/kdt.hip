@@ -830,6 +830,17 @@ struct GlobalDev {
     int* serial;                // ordered-pass list (move indices, any order)
     const int2* split;          // kd split keys in heap order (root 1)
     int depth;
+    // quad-tree cells instead of kd cells (qt = 1): node {x0, y0, log2 side,
+    // first of its 4 children or -1}, and for every leaf the node across each
+    // side (equal or larger), in move-direction order +x, -x, +y, -y (-1 at
+    // the border of the root square)
+    int qt;
+    int4* qn;
+    int4* ql;
+    int* qcnt;       // points per node (re-partition)
+    int* qlev;       // first node of every level (re-partition, breadth first)
+    int qcap;        // nodes the arrays hold
+    long long qthr;  // threshold
     int* powner;                // kd cell holding each point
     unsigned long long* gstats; // KDT_GSTAT_* counters
     unsigned long long* part;   // per commit workgroup: applied, star-only, algorithmic bytes, transfers
@@ -931,6 +942,150 @@ __device__ __forceinline__ int owner_after_move(const GlobalDev& g, int old, int
     }
     if (!ballot(!ok)) return old;
     return kd_cell_of(g.split, D, q);
+}
+
+// ---- quad-tree cells (Sec. III "Data structure", Fig. 3)
+__device__ __forceinline__ bool qt_contains(int4 nd, int2 q) {
+    const int side = 1 << nd.z;
+    return q.x >= nd.x && q.x < nd.x + side && q.y >= nd.y && q.y < nd.y + side;
+}
+// The leaf below `node` (which holds q) that holds q.
+__device__ __forceinline__ int qt_descend(const int4* qn, int node, int2 q) {
+    int4 nd = qn[node];
+    while (nd.w >= 0) {
+        const int h = 1 << (nd.z - 1);
+        node = nd.w + (q.x >= nd.x + h ? 1 : 0) + (q.y >= nd.y + h ? 2 : 0);
+        nd = qn[node];
+    }
+    return node;
+}
+// The block (leaf) that receives a point moved to q from leaf `old` in
+// direction dir -- "new-block" of Fig. 4: its own leaf, else through the
+// direct link to the neighbour on that side (Fig. 3, O(1) when the
+// neighbour is a leaf), else down from the root (O(log4 B)); *how = 0, 1, 2.
+__device__ __forceinline__ int qt_owner_after_move(const GlobalDev& g, int old, int2 q, int dir, int* how) {
+    if (qt_contains(g.qn[old], q)) {
+        *how = 0;
+        return old;
+    }
+    const int4 lk = g.ql[old];
+    const int nb = dir == 0 ? lk.x : (dir == 1 ? lk.y : (dir == 2 ? lk.z : lk.w));
+    if (nb >= 0 && qt_contains(g.qn[nb], q)) {
+        *how = 1;
+        return qt_descend(g.qn, nb, q);
+    }
+    *how = 2;
+    return qt_descend(g.qn, 0, q);
+}
+// The cell of a moved point, for either partition; counts how quad-tree
+// transfers were routed.
+__device__ __forceinline__ int cell_after_move(const GlobalDev& g, int old, int2 q, int dir) {
+    if (!g.qt) return owner_after_move(g, old, q);
+    int how = 0;
+    const int nc = qt_owner_after_move(g, old, q, dir, &how);
+    if (how > 0 && lane_id() == 0)
+        atomicAdd(&g.gstats[how == 1 ? KDT_GSTAT_LINK : KDT_GSTAT_TREE], 1ull);
+    return nc;
+}
+
+// ---- Quad-treeDvision on the device (Fig. 4, step 5): the quad-tree of
+// the current positions from scratch, breadth first.  Level l's nodes are
+// qlev[l] .. qlev[l+1]-1; a node holding more than the threshold (and wider
+// than one lattice cell) gets its four quarters at the end of level l+1,
+// in node order (a scan), and then every point in it moves one level down.
+constexpr int QT_LEVELS = 26;
+__global__ void k_qt_reset(GlobalDev g, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) g.powner[p] = 0;
+    if (p == 0) {
+        g.qcnt[0] = n;
+        g.qn[0].w = -1;
+        g.qlev[0] = 0;
+        g.qlev[1] = 1;
+    }
+}
+// One workgroup: the children of level `lvl`'s nodes.  qlev[lvl + 2] and the
+// count of nodes cut (in qlev[QT_LEVELS]) for the host; a level beyond the
+// arrays' capacity cuts nothing and reports -1.
+__global__ void __launch_bounds__(1024) k_qt_alloc(GlobalDev g, int lvl) {
+    __shared__ int wsum[16];
+    __shared__ int base;
+    const int k0 = g.qlev[lvl], k1 = g.qlev[lvl + 1];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    if (t == 0) base = 0;
+    __syncthreads();
+    bool room = true;
+    for (int c0 = k0; c0 < k1; c0 += 1024) {
+        const int k = c0 + t;
+        const int4 nd = k < k1 ? g.qn[k] : make_int4(0, 0, 0, -1);
+        const bool cut = k < k1 && g.qcnt[k] > g.qthr && nd.z > 0;
+        const uint64_t m = ballot(cut);
+        if (lane == 0) wsum[wv] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int i = 0; i < 16; ++i) {
+            before += i < wv ? wsum[i] : 0;
+            total += wsum[i];
+        }
+        const int idx = base + before + lanes_below(m);
+        const int c = k1 + 4 * idx;
+        if (cut && c + 4 <= g.qcap) {
+            g.qn[k].w = c;
+            const int h = 1 << (nd.z - 1);
+            for (int q = 0; q < 4; ++q) {
+                g.qn[c + q] = make_int4(nd.x + (q & 1) * h, nd.y + (q >> 1) * h, nd.z - 1, -1);
+                g.qcnt[c + q] = 0;
+            }
+        } else if (cut) {
+            room = false;
+        }
+        __syncthreads();
+        if (t == 0) base += total;
+        __syncthreads();
+    }
+    const bool full = __syncthreads_or(!room);
+    if (t == 0) {
+        g.qlev[lvl + 2] = k1 + 4 * base;
+        g.qlev[QT_LEVELS] = full ? -1 : base;
+    }
+}
+__global__ void k_qt_down(const DevState s, GlobalDev g, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int cur = g.powner[p];
+    const int4 nd = g.qn[cur];
+    if (nd.w < 0) return;
+    const int2 q = s.xy[p];
+    const int h = 1 << (nd.z - 1);
+    const int c = nd.w + (q.x >= nd.x + h ? 1 : 0) + (q.y >= nd.y + h ? 2 : 0);
+    g.powner[p] = c;
+    atomicAdd(&g.qcnt[c], 1);
+}
+// The node across each side of every leaf (equal or larger), or -1.
+__device__ __forceinline__ int qt_probe_dev(const int4* qn, long long px, long long py, int lg) {
+    const int4 r = qn[0];
+    const long long side = 1ll << r.z;
+    if (px < r.x || py < r.y || px >= r.x + side || py >= r.y + side) return -1;
+    int node = 0;
+    int4 nd = r;
+    while (nd.w >= 0 && nd.z > lg) {
+        const long long h = 1ll << (nd.z - 1);
+        node = nd.w + (px >= nd.x + h ? 1 : 0) + (py >= nd.y + h ? 2 : 0);
+        nd = qn[node];
+    }
+    return node;
+}
+__global__ void k_qt_links(GlobalDev g, int nodes) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nodes) return;
+    const int4 nd = g.qn[k];
+    if (nd.w >= 0) {
+        g.ql[k] = make_int4(-1, -1, -1, -1);
+        return;
+    }
+    const long long side = 1ll << nd.z;
+    g.ql[k] = make_int4(qt_probe_dev(g.qn, nd.x + side, nd.y, nd.z), qt_probe_dev(g.qn, nd.x - 1ll, nd.y, nd.z),
+                        qt_probe_dev(g.qn, nd.x, nd.y + side, nd.z), qt_probe_dev(g.qn, nd.x, nd.y - 1ll, nd.z));
 }
 
 __device__ __forceinline__ void stats_zero(WaveLDS& S) {
@@ -1116,7 +1271,7 @@ __global__ void __launch_bounds__(WAVE) k_g_commit(DevState s, GlobalDev g,
             const int p = mv[m].point;
             const int2 q = g.pq[m];
             const int oc = g.powner[p];
-            const int nc = owner_after_move(g, oc, q);
+            const int nc = cell_after_move(g, oc, q, mv[m].dir);
             if (lane == 0) {
                 B.xy[p] = q;
                 if (nc != oc) g.powner[p] = nc;
@@ -1164,7 +1319,7 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
         const int oc = g.powner[p];
         const int rc = apply_move(B, S, mv[m], fr, &S.st, &app);
         gsync();  // the new position is visible to every lane
-        const int nc = rc == ST_OK && app ? owner_after_move(g, oc, s.xy[p]) : oc;
+        const int nc = rc == ST_OK && app ? cell_after_move(g, oc, s.xy[p], mv[m].dir) : oc;
         if (lane == 0) {
             if (rc != ST_OK) fail_global(s, rc);
             if (nc != oc) {
@@ -2029,11 +2184,11 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
 // Global mode: the extra regions after the per-block layout of one block.
 struct GLayout {
     size_t claim, mstate, rs, rsn, pslot, prec, pvt, phdr, pq, hkey, hcnt, ctr, serial, split, powner, gstats,
-        part, att, pend, plan, deferred, big, total;
+        part, att, pend, plan, deferred, big, qn, ql, qcnt, qlev, total;
     int hsize;
 };
 
-GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves) {
+GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves, int64_t n_qt = 0) {
     GLayout G;
     size_t o = align_up(base);
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
@@ -2063,6 +2218,10 @@ GLayout make_glayout(size_t base, int64_t n, int32_t depth, int32_t max_moves) {
     G.plan = take(sizeof(int2) * GB_CHUNK);
     G.deferred = take(sizeof(int) * GB_DEFER);
     G.big = take(sizeof(int) * (4 * (size_t)GB_BIG + 6));
+    G.qn = take(sizeof(int4) * (size_t)std::max<int64_t>(n_qt, 1));
+    G.ql = take(sizeof(int4) * (size_t)std::max<int64_t>(n_qt, 1));
+    G.qcnt = take(sizeof(int) * (size_t)std::max<int64_t>(n_qt, 1));
+    G.qlev = take(sizeof(int) * (QT_LEVELS + 1));
     G.total = o;
     return G;
 }
@@ -2085,6 +2244,79 @@ void kd_build(const int32_t* xy, std::vector<int>& idx, size_t lo, size_t hi, in
     split[node] = make_int2(k.first, k.second);
     kd_build(xy, idx, lo, h, 2 * node, level + 1, depth, split, cell);
     kd_build(xy, idx, h, hi, 2 * node + 1, level + 1, depth, split, cell);
+}
+
+// Quad-tree of the initial points (Sec. III "Data structure"): the root is
+// the smallest power-of-two square at the domain's lower-left corner that
+// covers the domain; a node holding more than `thr` points (and wider than
+// one lattice cell) is cut into its four quarters, kept in the order (low x,
+// low y), (high x, low y), (low x, high y), (high x, high y) -- empty
+// quarters too, so that the leaves tile the square.  nodes: {x0, y0, log2
+// side, first child or -1}; cell: the leaf of every point.
+struct QtHost {
+    std::vector<int4> nodes, links;
+    std::vector<int> cell;
+};
+void qt_node(const int32_t* xy, std::vector<int>& idx, size_t lo, size_t hi, int node, int64_t thr, QtHost& T) {
+    const int4 nd = T.nodes[node];
+    if ((int64_t)(hi - lo) <= thr || nd.z == 0) {
+        for (size_t i = lo; i < hi; ++i) T.cell[idx[i]] = node;
+        return;
+    }
+    const int h = 1 << (nd.z - 1);
+    const int c0 = (int)T.nodes.size();
+    T.nodes[node].w = c0;
+    for (int q = 0; q < 4; ++q) T.nodes.push_back(make_int4(nd.x + (q & 1) * h, nd.y + (q >> 1) * h, nd.z - 1, -1));
+    auto quad = [&](int a) {
+        return (xy[2 * (size_t)a] >= nd.x + h ? 1 : 0) + (xy[2 * (size_t)a + 1] >= nd.y + h ? 2 : 0);
+    };
+    size_t cut[5];
+    cut[0] = lo;
+    for (int q = 0; q < 4; ++q) {
+        const auto mid = std::stable_partition(idx.begin() + cut[q], idx.begin() + hi, [&](int a) { return quad(a) == q; });
+        cut[q + 1] = (size_t)(mid - idx.begin());
+    }
+    for (int q = 0; q < 4; ++q) qt_node(xy, idx, cut[q], cut[q + 1], c0 + q, thr, T);
+}
+// The node across each side of every leaf: the node holding the first
+// lattice cell past that side, at the leaf's size or larger.
+int qt_probe(const QtHost& T, int64_t px, int64_t py, int lg) {
+    const int4 r = T.nodes[0];
+    const int64_t side = (int64_t)1 << r.z;
+    if (px < r.x || py < r.y || px >= r.x + side || py >= r.y + side) return -1;
+    int node = 0;
+    while (T.nodes[node].w >= 0 && T.nodes[node].z > lg) {
+        const int4 nd = T.nodes[node];
+        const int64_t h = (int64_t)1 << (nd.z - 1);
+        node = nd.w + (px >= nd.x + h ? 1 : 0) + (py >= nd.y + h ? 2 : 0);
+    }
+    return node;
+}
+void qt_build_host(const int32_t* xy, int64_t n, const int32_t* domain, int64_t thr, QtHost& T) {
+    int lg = 0;
+    const int32_t ext = std::max(domain[2] - domain[0], domain[3] - domain[1]);
+    while ((1 << lg) < ext) ++lg;
+    T.nodes.assign(1, make_int4(domain[0], domain[1], lg, -1));
+    T.cell.assign(n, 0);
+    std::vector<int> idx(n);
+    for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+    qt_node(xy, idx, 0, (size_t)n, 0, thr, T);
+    T.links.assign(T.nodes.size(), make_int4(-1, -1, -1, -1));
+    for (size_t k = 0; k < T.nodes.size(); ++k) {
+        const int4 nd = T.nodes[k];
+        if (nd.w >= 0) continue;
+        const int64_t side = (int64_t)1 << nd.z;
+        T.links[k] = make_int4(qt_probe(T, nd.x + side, nd.y, nd.z), qt_probe(T, (int64_t)nd.x - 1, nd.y, nd.z),
+                               qt_probe(T, nd.x, nd.y + side, nd.z), qt_probe(T, nd.x, (int64_t)nd.y - 1, nd.z));
+    }
+}
+
+// Nodes the quad-tree arrays hold: the initial tree, and any tree of n
+// points with this threshold (a level cuts at most n / (thr + 1) nodes,
+// each into 4, over at most log2 side levels).
+int64_t qt_capacity(const QtHost& T, int64_t n, int64_t thr) {
+    const int64_t lg = T.nodes.empty() ? 0 : T.nodes[0].z;
+    return std::max<int64_t>((int64_t)T.nodes.size(), 1 + 4 * lg * ((n + thr) / (thr + 1)));
 }
 
 // Hilbert index of (x, y) on a 2^16 x 2^16 grid (classic rotate-and-flip
@@ -2145,6 +2377,8 @@ struct kdt_ctx {
     int hsize = 0;
     GlobalDev g{};
     GBuild gb{};
+    int qt_count = 0;        // quad-tree cells: nodes in use
+    bool qt_every_step = false;  // re-partition after every step
     long long build_rounds = 0;
 };
 
@@ -3281,8 +3515,37 @@ int kdt_workspace_size_global(int64_t n, int32_t depth, int32_t max_moves, size_
     return KDT_OK;
 }
 
-int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, const int32_t* domain,
-                    int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+// Quad-treeDvision of the current positions on the device (k_qt_*), level
+// by level; the host reads each level's cut count to know when to stop.
+static int qt_repartition(kdt_ctx* c) {
+    hipStream_t st = c->stream;
+    const int n = (int)c->n;
+    k_qt_reset<<<(n + 255) / 256, 256, 0, st>>>(c->g, n);
+    int nodes = 1;
+    for (int lvl = 0; lvl + 2 < QT_LEVELS; ++lvl) {
+        k_qt_alloc<<<1, 1024, 0, st>>>(c->g, lvl);
+        int info[2] = {0, 0};
+        if (check_hip(c, hipGetLastError()) ||
+            check_hip(c, hipMemcpyAsync(&info[0], c->g.qlev + lvl + 2, sizeof(int), hipMemcpyDeviceToHost, st)) ||
+            check_hip(c, hipMemcpyAsync(&info[1], c->g.qlev + QT_LEVELS, sizeof(int), hipMemcpyDeviceToHost, st)) ||
+            check_hip(c, hipStreamSynchronize(st)))
+            return KDT_E_DEVICE;
+        if (info[1] < 0) return KDT_E_CAPACITY;
+        nodes = info[0];
+        if (info[1] == 0) break;
+        k_qt_down<<<(n + 255) / 256, 256, 0, st>>>(c->dev, c->g, n);
+    }
+    k_qt_links<<<(nodes + 255) / 256, 256, 0, st>>>(c->g, nodes);
+    c->qt_count = nodes;
+    return check_hip(c, hipGetLastError());
+}
+
+// A global context with kd cells of depth `depth` (qt_thr == 0) or the
+// quad-tree cells of threshold qt_thr.
+static int init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, int64_t qt_thr,
+                       const int32_t* domain, int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream) {
     if (!out) return KDT_E_ARG;
     *out = nullptr;
     if (!xy || !domain || n < 1 || depth < 0 || depth > 20 || max_moves < 1 || max_moves > (1 << 22))
@@ -3319,14 +3582,20 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     std::sort(key.begin(), key.end());
     std::vector<int> order(n);
     for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
-    // kd cells of the initial points
+    // kd cells or quad-tree cells of the initial points
     std::vector<int2> split((size_t)1 << depth, make_int2(0, 0));
     std::vector<int> cell(n), idx(n);
-    for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
-    kd_build(xy, idx, 0, (size_t)n, 1, 0, depth, split, cell);
+    QtHost QT;
+    if (qt_thr > 0) {
+        qt_build_host(xy, n, domain, qt_thr, QT);
+        cell = QT.cell;
+    } else {
+        for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+        kd_build(xy, idx, 0, (size_t)n, 1, 0, depth, split, cell);
+    }
 
     const Layout L = make_layout(n, 1, 0);
-    const GLayout G = make_glayout(L.total, n, depth, max_moves);
+    const GLayout G = make_glayout(L.total, n, depth, max_moves, qt_thr > 0 ? qt_capacity(QT, n, qt_thr) : 0);
     if (!dev_ws || ws_bytes < G.total) return KDT_E_CAPACITY;
     if (((uintptr_t)dev_ws & 255) != 0) return KDT_E_ARG;
     kdt_ctx* c = new (std::nothrow) kdt_ctx();
@@ -3383,6 +3652,14 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     c->g.serial = (int*)(w + G.serial);
     c->g.split = (const int2*)(w + G.split);
     c->g.depth = depth;
+    c->g.qt = qt_thr > 0 ? 1 : 0;
+    c->g.qn = (int4*)(w + G.qn);
+    c->g.ql = (int4*)(w + G.ql);
+    c->g.qcnt = (int*)(w + G.qcnt);
+    c->g.qlev = (int*)(w + G.qlev);
+    c->g.qcap = qt_thr > 0 ? (int)qt_capacity(QT, n, qt_thr) : 0;
+    c->g.qthr = qt_thr;
+    c->qt_count = (int)QT.nodes.size();
     c->g.powner = (int*)(w + G.powner);
     c->g.gstats = (unsigned long long*)(w + G.gstats);
     c->g.part = (unsigned long long*)(w + G.part);
@@ -3403,6 +3680,12 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     rc |= check_hip(c, hipMemcpyAsync(w + L.tri_off, c->tri_off.data(), sizeof(long long) * 2, hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemcpyAsync(w + L.frame, &fr, sizeof(int4), hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemcpyAsync(w + G.split, split.data(), sizeof(int2) * split.size(), hipMemcpyHostToDevice, s));
+    if (qt_thr > 0) {
+        rc |= check_hip(c, hipMemcpyAsync(w + G.qn, QT.nodes.data(), sizeof(int4) * QT.nodes.size(),
+                                          hipMemcpyHostToDevice, s));
+        rc |= check_hip(c, hipMemcpyAsync(w + G.ql, QT.links.data(), sizeof(int4) * QT.links.size(),
+                                          hipMemcpyHostToDevice, s));
+    }
     rc |= check_hip(c, hipMemcpyAsync(w + G.powner, cell.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemcpyAsync(w + G.ctr, ctr, sizeof(ctr), hipMemcpyHostToDevice, s));
     rc |= check_hip(c, hipMemsetAsync(w + L.status, 0, sizeof(int), s));
@@ -3418,6 +3701,76 @@ int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, 
     rc = gbuild(c);
     if (rc != KDT_OK) { delete c; return rc; }
     *out = c;
+    return KDT_OK;
+}
+
+extern "C" {
+
+int kdt_init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t depth, const int32_t* domain,
+                    int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream) {
+    return init_global(out, xy, n, depth, 0, domain, max_moves, dev_ws, ws_bytes, stream);
+}
+
+int kdt_workspace_size_global_qt(const int32_t* xy, int64_t n, const int32_t* domain, int64_t threshold,
+                                 int32_t max_moves, size_t* dev_bytes) {
+    if (!dev_bytes || !xy || !domain || n < 1 || threshold < 1 || max_moves < 1 || max_moves > (1 << 22))
+        return KDT_E_ARG;
+    if (n > (1 << 22)) return KDT_E_CAPACITY;
+    if (domain[0] < 0 || domain[1] < 0 || domain[2] > KDT_COORD_LIMIT || domain[3] > KDT_COORD_LIMIT ||
+        domain[0] >= domain[2] || domain[1] >= domain[3])
+        return KDT_E_RANGE;
+    for (int64_t i = 0; i < n; ++i)
+        if (xy[2 * i] < domain[0] || xy[2 * i] >= domain[2] || xy[2 * i + 1] < domain[1] || xy[2 * i + 1] >= domain[3])
+            return KDT_E_RANGE;
+    QtHost QT;
+    qt_build_host(xy, n, domain, threshold, QT);
+    const Layout L = make_layout(n, 1, 0);
+    *dev_bytes = make_glayout(L.total, n, 0, max_moves, qt_capacity(QT, n, threshold)).total;
+    return KDT_OK;
+}
+
+int kdt_init_global_qt(kdt_ctx** out, const int32_t* xy, int64_t n, const int32_t* domain, int64_t threshold,
+                       int32_t max_moves, void* dev_ws, size_t ws_bytes, void* stream) {
+    if (threshold < 1) {
+        if (out) *out = nullptr;
+        return KDT_E_ARG;
+    }
+    return init_global(out, xy, n, 0, threshold, domain, max_moves, dev_ws, ws_bytes, stream);
+}
+
+int kdt_quadtree(kdt_ctx* c, int32_t* host_nodes, int32_t cap, int32_t* n_nodes) {
+    if (!c || !n_nodes || cap < 0 || (cap > 0 && !host_nodes)) return KDT_E_ARG;
+    if (!c->global || !c->g.qt) return KDT_E_STATE;
+    const int rc = kdt_sync(c);
+    if (rc != KDT_OK) return rc;
+    const int nn = c->qt_count;
+    *n_nodes = nn;
+    if (nn > cap) return KDT_E_CAPACITY;
+    std::vector<int4> nd(nn), lk(nn);
+    if (check_hip(c, hipMemcpy(nd.data(), c->g.qn, sizeof(int4) * nn, hipMemcpyDeviceToHost)) ||
+        check_hip(c, hipMemcpy(lk.data(), c->g.ql, sizeof(int4) * nn, hipMemcpyDeviceToHost)))
+        return KDT_E_DEVICE;
+    for (int k = 0; k < nn; ++k) {
+        int32_t* r = host_nodes + 8 * (int64_t)k;
+        r[0] = nd[k].x; r[1] = nd[k].y; r[2] = 1 << nd[k].z; r[3] = nd[k].w;
+        const bool leaf = nd[k].w < 0;
+        r[4] = leaf ? lk[k].x : -1; r[5] = leaf ? lk[k].y : -1; r[6] = leaf ? lk[k].z : -1; r[7] = leaf ? lk[k].w : -1;
+    }
+    return KDT_OK;
+}
+
+int kdt_repartition(kdt_ctx* c) {
+    if (!c) return KDT_E_ARG;
+    if (!c->global || !c->g.qt || c->sticky != KDT_OK) return KDT_E_STATE;
+    const int rc = qt_repartition(c);
+    if (rc != KDT_OK) c->sticky = rc;
+    return rc;
+}
+
+int kdt_set_repartition(kdt_ctx* c, int32_t every_step) {
+    if (!c || every_step < 0 || every_step > 1) return KDT_E_ARG;
+    if (!c->global || !c->g.qt) return KDT_E_STATE;
+    c->qt_every_step = every_step != 0;
     return KDT_OK;
 }
 
@@ -3445,6 +3798,13 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
             k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r, r == G_ROUNDS - 1 ? 1 : 0, ap);
         }
         k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap, parts);
+        if (c->qt_every_step) {  // Quad-treeDvision after the step (Fig. 4)
+            const int rc = qt_repartition(c);
+            if (rc != KDT_OK) {
+                c->sticky = rc;
+                return rc;
+            }
+        }
         timing_end(c, e0);
         if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
         c->step_count++;

@@ -30,13 +30,15 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair")
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair",
+           "kdt_workspace_size_global_qt", "kdt_init_global_qt", "kdt_quadtree", "kdt_repartition",
+           "kdt_set_repartition")
 REPAIR = {"delins": 0, "flip": 1}
 MLP_NOALLOC_BATCH = 4096
 PART = {"grid": 0, "quadtree": 1}
 
 # kdt_global_stats counters, in order
-GSTATS = ("interacting", "serial", "lost", "transfers", "overflow", "build_rounds")
+GSTATS = ("interacting", "serial", "lost", "transfers", "overflow", "build_rounds", "link", "tree")
 GSTAT_N = 8
 
 
@@ -98,6 +100,11 @@ def _lib():
         L.kdt_set_launch.argtypes = [vp, i32]
         L.kdt_set_block_waves.argtypes = [vp, i32]
         L.kdt_set_repair.argtypes = [vp, i32]
+        L.kdt_workspace_size_global_qt.argtypes = [vp, i64, vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.kdt_init_global_qt.argtypes = [ctypes.POINTER(vp), vp, i64, vp, i64, i32, vp, ctypes.c_size_t, vp]
+        L.kdt_quadtree.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.kdt_repartition.argtypes = [vp]
+        L.kdt_set_repartition.argtypes = [vp, i32]
         L.kdt_dcalc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
         L.kdt_graph_launch.argtypes = [vp, vp]
@@ -442,10 +449,12 @@ def workspace_size_global(n, depth, max_moves):
 
 class GlobalDT(KineticDT):
     """A global-mode context: one DT* over every point of the domain
-    (x0, y0, x1, y1), kd cells of depth `depth`, at most `max_moves` moves
-    per step.  Query, digest, positions and stats as for one block."""
+    (x0, y0, x1, y1), kd cells of depth `depth` -- or, with `quadtree` =
+    threshold, the leaves of the quad-tree of the initial points -- and at
+    most `max_moves` moves per step.  Query, digest, positions and stats as
+    for one block."""
 
-    def __init__(self, xy, domain, depth, max_moves, device="cuda:0", stream=None):
+    def __init__(self, xy, domain, depth, max_moves, device="cuda:0", stream=None, quadtree=None):
         L = _lib()
         self.xy0 = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
         self.domain = np.ascontiguousarray(domain, dtype=np.int32).reshape(4)
@@ -455,15 +464,45 @@ class GlobalDT(KineticDT):
         self.B = 1
         self.pt_off = np.array([0, self.n], dtype=np.int64)
         self.device = torch.device(device)
-        ws = workspace_size_global(self.n, self.depth, self.max_moves)
-        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
-        rc = L.kdt_init_global(ctypes.byref(ctx), _ptr(self.xy0), self.n, self.depth, _ptr(self.domain),
-                               self.max_moves, ctypes.c_void_p(self.ws.data_ptr()), ws,
-                               ctypes.c_void_p(self.stream.cuda_stream))
-        _check(rc, "kdt_init_global")
+        if quadtree:
+            out = ctypes.c_size_t(0)
+            _check(L.kdt_workspace_size_global_qt(_ptr(self.xy0), self.n, _ptr(self.domain), int(quadtree),
+                                                  self.max_moves, ctypes.byref(out)), "kdt_workspace_size_global_qt")
+            ws = int(out.value)
+            self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+            rc = L.kdt_init_global_qt(ctypes.byref(ctx), _ptr(self.xy0), self.n, _ptr(self.domain), int(quadtree),
+                                      self.max_moves, ctypes.c_void_p(self.ws.data_ptr()), ws,
+                                      ctypes.c_void_p(self.stream.cuda_stream))
+            _check(rc, "kdt_init_global_qt")
+        else:
+            ws = workspace_size_global(self.n, self.depth, self.max_moves)
+            self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
+            rc = L.kdt_init_global(ctypes.byref(ctx), _ptr(self.xy0), self.n, self.depth, _ptr(self.domain),
+                                   self.max_moves, ctypes.c_void_p(self.ws.data_ptr()), ws,
+                                   ctypes.c_void_p(self.stream.cuda_stream))
+            _check(rc, "kdt_init_global")
         self.ctx = ctx
+
+    def repartition(self):
+        """Quad-treeDvision of the current positions (kdt_repartition)."""
+        _check(_lib().kdt_repartition(self.ctx), "kdt_repartition")
+
+    def set_repartition(self, every_step=True):
+        _check(_lib().kdt_set_repartition(self.ctx, 1 if every_step else 0), "kdt_set_repartition")
+
+    def quadtree(self):
+        """int32 [nodes, 8]: (x0, y0, side, first child, links +x, -x, +y, -y
+        of a leaf)."""
+        L = _lib()
+        nn = ctypes.c_int32(0)
+        rc = L.kdt_quadtree(self.ctx, None, 0, ctypes.byref(nn))
+        if rc not in (OK, E_CAPACITY):
+            _check(rc, "kdt_quadtree")
+        out = np.zeros((max(1, nn.value), 8), dtype=np.int32)
+        _check(L.kdt_quadtree(self.ctx, _ptr(out), nn.value, ctypes.byref(nn)), "kdt_quadtree")
+        return out[:nn.value]
 
     def run(self, moves, step_off, applied=None):
         """moves: device int32 [M, 4] (global point id, dir, dist, 0);
