@@ -158,10 +158,10 @@ def other_workload(args):
         ev_steps = args.other_steps or 10
         log(f"{name}: calibration workload (seed {100 + args.seed})")
         calib = gen(seed=100 + args.seed, steps=cal_steps)
-        X, Y = S.collect(calib, cal_steps, dev)
+        X, Y, cal_step = S.collect_steps(calib, cal_steps, dev)
         del calib
         wts = S.train(X, Y, epochs=300, batch=2048, lr=0.02, device=dev)
-        tau = S.calibrate_threshold(X, Y)
+        tau = S.calibrate_threshold_cp(X, Y, cal_step)
         log(f"trained on {len(X)} samples, tau = {tau:.3f}; evaluation workload (seed {args.seed})")
         evalw = gen(seed=args.seed, steps=ev_steps)
         res = S.evaluate(evalw, ev_steps, torch.from_numpy(wts).to(dev), tau, dev)
@@ -174,7 +174,8 @@ def other_workload(args):
         out = {"workload": desc, "steps": ev_steps, "train_samples": int(len(X)), "tau": tau, "policies": res}
         for pol, r in res.items():
             log(f"{name} {pol}: {r['seconds'] * 1e3:.2f} ms, rebuilt fraction {r['rebuild_fraction']:.3f}, "
-                f"chosen/best ticks {r['chosen_ticks'] / max(r['best_ticks'], 1):.3f}")
+                f"chosen/best ticks {r['chosen_ticks'] / max(r['best_ticks'], 1):.3f}, "
+                f"critical path chosen/best {r['cp_ticks'] / max(r['cp_best_ticks'], 1):.3f}")
         print(json.dumps(out), flush=True)
         return
     if name == "lattice256":
@@ -507,17 +508,25 @@ def headline(args):
     # another seed (forced-repair and forced-rebuild runs give both costs)
     t0 = time.perf_counter()
     cal = W.multi2048(seed=100 + args.seed, steps=CAL_STEPS)
-    X, Y = S.collect(cal, CAL_STEPS, dev)
+    X, Y, cal_step = S.collect_steps(cal, CAL_STEPS, dev)
     mlp = torch.from_numpy(S.train(X, Y, epochs=200, batch=2048, lr=0.02, device=dev)).to(dev)
-    tau = S.calibrate_threshold(X, Y)
+    tau = S.calibrate_threshold_cp(X, Y, cal_step)  # on the step's critical path
+    tau_sum = S.calibrate_threshold(X, Y)           # on summed block costs, for comparison
     log(f"selector trained on {len(X)} block-steps of seed {100 + args.seed} "
-        f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.2f}")
+        f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.2f} on the critical path, "
+        f"{tau_sum:.2f} on summed costs")
     pol_mlp = ("mlp", 0.0, mlp)
-    best = A.autotune(cal, steps=CAL_STEPS, candidates=HEADLINE_FORMS, device=dev, use_cache=False,
-                      policy=pol_mlp)
-    form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves") if k in best}
-    log("autotuner (calibration workload, MLP policy): " + ", ".join(
-        f"{form_name(r)} {r['s_per_step'] * 1e3:.3f} ms" for r in best["table"]) + f" -> {form_name(form)}")
+    if args.form:  # a fixed launch form (profiling runs)
+        form = {"step": {"mode": "step", "graph": False}, "step_graph": {"mode": "step", "graph": True},
+                "fused": {"mode": "fused", "graph": False}}[args.form]
+        autotune_table = None
+    else:
+        best = A.autotune(cal, steps=CAL_STEPS, candidates=HEADLINE_FORMS, device=dev, use_cache=False,
+                          policy=pol_mlp)
+        form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves") if k in best}
+        autotune_table = {form_name(r): r["s_per_step"] * 1e3 for r in best["table"]}
+        log("autotuner (calibration workload, MLP policy): " + ", ".join(
+            f"{form_name(r)} {r['s_per_step'] * 1e3:.3f} ms" for r in best["table"]) + f" -> {form_name(form)}")
     del cal
     t0 = time.perf_counter()
     w = W.multi2048(seed=args.seed, steps=Wu + K)
@@ -543,6 +552,7 @@ def headline(args):
         runs += [(form_name(form) + "_repair_only", form, ("repair", 0.0, None), K),
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
+                 (form_name(form) + "_threshold_summed_tau", form, ("threshold", tau_sum, None), K),
                  (form_name(form) + "_dlimit", form, ("dlimit", 1.0, None), K),
                 (form_name(dict(form, repair="flip")) + "_mlp", dict(form, repair="flip"), pol_mlp, K),
                  ("per_step_rebuild_only", {"mode": "step", "graph": False}, ("rebuild", 0.0, None), min(10, K))]
@@ -618,6 +628,7 @@ def headline(args):
         "blocked_moves": blocked,
         "rebuilt_block_steps": rebuilt,
         "variants": variants,
+        "autotune_ms_per_step": autotune_table,
         "d_calculation": dcal,
         "phase_us_per_move": phases,
         "mtri_touched_per_s": touched / (ms / 1e3) / 1e6,
@@ -666,6 +677,8 @@ def main():
                     choices=["multi2048", "grid1024", "lattice256", "uneven4096", "selector_mix", "global4m"],
                     help="multi2048 is the measured configuration; the others print a secondary report")
     ap.add_argument("--other-steps", type=int, default=0, help="steps for the secondary reports")
+    ap.add_argument("--form", choices=["step", "step_graph", "fused"], default=None,
+                    help="headline: this launch form instead of the autotuner's pick (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

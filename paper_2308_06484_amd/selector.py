@@ -5,7 +5,11 @@ points move far (Sec. I, abstract).  Here that choice is made per block and
 time step by a small network (16 -> 32 -> 32 -> 2) that predicts the log2
 device-clock cost of each branch from the block's features; a threshold on
 the summed move distance (in units of the block's point spacing) is the
-fallback.  Features, costs and branch choices are produced by the library's
+fallback.  Every block of a step runs at once, so a step lasts as long as
+its slowest block: choosing the cheaper branch for every block also
+minimises each step's slowest block, so the network predicts per-block
+costs, while the threshold is calibrated and the choices are judged on
+that critical path (the sum over steps of the slowest block's cost).  Features, costs and branch choices are produced by the library's
 kernels (the per-step log), and the network is trained by the library's own
 forward/backward/SGD kernels; this module only arranges the runs, the
 feature normalisation (folded into the first layer afterwards) and the
@@ -48,10 +52,11 @@ def run_policy(w, steps, policy, device="cuda:0", tau=0.0, mlp_w=None, log=True)
     return out, secs, st
 
 
-def collect(w, steps, device="cuda:0"):
+def collect_steps(w, steps, device="cuda:0"):
     """Training samples: features and the log2 cost of both branches for
     every (step, block) with moves, from a forced-repair and a forced-rebuild
-    run of the same workload (identical states: DT* is unique)."""
+    run of the same workload (identical states: DT* is unique), and the step
+    of each sample."""
     lr_, _, _ = run_policy(w, steps, "repair", device)
     lb_, _, _ = run_policy(w, steps, "rebuild", device)
     # block-steps with moves; a repair that hit the repair path's capacity
@@ -60,6 +65,12 @@ def collect(w, steps, device="cuda:0"):
     X = lr_[..., :IN][valid].astype(np.float32)
     Y = np.stack([np.log2(np.maximum(lr_[..., 17][valid], 1.0)),
                   np.log2(np.maximum(lb_[..., 17][valid], 1.0))], axis=1).astype(np.float32)
+    step = np.nonzero(valid)[0]
+    return X, Y, step
+
+
+def collect(w, steps, device="cuda:0"):
+    X, Y, _ = collect_steps(w, steps, device)
     return X, Y
 
 
@@ -108,6 +119,31 @@ def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0"):
     return fold_normalisation(w, mu, sd)
 
 
+def step_time(cost, step):
+    """A step lasts as long as its slowest block (every block of a step
+    runs at once): the sum over steps of the largest cost."""
+    out = np.zeros(int(step.max()) + 1 if len(step) else 0)
+    np.maximum.at(out, step, cost)
+    return float(out.sum())
+
+
+def calibrate_threshold_cp(X, Y, step, candidates=256):
+    """tau for "rebuild iff sum d/s > tau" that minimises the step time --
+    the sum over steps of the slowest block's cost, the critical path --
+    on the samples (candidates: quantiles of the observed values, rebuild
+    everything, rebuild nothing).  A choice that makes one block of a step slower costs
+    the whole step; per-block sums would not see it."""
+    f = X[:, 3].astype(np.float64)
+    cr, cb = np.exp2(Y[:, 0].astype(np.float64)), np.exp2(Y[:, 1].astype(np.float64))
+    cand = np.unique(np.concatenate([np.quantile(f, np.linspace(0, 1, candidates)), [f.min() - 1.0, f.max() + 1.0]]))
+    best_tau, best = float(f.max() + 1.0), np.inf
+    for tau in cand:
+        t = step_time(np.where(f > tau, cb, cr), step)
+        if t < best:
+            best, best_tau = t, float(tau)
+    return best_tau
+
+
 def calibrate_threshold(X, Y):
     """tau for the rule "rebuild iff sum d/s > tau" that minimises the
     summed cost on the samples (candidates: the observed values)."""
@@ -130,13 +166,16 @@ def regret(branch_log, cost_repair, cost_rebuild, valid):
     one's (device ticks), and the total cost of the choices."""
     cr, cb = cost_repair[valid], cost_rebuild[valid]
     ch = branch_log[valid]
-    chosen = np.where(ch > 0.5, cb, cr)
+    chosen = np.where(ch == 1, cb, cr)  # 2: a repair that fell back (no clean cost): counted as repair
     best = np.minimum(cr, cb)
     return float((chosen - best).sum()), float(chosen.sum()), float(best.sum())
 
 
 def evaluate(w, steps, mlp_w, tau, device="cuda:0"):
-    """Wall time and regret of every policy on the workload."""
+    """Wall time and regret of every policy on the workload: the summed
+    regret over block-steps and the critical-path regret (the sum over steps
+    of the slowest block's cost under the policy's choices, minus the same
+    under the cheaper branch of every block, from the forced runs' costs)."""
     res = {}
     logs = {}
     for pol in ("repair", "rebuild", "threshold", "mlp"):
@@ -145,9 +184,14 @@ def evaluate(w, steps, mlp_w, tau, device="cuda:0"):
         res[pol] = {"seconds": secs, "applied": st["applied"], "rebuilt_block_steps": st["rebuilt"],
                     "moves_per_s": st["applied"] / secs}
     valid = logs["repair"][..., 18] > 0
+    step = np.nonzero(valid)[0]
     cr, cb = logs["repair"][..., 17], logs["rebuild"][..., 17]
+    best_cp = step_time(np.minimum(cr[valid], cb[valid]).astype(np.float64), step)
     for pol in res:
         r, tot, best = regret(logs[pol][..., 16], cr, cb, valid)
+        chosen = np.where(logs[pol][..., 16][valid] == 1, cb[valid], cr[valid]).astype(np.float64)
+        cp = step_time(chosen, step)
         res[pol].update(regret_ticks=r, chosen_ticks=tot, best_ticks=best,
-                        rebuild_fraction=float(logs[pol][..., 16][valid].mean()))
+                        cp_ticks=cp, cp_best_ticks=best_cp, cp_regret_ticks=cp - best_cp,
+                        rebuild_fraction=float((logs[pol][..., 16][valid] == 1).mean()))
     return res

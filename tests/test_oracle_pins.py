@@ -13,7 +13,7 @@ import json
 import math
 import os
 from fractions import Fraction
-from itertools import permutations
+from itertools import combinations, permutations
 
 import numpy as np
 import pytest
@@ -299,3 +299,55 @@ def test_certificate_rejects_planted_mistakes():
         certificate.check(xy, np.arange(25), bad)
     with pytest.raises(AssertionError):
         certificate.check(xy, np.arange(25), good[1:])
+
+
+def test_every_subset_of_4x4_lattice_three_labelings():
+    """Exhaustive over the 4 x 4 lattice: all 2^16 subsets of at least 3
+    points, 3 labelings of the 16 points each.  The definition is evaluated
+    once per labeling as a table -- for every counter-clockwise triple of
+    lattice points, the set of other lattice points its perturbed circle
+    holds -- so DT*(M) of a subset M is every triple inside M whose table
+    set misses M.  All-collinear subsets have no triangulation: the oracle
+    refuses them."""
+    pts = [(x, y) for y in range(4) for x in range(4)]
+    tri_ids = list(combinations(range(16), 3))
+    masks = np.arange(1 << 16, dtype=np.int64)
+    popc = np.array([bin(m).count("1") for m in range(1 << 16)])
+    rng = np.random.default_rng(44)
+    checked = 0
+    for lab in range(3):
+        label = np.arange(16) if lab == 0 else rng.permutation(16) * 5 + 2
+        ccw, bits, bad, canon = [], [], [], []
+        for i, j, k in tri_ids:
+            o = D.orient(pts[i], pts[j], pts[k])
+            if o == 0:
+                continue
+            if o < 0:
+                j, k = k, j
+            m = 0
+            for d in range(16):
+                if d in (i, j, k):
+                    continue
+                if D.incircle_star(pts[i], pts[j], pts[k], pts[d], label[i], label[j], label[k], label[d]) > 0:
+                    m |= 1 << d
+            ccw.append((i, j, k))
+            bits.append((1 << i) | (1 << j) | (1 << k))
+            bad.append(m)
+            canon.append(D.canonical([(int(label[i]), int(label[j]), int(label[k]))])[0])
+        bits, bad = np.array(bits, np.int64), np.array(bad, np.int64)
+        inside = ((bits[None, :] & ~masks[:, None]) == 0) & ((bad[None, :] & masks[:, None]) == 0)
+        for mask in range(1 << 16):
+            if popc[mask] < 3:
+                continue
+            idx = [i for i in range(16) if mask >> i & 1]
+            sub = [pts[i] for i in idx]
+            ids = [int(label[i]) for i in idx]
+            want = sorted(canon[t] for t in np.nonzero(inside[mask])[0])
+            if not want:  # every point on one line
+                with pytest.raises(oracle.OracleError):
+                    oracle.dt_star(sub, ids)
+                continue
+            got = [tuple(t) for t in oracle.dt_star(sub, ids).tolist()]
+            assert got == want, (lab, mask)
+            checked += 1
+    assert checked > 3 * 65000

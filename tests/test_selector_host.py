@@ -1,0 +1,37 @@
+"""Host logic of the selector (no GPU): the threshold calibrated on the
+step's critical path against a brute force over every threshold, and a case
+where summing per-block costs picks the wrong rule."""
+import numpy as np
+
+from paper_2308_06484_amd import selector as S
+
+
+def _cp_brute(X, Y, step, tau):
+    cost = np.where(X[:, 3] > tau, np.exp2(Y[:, 1]), np.exp2(Y[:, 0])).astype(np.float64)
+    return sum(cost[step == t].max() for t in np.unique(step))
+
+
+def test_critical_path_threshold_is_optimal_among_thresholds():
+    rng = np.random.default_rng(0)
+    for trial in range(20):
+        m = int(rng.integers(5, 60))
+        X = np.zeros((m, 16), np.float32)
+        X[:, 3] = rng.integers(0, 30, size=m)
+        Y = rng.uniform(1, 12, size=(m, 2)).astype(np.float32)
+        step = np.sort(rng.integers(0, 6, size=m))
+        tau = S.calibrate_threshold_cp(X, Y, step, candidates=4096)
+        got = _cp_brute(X, Y, step, tau)
+        best = min(_cp_brute(X, Y, step, t) for t in list(np.unique(X[:, 3])) + [-1.0, 1e9])
+        assert np.isclose(got, best), trial
+
+
+def test_summed_costs_pick_a_rule_that_slows_the_step():
+    # one step, two blocks with the same feature: rebuilding both saves
+    # summed cost (141 < 150) but makes the slowest block slower (140 > 100)
+    X = np.zeros((2, 16), np.float32)
+    X[:, 3] = 10.0
+    Y = np.log2(np.array([[100.0, 1.0], [50.0, 140.0]])).astype(np.float32)
+    step = np.array([0, 0])
+    assert S.calibrate_threshold(X, Y) < 10.0          # rebuild both
+    assert S.calibrate_threshold_cp(X, Y, step) >= 10.0  # repair both
+    assert np.isclose(S.step_time(np.array([100.0, 50.0]), step), 100.0)
