@@ -158,10 +158,10 @@ def other_workload(args):
         ev_steps = args.other_steps or 10
         log(f"{name}: calibration workload (seed {100 + args.seed})")
         calib = gen(seed=100 + args.seed, steps=cal_steps)
-        X, Y, cal_step = S.collect_steps(calib, cal_steps, dev)
+        X, Y, cal_step, cal_after = S.collect_steps(calib, cal_steps, dev)
         del calib
         wts = S.train(X, Y, epochs=300, batch=2048, lr=0.02, device=dev)
-        tau = S.calibrate_threshold_cp(X, Y, cal_step)
+        tau = S.calibrate_threshold_cp(X, Y, cal_step, cal_after)
         log(f"trained on {len(X)} samples, tau = {tau:.3f}; evaluation workload (seed {args.seed})")
         evalw = gen(seed=args.seed, steps=ev_steps)
         res = S.evaluate(evalw, ev_steps, torch.from_numpy(wts).to(dev), tau, dev)
@@ -432,13 +432,13 @@ def grid_report(args):
 
 
 
-HEADLINE_FORMS = (
-    {"mode": "step", "graph": False},
-    {"mode": "step", "graph": True},
-    *({"mode": "step", "graph": g, "waves": nw} for nw in (2, 4) for g in (False, True)),
-    *({"mode": "persistent", "graph": False, "per_cu": pc} for pc in (2, 4, 8)),
-    {"mode": "fused", "graph": False},
-)
+def headline_forms():
+    from paper_2308_06484_amd import autotune as A
+    return (
+        *A.PER_STEP_CANDIDATES,
+        *({"mode": "persistent", "graph": False, "per_cu": pc} for pc in (2, 4, 8)),
+        {"mode": "fused", "graph": False},
+    )
 CAL_STEPS = 6
 
 
@@ -448,6 +448,12 @@ def form_name(f):
         n += f"_{f['per_cu']}wg"
     if f.get("waves", 1) > 1:
         n += f"_{f['waves']}waves"
+    if f.get("order"):
+        n += "_ordered"
+    if f.get("cut"):
+        n += f"_cut{f['cut']}"
+    if f.get("prefetch") == 0:
+        n += "_noprefetch"
     if f.get("repair"):
         n += "_" + f["repair"]
     return n + ("_graph" if f.get("graph") else "")
@@ -460,6 +466,7 @@ def timed_run(w, mv, off_warm, off_timed, form, policy, dev, period=0):
     milliseconds and the counters before and after."""
     import torch
 
+    from paper_2308_06484_amd import autotune as A
     from paper_2308_06484_amd import selector as S
     from paper_2308_06484_amd.kdt import KineticDT
     stream = torch.cuda.Stream(device=dev)
@@ -467,12 +474,7 @@ def timed_run(w, mv, off_warm, off_timed, form, policy, dev, period=0):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev, stream=stream)
         dt.dcalc(S.DCALC_N)  # d of the initial positions: the selector's feature 15, the d-limit rule
         dt.set_policy(*policy)
-        if form.get("per_cu"):
-            dt.set_launch(form["per_cu"])
-        if form.get("waves", 1) > 1:
-            dt.set_block_waves(form["waves"])
-        if form.get("repair"):
-            dt.set_repair(form["repair"])
+        A.apply_form(dt, form)
         if off_warm is not None and off_warm.shape[0]:
             dt.run(mv, off_warm, mode=form["mode"])
         dt.sync()
@@ -508,22 +510,26 @@ def headline(args):
     # another seed (forced-repair and forced-rebuild runs give both costs)
     t0 = time.perf_counter()
     cal = W.multi2048(seed=100 + args.seed, steps=CAL_STEPS)
-    X, Y, cal_step = S.collect_steps(cal, CAL_STEPS, dev)
+    X, Y, cal_step, cal_after = S.collect_steps(cal, CAL_STEPS, dev)
     mlp = torch.from_numpy(S.train(X, Y, epochs=200, batch=2048, lr=0.02, device=dev)).to(dev)
-    tau = S.calibrate_threshold_cp(X, Y, cal_step)  # on the step's critical path
+    tau = S.calibrate_threshold_cp(X, Y, cal_step, cal_after)  # on the step's critical path
     tau_sum = S.calibrate_threshold(X, Y)           # on summed block costs, for comparison
     log(f"selector trained on {len(X)} block-steps of seed {100 + args.seed} "
         f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.2f} on the critical path, "
         f"{tau_sum:.2f} on summed costs")
     pol_mlp = ("mlp", 0.0, mlp)
-    if args.form:  # a fixed launch form (profiling runs)
-        form = {"step": {"mode": "step", "graph": False}, "step_graph": {"mode": "step", "graph": True},
-                "fused": {"mode": "fused", "graph": False}}[args.form]
+    if args.form:  # a fixed launch form (profiling runs): a candidate's name
+        forms = {form_name(f): f for f in headline_forms()}
+        forms.update(step={"mode": "step", "graph": False}, step_graph={"mode": "step", "graph": True},
+                     fused={"mode": "fused", "graph": False})
+        if args.form not in forms:
+            sys.exit(f"--form: one of {', '.join(sorted(forms))}")
+        form = forms[args.form]
         autotune_table = None
     else:
-        best = A.autotune(cal, steps=CAL_STEPS, candidates=HEADLINE_FORMS, device=dev, use_cache=False,
+        best = A.autotune(cal, steps=CAL_STEPS, candidates=headline_forms(), device=dev, use_cache=False,
                           policy=pol_mlp)
-        form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves") if k in best}
+        form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves", "order", "cut", "prefetch") if k in best}
         autotune_table = {form_name(r): r["s_per_step"] * 1e3 for r in best["table"]}
         log("autotuner (calibration workload, MLP policy): " + ", ".join(
             f"{form_name(r)} {r['s_per_step'] * 1e3:.3f} ms" for r in best["table"]) + f" -> {form_name(form)}")
@@ -548,7 +554,7 @@ def headline(args):
 
     variants = {}
     if not args.no_variants:
-        runs = [(form_name(f) + "_mlp", f, pol_mlp, K) for f in HEADLINE_FORMS if f != form]
+        runs = [(form_name(f) + "_mlp", f, pol_mlp, K) for f in headline_forms() if f != form]
         runs += [(form_name(form) + "_repair_only", form, ("repair", 0.0, None), K),
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
@@ -677,8 +683,10 @@ def main():
                     choices=["multi2048", "grid1024", "lattice256", "uneven4096", "selector_mix", "global4m"],
                     help="multi2048 is the measured configuration; the others print a secondary report")
     ap.add_argument("--other-steps", type=int, default=0, help="steps for the secondary reports")
-    ap.add_argument("--form", choices=["step", "step_graph", "fused"], default=None,
-                    help="headline: this launch form instead of the autotuner's pick (profiling)")
+    ap.add_argument("--form", default=None,
+                    help="headline: this launch form (step, step_graph, fused or an autotuner "
+                         "candidate's name such as per_step_2waves_ordered_graph) instead of the "
+                         "autotuner's pick (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -224,6 +224,14 @@ int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
 #define KDT_REPAIR_FLIP 1
 int kdt_set_repair(kdt_ctx* ctx, int32_t variant);
 
+/* Star prefetch (on by default; a tuning knob, not a semantic one): before
+ * a block's moves of a step run one after another, its wavefront walks the
+ * stars of all the step's movers at once, reading and dropping the records
+ * (and the triangles beyond each star's link, the positions and the move
+ * records), so that the moves find them in cache.  Same results either way.
+ * KDT_E_ARG for a value other than 0 or 1. */
+int kdt_set_prefetch(kdt_ctx* ctx, int32_t on);
+
 /* Wavefronts per block of the per-step launch (KDT_RUN_PER_STEP): 1
  * (default: one wavefront applies the block's moves one after another), 2
  * or 4.  With more than one, the wavefronts of a block's workgroup share
@@ -241,6 +249,20 @@ int kdt_set_repair(kdt_ctx* ctx, int32_t variant);
  * block, the rounds' ticks; the rest launch logs blocks all of whose moves
  * it ran.  KDT_E_ARG for another count, KDT_E_STATE in global mode. */
 int kdt_set_block_waves(kdt_ctx* ctx, int32_t waves);
+
+/* Schedule of the per-step launch (KDT_RUN_PER_STEP; tuning only, the
+ * results are the same).  order = 1: every step, a small kernel sorts the
+ * blocks by their number of moves in the step, most first, and the step's
+ * workgroups take them in that order, so that the blocks that set the
+ * step's length start first (a step lasts as long as its slowest block).
+ * heavy_cut > 0 (needs order = 1, and matters with kdt_set_block_waves
+ * above 1): size classes -- only the blocks with at least heavy_cut moves
+ * in the step get the several-wavefront workgroups, on a second stream of
+ * the context, while the one-wavefront kernel takes the others at the same
+ * time on the context's stream; the rest launch follows both.  Default
+ * order 0, heavy_cut 0.  KDT_E_ARG for order outside {0, 1}, a negative
+ * heavy_cut or heavy_cut > 0 with order 0; KDT_E_STATE in global mode. */
+int kdt_set_block_order(kdt_ctx* ctx, int32_t order, int32_t heavy_cut);
 
 /* The same n_steps steps captured once as a HIP graph and replayed by
  * kdt_graph_launch (each replay applies the same move stream again, from the
@@ -381,7 +403,10 @@ int kdt_set_policy(kdt_ctx* ctx, int32_t policy, float tau, const float* mlp_w);
  * log2(1+k)/log2 n, max d / d of the latest kdt_dcalc (0 if none)), 16 branch taken (0 repair, 1 rebuild, 2 repair that
  * hit the repair path's capacity and finished the step by rebuilding: no
  * clean cost of either branch), 17 device clock ticks the branch took,
- * 18 k.  Steps without moves are not logged. */
+ * 18 k, 19 1 if the block's rebuild would run after the step's kernel (the
+ * launch forms that defer, and a build that does not fit the step kernel's
+ * LDS), else 0.  Steps without moves
+ * are not logged. */
 #define KDT_LOG_FIELDS 20
 int kdt_set_log(kdt_ctx* ctx, float* log, int64_t cap_steps);
 

@@ -2,9 +2,12 @@
 
 Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
 one kernel per step with 1, 2 or 4 wavefronts per block (the workgroup
-size), the persistent launch with 1..8 workgroups per
-compute unit (the LDS of an MI355X compute unit holds 5), each either launched step by step or captured as a HIP graph,
-and the fused multi-step launch.  Every candidate computes the same
+size), the blocks taken in index order or most moves first, size classes
+(only the blocks with at least `cut` moves get several wavefronts, the
+others one, at once on two streams), the star prefetch on or off, the
+persistent launch with 1..8 workgroups per compute unit (the LDS of an
+MI355X compute unit holds 5), each either launched step by step or
+captured as a HIP graph, and the fused multi-step launch.  Every candidate computes the same
 triangulations (tests check this bit for bit), so the choice only changes
 speed.  Each candidate is timed on its own fresh context built from a
 calibration workload (a different seed from the measured one), the fastest
@@ -21,13 +24,34 @@ import torch
 
 from .kdt import KineticDT
 
+PER_STEP_CANDIDATES = (
+    *({"mode": "step", "graph": g, "order": o} for o in (0, 1) for g in (False, True)),
+    *({"mode": "step", "graph": g, "waves": 2, "order": 1} for g in (False, True)),
+    *({"mode": "step", "graph": True, "waves": nw, "order": 0} for nw in (2, 4)),
+    {"mode": "step", "graph": True, "waves": 4, "order": 1},
+    {"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": 24},
+    {"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": 32},
+    {"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": 0},
+)
 DEFAULT_CANDIDATES = (
-    {"mode": "step", "graph": False},
-    {"mode": "step", "graph": True},
-    *({"mode": "step", "graph": g, "waves": nw} for nw in (2, 4) for g in (False, True)),
+    *PER_STEP_CANDIDATES,
     *({"mode": "persistent", "graph": g, "per_cu": pc} for pc in (1, 2, 4, 5, 8) for g in (False, True)),
     {"mode": "fused", "graph": False},
 )
+
+
+def apply_form(dt, form):
+    """Set a context's launch shape from a candidate's keys."""
+    if form.get("per_cu"):
+        dt.set_launch(form["per_cu"])
+    if form.get("waves", 1) > 1:
+        dt.set_block_waves(form["waves"])
+    if form.get("order") or form.get("cut"):
+        dt.set_block_order(form.get("order", 0), form.get("cut", 0))
+    if "prefetch" in form:
+        dt.set_prefetch(form["prefetch"])
+    if form.get("repair"):
+        dt.set_repair(form["repair"])
 
 
 def cache_path():
@@ -52,10 +76,7 @@ def time_candidate(w, cand, steps, device="cuda:0", policy=None):
             from .selector import DCALC_N
             dt.dcalc(DCALC_N)  # as in the runs the selector was trained on
             dt.set_policy(*policy)
-        if cand.get("per_cu"):
-            dt.set_launch(cand["per_cu"])
-        if cand.get("waves", 1) > 1:
-            dt.set_block_waves(cand["waves"])
+        apply_form(dt, cand)
         mv = torch.from_numpy(w["mv"]).to(device)
         off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:steps])).to(device)
         g = dt.graph(mv, off, mode=cand["mode"]) if cand["graph"] else None

@@ -60,6 +60,8 @@ struct DevState {
     float dlim;          // d of the latest d-calculation (0: none yet): feature 15, the d-limit rule
     int n_blocks;
     int repair;    // repair variant: KDT_REPAIR_*
+    int prefetch;  // 1: warm the caches with the movers' stars before a block's moves
+    int pad_;
     BlockStats* stats;
     float* log;  // per step and block: LOG_FIELDS floats, or null
 };
@@ -166,6 +168,7 @@ __global__ void __launch_bounds__(PB_THREADS) k_build_blocks(DevState s, int lds
 __global__ void __launch_bounds__(PB_THREADS) k_build_listed(DevState s, long long step, int lds_bytes) {
     extern __shared__ __align__(16) char dyn[];
     const int cnt = s.rb_list[0];
+    if (cnt == 0) return;  // nothing listed: nothing to empty either
     for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
         build_block(s, s.rb_list[2 + i], true, step, lds_bytes, dyn);
         __syncthreads();
@@ -641,6 +644,54 @@ __device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t*
     f[13] = log2f(sp); f[14] = lk / ln; f[15] = dlim > 0.f ? mx * sp / dlim : 0.f;
 }
 
+// Warms the caches with what the block's moves of the step read first: lane
+// i walks the star of mover i as the step starts (both ways round at once,
+// one pair of records per round trip) and touches the triangle beyond each
+// link edge, the mover's position and its move record; the values are
+// dropped.  The moves, one after another, then find most of their records
+// in cache instead of memory: every record a move reads through its star is
+// one it would otherwise wait a full memory round trip for.  Read only, with
+// every index checked against the block, so a stale or corrupt record only
+// ends the lane's walk.
+__device__ __forceinline__ void prefetch_stars(const BlockView& B, const kdt_move_t* __restrict__ mv, int m0,
+                                               int m1) {
+    const int lane = lane_id();
+    int acc = 0;
+    const int m = m0 + lane;
+    const int p = m < m1 ? mv[m].point : -1;
+    if ((unsigned)p < (unsigned)B.n) {
+        const int t0 = B.vtri[p];
+        acc ^= B.xy[p].x;
+        if (!bad_slot(B, t0)) {
+            const int4 v0 = B.tri[t0].v, n0 = B.tri[t0].n;
+            const int pi = v0.x == p ? 0 : (v0.y == p ? 1 : (v0.z == p ? 2 : -1));
+            if (pi >= 0) {
+                int ccw = vget(n0, (pi + 1) % 3), cw = vget(n0, (pi + 2) % 3);
+                int ring = vget(n0, pi) >> 2;
+                int last_ccw = t0, last_cw = t0;
+                for (int it = 0; it < KMAX / 2; ++it) {
+                    const int cs = ccw >> 2, ws = cw >> 2;
+                    if (cs == last_cw || bad_slot(B, cs) || bad_slot(B, ws) || bad_slot(B, ring)) break;
+                    const int4 vc = B.tri[cs].v, nc = B.tri[cs].n, vw = B.tri[ws].v, nw = B.tri[ws].n;
+                    acc ^= B.tri[ring].v.x;  // the previous round's ring record, in flight with these
+                    const int pc = ((ccw & 3) + 1) % 3, pw = ((cw & 3) + 2) % 3;
+                    if (vget(vc, pc) != p || vget(vw, pw) != p) break;
+                    ring = vget(nc, pc) >> 2;
+                    const int ring_w = vget(nw, pw) >> 2;
+                    if (ws == cs) break;
+                    if (!bad_slot(B, ring_w)) acc ^= B.tri[ring_w].v.x;
+                    last_ccw = cs;
+                    last_cw = ws;
+                    ccw = vget(nc, (pc + 1) % 3);
+                    cw = vget(nw, (pw + 2) % 3);
+                    if ((cw >> 2) == last_ccw) break;
+                }
+            }
+        }
+    }
+    asm volatile("" ::"v"(acc));
+}
+
 __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, int b, const kdt_move_t* mv,
                                 const BlockHead& h, int8_t* applied, long long step, bool defer, char* dynx) {
     BlockView B;
@@ -669,6 +720,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     const long long c0 = wall_clock64();
     int rc = ST_OK;
     if (branch == 0) {
+        if (k > 1 && s.prefetch) prefetch_stars(B, mv, m0, m1);
         for (int m = m0; m < m1; ++m) {
             int app = 0;
             if (m > m0) gsync();  // the previous move's stores are visible
@@ -709,6 +761,8 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
             v = (float)(c1 - c0);
         } else if (lane == 18) {
             v = (float)k;
+        } else if (lane == 19) {
+            v = defer && pb_block_lds(B.n) > (size_t)s.step_lds ? 1.f : 0.f;
         }
         rec[lane] = v;
     }
@@ -720,11 +774,66 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     return rc;
 }
 
+// The blocks of a step by their number of moves, most first (a counting
+// sort; blocks with equal counts in any order, which changes nothing: the
+// blocks are independent), for the per-step launches: the blocks that set
+// the step's length start first instead of wherever their index puts them.
+// order[B] = the number of blocks with at least `cut` moves (the heavy
+// class of the split launch: the first order[B] entries).
+constexpr int ORD_BUCKETS = DRYMAX + 2;  // k = 0 .. DRYMAX, and more
+__global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int B, int cut, int* order) {
+    __shared__ int cnt[ORD_BUCKETS];
+    __shared__ int base[ORD_BUCKETS];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < ORD_BUCKETS; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    for (int b = tid; b < B; b += blockDim.x) {
+        const int k = min(max(off[b + 1] - off[b], 0), DRYMAX + 1);
+        atomicAdd(&cnt[DRYMAX + 1 - k], 1);
+    }
+    __syncthreads();
+    if (tid < WAVE) {  // exclusive prefix over the buckets, one wavefront
+        int run = 0;
+        for (int c0 = 0; c0 < ORD_BUCKETS; c0 += WAVE) {
+            const int i = c0 + tid;
+            const int v = i < ORD_BUCKETS ? cnt[i] : 0;
+            int x = v;
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const int y = __shfl_up(x, d);
+                if (tid >= d) x += y;
+            }
+            if (i < ORD_BUCKETS) base[i] = run + x - v;
+            run += __shfl(x, WAVE - 1);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) order[B] = cut <= 0 ? B : (cut > DRYMAX + 1 ? 0 : base[DRYMAX + 2 - cut]);
+    __syncthreads();
+    for (int b = tid; b < B; b += blockDim.x) {
+        const int k = min(max(off[b + 1] - off[b], 0), DRYMAX + 1);
+        order[atomicAdd(&base[DRYMAX + 1 - k], 1)] = b;
+    }
+}
+
+// The block a per-step workgroup takes: its index (no order), or its rank
+// in the step's order over all blocks (part 0), over the heavy class (part
+// 1: the first order[B] ranks) or over the rest (part 2); -1: none.
+constexpr int PART_ALL = 0, PART_HEAVY = 1, PART_LIGHT = 2;
+__device__ __forceinline__ int pick_block(int B, const int* __restrict__ order, int part) {
+    const int g = blockIdx.x;
+    if (!order) return g < B ? g : -1;
+    const int r = part == PART_LIGHT ? order[B] + g : g;
+    if (r >= (part == PART_HEAVY ? order[B] : B)) return -1;
+    return order[r];
+}
+
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
-                                               const int* __restrict__ off, int8_t* applied, long long step) {
+                                               const int* __restrict__ off, int8_t* applied, long long step,
+                                               const int* __restrict__ order = nullptr, int part = PART_ALL) {
     __shared__ WaveLDS S;
     extern __shared__ __align__(16) char dynx[];
-    const int b = blockIdx.x;
+    const int b = pick_block(s.n_blocks, order, part);
+    if (b < 0) return;
     const BlockHead h = load_head(s, b, off);
     if (head_skip(h)) return;
     scratch_init(S);
@@ -1427,13 +1536,17 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
 // round.  The lowest pending move always wins.  Every other move (moves that
 // share a cell with another, a plan beyond the plan or table capacities,
 // every move of a block that takes the rebuild branch or has more moves than
-// DRYMAX) goes, in list order, to the block's rest list, which k_step_rest
+// MW_KMAX) goes, in list order, to the block's rest list, which k_step_rest
 // applies after the rounds one after another (the sequential path).  The
 // commuting moves commute with them too, so the result is the sequential
 // rule's, and DT* (unique) is the same triangulation.
 constexpr int MW_MAX_WAVES = 4;
-constexpr int MW_HASH = 2048;  // claim hash entries: holds every slot of MW_MAX_WAVES plans
-static_assert(MW_HASH >= MW_MAX_WAVES * RSMAX, "claim hash smaller than the plans of one round");
+// claim hash entries: every slot of one round's NW plans (a power of two)
+template <int NW>
+constexpr int mw_hash() { return NW * RSMAX <= 1024 ? 1024 : 2048; }
+static_assert(mw_hash<MW_MAX_WAVES>() >= MW_MAX_WAVES * RSMAX && mw_hash<2>() >= 2 * RSMAX,
+              "claim hash smaller than the plans of one round");
+constexpr int MW_KMAX = 128;  // moves of a block's step the rounds take; a block with more runs in the rest launch
 constexpr int MWS_PEND = 0, MWS_DONE = 1, MWS_REST = 2;
 constexpr int REST_ALL = -1;  // rest count of a block deferred whole
 
@@ -1449,19 +1562,23 @@ struct RestBuf {
 template <int NW>
 struct MwLDS {
     WaveLDS S[NW];
-    BlockStats pst[NW];        // the counters of each wavefront's current plan
-    int hkey[MW_HASH];         // slot, or -1
-    int hprio[MW_HASH];        // lowest move index claiming it
-    int mstate[DRYMAX];        // MWS_* per move of the step (offset from m0)
-    int list[DRYMAX];          // pending commuting moves, list order
-    int2 cs[DRYMAX], ct[DRYMAX];  // source and target cells (ct.x < 0: target outside the frame)
-    int pt[DRYMAX];            // moved point
+    BlockStats pst[NW];          // the counters of each wavefront's current plan
+    int hkey[mw_hash<NW>()];     // slot, or -1
+    int hprio[mw_hash<NW>()];    // lowest move index claiming it
+    int mstate[MW_KMAX];         // MWS_* per move of the step (offset from m0)
+    int list[MW_KMAX];           // pending commuting moves, list order
+    int2 cs[MW_KMAX], ct[MW_KMAX];  // source and target cells (ct.x < 0: target outside the frame)
+    int pt[MW_KMAX];             // moved point
     int outcome[NW];
     int np, defer_all, fail, nrest;
     float f[MLP_IN];
 };
 
-__device__ __forceinline__ int mw_home(int slot) { return (int)(((unsigned)slot * 0x9E3779B1u) >> 21); }
+template <int H>
+__device__ __forceinline__ int mw_home(int slot) {
+    static_assert(H == 1024 || H == 2048, "claim hash size");
+    return (int)(((unsigned)slot * 0x9E3779B1u) >> (H == 1024 ? 22 : 21));
+}
 
 // Slot i of a plan's read set: the star, then the table's entries, then the
 // walk's path.
@@ -1470,14 +1587,19 @@ __device__ __forceinline__ int mw_read_slot(const WaveLDS& S, const MovePlan& pl
 }
 
 static_assert(sizeof(MwLDS<4>) <= 160 * 1024, "four wavefronts' scratch exceeds a compute unit's LDS");
+static_assert(sizeof(MwLDS<2>) <= 80 * 1024, "two two-wavefront workgroups no longer share a compute unit");
 
 template <int NW>
 __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_move_t* __restrict__ mv,
                                                        const int* __restrict__ off, int8_t* applied,
-                                                       long long step, RestBuf rb) {
+                                                       long long step, RestBuf rb,
+                                                       const int* __restrict__ order = nullptr,
+                                                       int part = PART_ALL) {
     extern __shared__ __align__(16) char dyn[];
     MwLDS<NW>& M = *reinterpret_cast<MwLDS<NW>*>(dyn);
-    const int b = blockIdx.x;
+    constexpr int HS = mw_hash<NW>();
+    const int b = pick_block(s.n_blocks, order, part);
+    if (b < 0) return;  // uniform over the workgroup
     const int tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     constexpr int NT = NW * WAVE;
     const BlockHead h = load_head(s, b, off);
@@ -1495,10 +1617,10 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     table_clear(S);
     if (lane < NF) reinterpret_cast<long long*>(&S.st)[lane] = 0;
     if (tid == 0) {
-        M.defer_all = k > DRYMAX ? 1 : 0;
+        M.defer_all = k > MW_KMAX ? 1 : 0;
         M.fail = ST_OK;
     }
-    for (int i = tid; i < MW_HASH; i += NT) {
+    for (int i = tid; i < HS; i += NT) {
         M.hkey[i] = -1;
         M.hprio[i] = 0x7fffffff;
     }
@@ -1555,6 +1677,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
             M.np = np;
         }
     }
+    if (!M.defer_all && k > 1 && s.prefetch) prefetch_stars(B, mv, m0 + w * WAVE, h.m1);
     __syncthreads();
     // reservation rounds over the commuting moves
     while (!M.defer_all && M.np > 0 && M.fail == ST_OK) {
@@ -1573,14 +1696,14 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
                 } else {
                     for (int e = lane; e < total; e += WAVE) {
                         const int slot = mw_read_slot(S, pl, e);
-                        int hh = mw_home(slot);
-                        for (int t = 0; t < MW_HASH; ++t) {
+                        int hh = mw_home<HS>(slot);
+                        for (int t = 0; t < HS; ++t) {
                             const int old = atomicCAS(&M.hkey[hh], -1, slot);
                             if (old == -1 || old == slot) {
                                 atomicMin(&M.hprio[hh], i);
                                 break;
                             }
-                            hh = (hh + 1) & (MW_HASH - 1);
+                            hh = (hh + 1) & (HS - 1);
                         }
                     }
                 }
@@ -1599,15 +1722,15 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
                 bool held = true;
                 for (int e = lane; e < total; e += WAVE) {
                     const int slot = mw_read_slot(S, pl, e);
-                    int hh = mw_home(slot);
-                    for (int t = 0; t < MW_HASH && M.hkey[hh] != slot; ++t) hh = (hh + 1) & (MW_HASH - 1);
+                    int hh = mw_home<HS>(slot);
+                    for (int t = 0; t < HS && M.hkey[hh] != slot; ++t) hh = (hh + 1) & (HS - 1);
                     held &= M.hprio[hh] == i;
                 }
                 outc = ballot(!held) ? 2 : 1;
             }
         }
         __syncthreads();  // every wavefront has read the claims
-        for (int e = tid; e < MW_HASH; e += NT) {
+        for (int e = tid; e < HS; e += NT) {
             M.hkey[e] = -1;
             M.hprio[e] = 0x7fffffff;
         }
@@ -2139,8 +2262,8 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
-        qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, rest_mv, rest_idx, rest_app, rest_cnt,
-        dc_mind2, dc_diam2, dc_g, total;
+        qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, sorder, rest_mv, rest_idx, rest_app,
+        rest_cnt, dc_mind2, dc_diam2, dc_g, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -2170,6 +2293,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_app = take((size_t)std::max(max_staged, 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
+    L.sorder = take(sizeof(int) * (B + 1));
     L.rest_mv = take(sizeof(kdt_move_t) * (size_t)B * DRYMAX);
     L.rest_idx = take(sizeof(int) * (size_t)B * DRYMAX);
     L.rest_app = take((size_t)B * DRYMAX);
@@ -2355,6 +2479,10 @@ struct kdt_ctx {
     long long epoch = 0;       // changes of policy, log or launch shape (graphs record theirs)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
     int block_waves = 1;     // wavefronts per block of the per-step launch (1, 2 or 4)
+    int block_order = 0;     // 1: the per-step launch takes blocks most moves first
+    int heavy_cut = 0;       // > 0 (with block_waves > 1): only blocks of this many moves get several wavefronts
+    hipStream_t side = nullptr;                          // second stream of the split launch
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;     // its fork and join
     RestBuf rest{};          // rest lists of the multi-wavefront launch
     // d-calculation over time (kdt_dcalc): running minimum of the squared
     // mindistance, every block's running maximum N-spread, for one N
@@ -2852,6 +2980,7 @@ int kdt_init(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t n_blocks,
     c->dev.policy = KDT_POLICY_REPAIR;
     c->dev.tau = 0.f;
     c->dev.dlim = 0.f;
+    c->dev.prefetch = 1;
     c->dev.mlp_w = nullptr;
     c->dev.log = nullptr;
     c->dev.log_cap = 0;
@@ -3036,17 +3165,37 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
         if (flags == KDT_RUN_PERSISTENT) {
             k_step_persist<<<grid, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
                                                                        c->B, applied, c->step_count);
-        } else if (c->block_waves > 1) {
-            if (c->block_waves == 4)
-                k_step_mw<4><<<c->B, 4 * WAVE, sizeof(MwLDS<4>), c->stream>>>(c->dev, moves, off, applied,
-                                                                             c->step_count, c->rest);
-            else
-                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), c->stream>>>(c->dev, moves, off, applied,
-                                                                             c->step_count, c->rest);
-            k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, c->rest, applied,
-                                                                    c->step_count);
         } else {
-            k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count);
+            // the step's order (most moves first) and, for the split launch,
+            // its heavy class: the blocks with at least heavy_cut moves
+            int* ord = nullptr;
+            const bool split = c->block_waves > 1 && c->heavy_cut > 0;
+            if (c->block_order || split) {
+                ord = (int*)(w + c->L.sorder);
+                k_order<<<1, 1024, 0, c->stream>>>(off, c->B, split ? c->heavy_cut : DRYMAX + 2, ord);
+            }
+            hipStream_t mws = c->stream;
+            if (split) {  // heavy blocks on the side stream, at the same time as the others
+                if (check_hip(c, hipEventRecord(c->fork_ev, c->stream)) ||
+                    check_hip(c, hipStreamWaitEvent(c->side, c->fork_ev, 0)))
+                    return KDT_E_DEVICE;
+                mws = c->side;
+            }
+            if (c->block_waves == 4)
+                k_step_mw<4><<<c->B, 4 * WAVE, sizeof(MwLDS<4>), mws>>>(
+                    c->dev, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
+            else if (c->block_waves == 2)
+                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), mws>>>(
+                    c->dev, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
+            if (c->block_waves == 1 || split)
+                k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count, ord,
+                                                                   split ? PART_LIGHT : PART_ALL);
+            if (split && (check_hip(c, hipEventRecord(c->join_ev, c->side)) ||
+                          check_hip(c, hipStreamWaitEvent(c->stream, c->join_ev, 0))))
+                return KDT_E_DEVICE;
+            if (c->block_waves > 1)
+                k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, c->rest, applied,
+                                                                        c->step_count);
         }
         if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch listed
             k_build_listed<<<std::min(c->B, 8 * c->cus), PB_THREADS, c->pb_lds_follow, c->stream>>>(
@@ -3090,6 +3239,28 @@ int kdt_set_repair(kdt_ctx* c, int32_t variant) {
     if (!c || (variant != KDT_REPAIR_DELINS && variant != KDT_REPAIR_FLIP)) return KDT_E_ARG;
     if (c->global) return KDT_E_STATE;
     c->dev.repair = variant;
+    c->epoch++;
+    return KDT_OK;
+}
+
+int kdt_set_prefetch(kdt_ctx* c, int32_t on) {
+    if (!c || (on != 0 && on != 1)) return KDT_E_ARG;
+    c->dev.prefetch = on;
+    c->epoch++;
+    return KDT_OK;
+}
+
+int kdt_set_block_order(kdt_ctx* c, int32_t order, int32_t heavy_cut) {
+    if (!c || (order != 0 && order != 1) || heavy_cut < 0 || (heavy_cut > 0 && !order)) return KDT_E_ARG;
+    if (c->global) return KDT_E_STATE;
+    if (heavy_cut > 0 && !c->side) {
+        if (check_hip(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) ||
+            check_hip(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) ||
+            check_hip(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)))
+            return KDT_E_DEVICE;
+    }
+    c->block_order = order;
+    c->heavy_cut = heavy_cut;
     c->epoch++;
     return KDT_OK;
 }
@@ -3845,6 +4016,12 @@ void kdt_destroy(kdt_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     release_events(c);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     delete c;
 }
 

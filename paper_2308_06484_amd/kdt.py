@@ -30,7 +30,7 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair",
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair", "kdt_set_prefetch", "kdt_set_block_order",
            "kdt_workspace_size_global_qt", "kdt_init_global_qt", "kdt_quadtree", "kdt_repartition",
            "kdt_set_repartition")
 REPAIR = {"delins": 0, "flip": 1}
@@ -326,6 +326,16 @@ class KineticDT:
     def set_repair(self, variant):
         """Repair variant: "delins" (delete + insert) or "flip" (move-and-flip)."""
         _check(_lib().kdt_set_repair(self.ctx, REPAIR[variant]), "kdt_set_repair")
+
+    def set_prefetch(self, on):
+        """Star prefetch before a block's moves (on by default; same results)."""
+        _check(_lib().kdt_set_prefetch(self.ctx, 1 if on else 0), "kdt_set_prefetch")
+
+    def set_block_order(self, order, heavy_cut=0):
+        """Per-step launch schedule: blocks most moves first (order=1) and,
+        with several wavefronts per block, size classes split at heavy_cut
+        moves (run at once on two streams)."""
+        _check(_lib().kdt_set_block_order(self.ctx, int(order), int(heavy_cut)), "kdt_set_block_order")
 
     def set_block_waves(self, waves):
         """Wavefronts per block of the per-step launch (1, 2 or 4)."""

@@ -9,7 +9,8 @@ fallback.  Every block of a step runs at once, so a step lasts as long as
 its slowest block: choosing the cheaper branch for every block also
 minimises each step's slowest block, so the network predicts per-block
 costs, while the threshold is calibrated and the choices are judged on
-that critical path (the sum over steps of the slowest block's cost).  Features, costs and branch choices are produced by the library's
+that critical path (the sum over steps of the slowest block's cost, plus the
+slowest rebuild too large for the step's kernel, which runs after it).  Features, costs and branch choices are produced by the library's
 kernels (the per-step log), and the network is trained by the library's own
 forward/backward/SGD kernels; this module only arranges the runs, the
 feature normalisation (folded into the first layer afterwards) and the
@@ -22,7 +23,7 @@ import time
 import numpy as np
 import torch
 
-from .kdt import LOG_FIELDS, MLP_PARAMS, KineticDT, mlp_train
+from .kdt import LOG_FIELDS, MLP_NOALLOC_BATCH, MLP_PARAMS, KineticDT, mlp_train, mlp_train_noalloc
 
 H, IN = 32, 16
 
@@ -55,8 +56,8 @@ def run_policy(w, steps, policy, device="cuda:0", tau=0.0, mlp_w=None, log=True)
 def collect_steps(w, steps, device="cuda:0"):
     """Training samples: features and the log2 cost of both branches for
     every (step, block) with moves, from a forced-repair and a forced-rebuild
-    run of the same workload (identical states: DT* is unique), and the step
-    of each sample."""
+    run of the same workload (identical states: DT* is unique), the step of
+    each sample, and whether its rebuild would run after the step's kernel."""
     lr_, _, _ = run_policy(w, steps, "repair", device)
     lb_, _, _ = run_policy(w, steps, "rebuild", device)
     # block-steps with moves; a repair that hit the repair path's capacity
@@ -66,11 +67,12 @@ def collect_steps(w, steps, device="cuda:0"):
     Y = np.stack([np.log2(np.maximum(lr_[..., 17][valid], 1.0)),
                   np.log2(np.maximum(lb_[..., 17][valid], 1.0))], axis=1).astype(np.float32)
     step = np.nonzero(valid)[0]
-    return X, Y, step
+    after = lb_[..., 19][valid] > 0.5
+    return X, Y, step, after
 
 
 def collect(w, steps, device="cuda:0"):
-    X, Y, _ = collect_steps(w, steps, device)
+    X, Y, _, _ = collect_steps(w, steps, device)
     return X, Y
 
 
@@ -112,33 +114,44 @@ def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0"):
     wt = torch.from_numpy(w0).to(device)
     xt = torch.from_numpy(Xn).to(device)
     yt = torch.from_numpy(Yc).to(device)
-    mlp_train(wt, xt, yt, epochs, batch, lr)
+    # the same floats either way; the no-alloc path spreads a batch over
+    # one workgroup per 64 samples
+    (mlp_train_noalloc if batch <= MLP_NOALLOC_BATCH else mlp_train)(wt, xt, yt, epochs, batch, lr)
     torch.cuda.synchronize()
     w = wt.cpu().numpy()
     w[-2:] += ym.astype(np.float32)  # output bias back to the label scale
     return fold_normalisation(w, mu, sd)
 
 
-def step_time(cost, step):
-    """A step lasts as long as its slowest block (every block of a step
-    runs at once): the sum over steps of the largest cost."""
-    out = np.zeros(int(step.max()) + 1 if len(step) else 0)
-    np.maximum.at(out, step, cost)
-    return float(out.sum())
+def step_time(cost, step, after=None):
+    """The blocks of a step run at once, so the step's kernel lasts as long
+    as its slowest block; rebuilds too large for that kernel run after it
+    (at once too): the sum over steps of the slowest block's cost in the
+    kernel plus the slowest of those after it.  after: bool per sample, or
+    None (all in the kernel)."""
+    n = int(step.max()) + 1 if len(step) else 0
+    during, later = np.zeros(n), np.zeros(n)
+    late = np.zeros(len(cost), dtype=bool) if after is None else np.asarray(after, dtype=bool)
+    np.maximum.at(during, step[~late], cost[~late])
+    np.maximum.at(later, step[late], cost[late])
+    return float(during.sum() + later.sum())
 
 
-def calibrate_threshold_cp(X, Y, step, candidates=256):
-    """tau for "rebuild iff sum d/s > tau" that minimises the step time --
-    the sum over steps of the slowest block's cost, the critical path --
-    on the samples (candidates: quantiles of the observed values, rebuild
-    everything, rebuild nothing).  A choice that makes one block of a step slower costs
-    the whole step; per-block sums would not see it."""
+def calibrate_threshold_cp(X, Y, step, after=None, candidates=256):
+    """tau for "rebuild iff sum d/s > tau" that minimises the step time of
+    step_time -- the critical path -- on the samples (candidates: quantiles
+    of the observed values, rebuild everything, rebuild nothing).  A choice
+    that makes one block of a step slower costs the whole step; per-block
+    sums would not see it.  after: per sample, whether its rebuild would run
+    after the step's kernel (None: none would)."""
     f = X[:, 3].astype(np.float64)
     cr, cb = np.exp2(Y[:, 0].astype(np.float64)), np.exp2(Y[:, 1].astype(np.float64))
+    late = np.zeros(len(f), dtype=bool) if after is None else np.asarray(after, dtype=bool)
     cand = np.unique(np.concatenate([np.quantile(f, np.linspace(0, 1, candidates)), [f.min() - 1.0, f.max() + 1.0]]))
     best_tau, best = float(f.max() + 1.0), np.inf
     for tau in cand:
-        t = step_time(np.where(f > tau, cb, cr), step)
+        rb = f > tau
+        t = step_time(np.where(rb, cb, cr), step, rb & late)
         if t < best:
             best, best_tau = t, float(tau)
     return best_tau
@@ -186,11 +199,16 @@ def evaluate(w, steps, mlp_w, tau, device="cuda:0"):
     valid = logs["repair"][..., 18] > 0
     step = np.nonzero(valid)[0]
     cr, cb = logs["repair"][..., 17], logs["rebuild"][..., 17]
-    best_cp = step_time(np.minimum(cr[valid], cb[valid]).astype(np.float64), step)
+    late = logs["rebuild"][..., 19][valid] > 0.5
+    # the per-block cheaper branch (not exactly the fastest step once
+    # deferred rebuilds add to it, but the reference the regret is taken to)
+    rb_best = cb[valid] < cr[valid]
+    best_cp = step_time(np.minimum(cr[valid], cb[valid]).astype(np.float64), step, rb_best & late)
     for pol in res:
         r, tot, best = regret(logs[pol][..., 16], cr, cb, valid)
-        chosen = np.where(logs[pol][..., 16][valid] == 1, cb[valid], cr[valid]).astype(np.float64)
-        cp = step_time(chosen, step)
+        took = logs[pol][..., 16][valid] == 1
+        chosen = np.where(took, cb[valid], cr[valid]).astype(np.float64)
+        cp = step_time(chosen, step, took & late)
         res[pol].update(regret_ticks=r, chosen_ticks=tot, best_ticks=best,
                         cp_ticks=cp, cp_best_ticks=best_cp, cp_regret_ticks=cp - best_cp,
                         rebuild_fraction=float((logs[pol][..., 16][valid] == 1).mean()))

@@ -1,6 +1,8 @@
-"""Launch forms (one kernel per step, persistent, fused, HIP graph replay)
-and the autotuner: every form gives the same triangulations, bit for bit,
-as the oracle, under the repair and the rebuild policies."""
+"""Launch forms (one kernel per step, persistent, fused, HIP graph replay,
+several wavefronts per block, blocks most moves first, size classes on two
+streams, the star prefetch off) and the autotuner: every form gives the same
+triangulations, bit for bit, as the oracle, under the repair and the rebuild
+policies."""
 import numpy as np
 import pytest
 import torch
@@ -12,13 +14,16 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def _run(w, mode, graph=False, per_cu=None, repeat=1, policy=None):
+def _run(w, mode, graph=False, per_cu=None, repeat=1, policy=None, shape=None):
+    from paper_2308_06484_amd.autotune import apply_form
     from paper_2308_06484_amd.kdt import KineticDT
     stream = torch.cuda.Stream(device=DEV)
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
         if per_cu:
             dt.set_launch(per_cu)
+        if shape:
+            apply_form(dt, shape)
         if policy:
             dt.set_policy(policy)
         mv = torch.from_numpy(w["mv"]).to(DEV)
@@ -59,6 +64,13 @@ def test_launch_forms_bit_identical(uneven):
         assert np.array_equal(got[1], ref[1]), (mode, graph, per_cu)
         assert np.array_equal(got[2], ref[2]), (mode, graph, per_cu)
         assert got[3]["applied"] == ref[3]["applied"] and got[3]["errors"] == 0
+    for graph, shape in [(False, {"order": 1}), (True, {"waves": 2, "order": 1}), (False, {"waves": 4, "order": 1}),
+                         (True, {"waves": 4, "order": 1, "cut": 3}), (False, {"waves": 2, "order": 1, "cut": 2}),
+                         (True, {"order": 1, "prefetch": 0})]:
+        got = _run(w, "step", graph, shape=shape)
+        for i in range(3):
+            assert np.array_equal(got[i], ref[i]), (graph, shape, i)
+        assert got[3]["applied"] == ref[3]["applied"] and got[3]["errors"] == 0
 
 
 def test_graph_replays_apply_the_stream_again(uneven):
@@ -66,6 +78,9 @@ def test_graph_replays_apply_the_stream_again(uneven):
     a = _run(w, "step", repeat=2)
     b = _run(w, "persistent", graph=True, per_cu=2, repeat=2)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # the split launch's fork and join replayed
+    c = _run(w, "step", graph=True, repeat=2, shape={"waves": 2, "order": 1, "cut": 3})
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     oracle = Kinetic(w["xy"], w["pt_off"], w["frame"])
     for _ in range(2):
         for t in range(w["mv_off"].shape[0]):

@@ -26,7 +26,7 @@ def _say(*a):
 
 
 def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label="", waves=1,
-                    repair=None):
+                    repair=None, order=0, cut=0):
     """Run w's first T steps one step per call; after every step compare the
     applied flags and a rotating subset of SUBSET blocks; at the end, all."""
     from paper_2308_06484_amd.kdt import KineticDT
@@ -36,6 +36,8 @@ def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0,
         dt.set_policy(policy, tau, mlp_w)
     if waves > 1:
         dt.set_block_waves(waves)
+    if order or cut:
+        dt.set_block_order(order, cut)
     if repair:
         dt.set_repair(repair)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
@@ -102,6 +104,9 @@ def test_multi2048_full_size_every_step_all_policies():
     w = W.multi2048(seed=1, steps=100)
     rotating_parity(w, 100, label="multi2048 repair")
     rotating_parity(w, 100, policy="mlp", mlp_w=wts, seed=1, label="multi2048 mlp")
+    # the benchmark's launch shape: two wavefronts per block, most moves first
+    rotating_parity(w, 100, policy="mlp", mlp_w=wts, seed=4, waves=2, order=1,
+                    label="multi2048 mlp, 2 waves, ordered")
     st = rotating_parity(w, 100, policy="threshold", tau=tau_lo, seed=2, label="multi2048 threshold")
     assert st["rebuilt"] > 0
     st = rotating_parity(w, 10, policy="rebuild", seed=3, label="multi2048 rebuild")

@@ -190,9 +190,9 @@ def test_learned_selector_gains_on_mixed_blocks():
     its policy runs faster than both."""
     from paper_2308_06484_amd import selector as S
     calib = W.selector_mix(seed=111, steps=4, small=48, large=48)
-    X, Y, step = S.collect_steps(calib, 4)
+    X, Y, step, after = S.collect_steps(calib, 4)
     wts = S.train(X, Y, epochs=200, batch=256, lr=0.02)
-    tau = S.calibrate_threshold_cp(X, Y, step)
+    tau = S.calibrate_threshold_cp(X, Y, step, after)
     evalw = W.selector_mix(seed=11, steps=4, small=48, large=48)
     res = S.evaluate(evalw, 4, torch.from_numpy(wts).to(DEV), tau)
     m, rp, rb, th = res["mlp"], res["repair"], res["rebuild"], res["threshold"]

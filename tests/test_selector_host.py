@@ -35,3 +35,13 @@ def test_summed_costs_pick_a_rule_that_slows_the_step():
     assert S.calibrate_threshold(X, Y) < 10.0          # rebuild both
     assert S.calibrate_threshold_cp(X, Y, step) >= 10.0  # repair both
     assert np.isclose(S.step_time(np.array([100.0, 50.0]), step), 100.0)
+
+
+def test_rebuilds_after_the_kernel_add_to_the_step():
+    # two blocks whose rebuilds run after the step's kernel: their costs add
+    # to the slowest block that stays in the kernel
+    step = np.array([0, 0, 0])
+    cost = np.array([100.0, 30.0, 50.0])
+    after = np.array([False, True, True])
+    assert np.isclose(S.step_time(cost, step, after), 100.0 + 50.0)
+    assert np.isclose(S.step_time(cost, step), 100.0)
