@@ -41,19 +41,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None if the kernel sources changed since it was taken."""
+def source_hash():
     import hashlib
-    name = kernel.replace("<", "").replace(">", "")
-    path = os.path.join(ROOT, "profiles", f"{name}_{workload}_traffic.json")
-    if not os.path.exists(path):
-        return None
-    d = json.load(open(path))
     h = hashlib.sha256()
     for f in ("kdt.hip", "kdt_device.hpp", "kdt_pbuild.hpp", "kdt_mlp.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2308_06484_amd", "csrc", f), "rb").read())
-    return d["traffic_bytes_per_launch"] if h.hexdigest()[:16] == d["source_sha256_16"] else None
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(form, workload):
+    """HBM bytes per time step of a launch form (summed over the step's
+    kernels) from the committed rocprofv3 counter summary, or None if that
+    form was not profiled or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"step_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha256_16") != source_hash():
+        return None
+    rec = d.get("forms", {}).get(form_name(form))
+    return rec["traffic_bytes_per_step"] if rec else None
+
+
+def step_kernels(form, policy):
+    """The kernels one time step of a launch form runs, in launch order
+    (the two size classes of a split launch run at the same time)."""
+    if form["mode"] == "fused":
+        return ["k_run_fused"]
+    ks = []
+    if form["mode"] == "persistent":
+        ks = ["k_step_persist"]
+    else:
+        w = form.get("waves", 1)
+        if form.get("order") or form.get("cut"):
+            ks.append("k_order")
+        if w > 1:
+            ks.append(f"k_step_mw<{w}>")
+        if w == 1 or form.get("cut"):
+            ks.append("k_step")
+        if w > 1:
+            ks.append("k_step_rest")
+    if policy[0] != "repair":
+        ks.append("k_build_listed")
+    return ks
 
 
 def copy_probe():
@@ -417,7 +447,7 @@ def grid_report(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_run_fused" if args.fused else "k_step", "grid1024"),
+            "traffic": measured_traffic({"mode": "fused" if args.fused else "step", "graph": False}, "grid1024"),
             "kernel": "k_run_fused" if args.fused else "k_step",
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg / n_launch,
@@ -452,8 +482,8 @@ def form_name(f):
         n += "_ordered"
     if f.get("cut"):
         n += f"_cut{f['cut']}"
-    if f.get("prefetch") == 0:
-        n += "_noprefetch"
+    if "prefetch" in f:
+        n += f"_depth{f['prefetch']}"
     if f.get("repair"):
         n += "_" + f["repair"]
     return n + ("_graph" if f.get("graph") else "")
@@ -598,9 +628,7 @@ def headline(args):
     # the region over the launches, gaps and the selector's follow-up
     # launches included: an upper bound of the kernel's own duration
     n_launch = 1 if form["mode"] == "fused" else K
-    kernel = {"step": "k_step", "persistent": "k_step_persist", "fused": "k_run_fused"}[form["mode"]]
-    if form.get("waves", 1) > 1:
-        kernel = f"k_step_mw<{form['waves']}>"
+    kernels = step_kernels(form, pol_mlp)
     avg_launch_s = ms / 1e3 / n_launch
     achieved = alg / n_launch / avg_launch_s / 1e9
     khz = max(1, s1["clock_khz"])
@@ -644,8 +672,11 @@ def headline(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(kernel, "multi2048"),
-            "kernel": kernel,
+            "traffic": (measured_traffic(form, "multi2048") * K / n_launch
+                        if measured_traffic(form, "multi2048") is not None else None),
+            # the unit is one time step: its kernels (the size classes of a
+            # split launch at the same time), gaps between them included
+            "kernel": " + ".join(kernels),
             "avg_launch_us": avg_launch_s * 1e6,
             "alg_bytes_per_launch": alg / n_launch,
             "timed_launches": n_launch,

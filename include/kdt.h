@@ -224,13 +224,14 @@ int kdt_set_launch(kdt_ctx* ctx, int32_t persist_per_cu);
 #define KDT_REPAIR_FLIP 1
 int kdt_set_repair(kdt_ctx* ctx, int32_t variant);
 
-/* Star prefetch (on by default; a tuning knob, not a semantic one): before
- * a block's moves of a step run one after another, its wavefront walks the
- * stars of all the step's movers at once, reading and dropping the records
- * (and the triangles beyond each star's link, the positions and the move
- * records), so that the moves find them in cache.  Same results either way.
- * KDT_E_ARG for a value other than 0 or 1. */
-int kdt_set_prefetch(kdt_ctx* ctx, int32_t on);
+/* Staging depth of the star prefetch (a tuning knob, not a semantic one):
+ * before a block's moves of a step run one after another, its wavefront
+ * walks the stars of all the step's movers at once, reading and dropping
+ * the records, so that the moves find them in cache: depth 0 off, 1 (the
+ * default) the star and the triangle beyond each link edge, 2 also the
+ * triangles beyond those; the positions and move records are touched too.
+ * Same results at every depth.  KDT_E_ARG for a depth outside 0..2. */
+int kdt_set_prefetch(kdt_ctx* ctx, int32_t depth);
 
 /* Wavefronts per block of the per-step launch (KDT_RUN_PER_STEP): 1
  * (default: one wavefront applies the block's moves one after another), 2

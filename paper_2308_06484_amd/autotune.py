@@ -4,7 +4,8 @@ Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
 one kernel per step with 1, 2 or 4 wavefronts per block (the workgroup
 size), the blocks taken in index order or most moves first, size classes
 (only the blocks with at least `cut` moves get several wavefronts, the
-others one, at once on two streams), the star prefetch on or off, the
+others one, at once on two streams), the staging depth of the star
+prefetch (0, 1 or 2 rings), the
 persistent launch with 1..8 workgroups per compute unit (the LDS of an
 MI355X compute unit holds 5), each either launched step by step or
 captured as a HIP graph, and the fused multi-step launch.  Every candidate computes the same
@@ -29,9 +30,9 @@ PER_STEP_CANDIDATES = (
     *({"mode": "step", "graph": g, "waves": 2, "order": 1} for g in (False, True)),
     *({"mode": "step", "graph": True, "waves": nw, "order": 0} for nw in (2, 4)),
     {"mode": "step", "graph": True, "waves": 4, "order": 1},
-    {"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": 24},
+    *({"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": c} for c in (24, 40)),
     {"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": 32},
-    {"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": 0},
+    *({"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": d} for d in (0, 2)),
 )
 DEFAULT_CANDIDATES = (
     *PER_STEP_CANDIDATES,

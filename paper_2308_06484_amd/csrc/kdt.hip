@@ -60,7 +60,7 @@ struct DevState {
     float dlim;          // d of the latest d-calculation (0: none yet): feature 15, the d-limit rule
     int n_blocks;
     int repair;    // repair variant: KDT_REPAIR_*
-    int prefetch;  // 1: warm the caches with the movers' stars before a block's moves
+    int prefetch;  // rings around the movers' stars warmed in cache before a block's moves (0: none)
     int pad_;
     BlockStats* stats;
     float* log;  // per step and block: LOG_FIELDS floats, or null
@@ -647,14 +647,25 @@ __device__ __forceinline__ void block_features(int n, int4 fr, const kdt_move_t*
 // Warms the caches with what the block's moves of the step read first: lane
 // i walks the star of mover i as the step starts (both ways round at once,
 // one pair of records per round trip) and touches the triangle beyond each
-// link edge, the mover's position and its move record; the values are
-// dropped.  The moves, one after another, then find most of their records
-// in cache instead of memory: every record a move reads through its star is
-// one it would otherwise wait a full memory round trip for.  Read only, with
-// every index checked against the block, so a stale or corrupt record only
-// ends the lane's walk.
+// link edge (depth 1) and, at depth 2, the triangles beyond those, the
+// mover's position and its move record; the values are dropped.  The
+// moves, one after another, then find more of their records in cache
+// instead of memory.  Read only, with every index checked against the
+// block, so a stale or corrupt record only ends the lane's walk.
+__device__ __forceinline__ int touch_ring(const BlockView& B, int ring, int depth) {
+    if (bad_slot(B, ring)) return 0;
+    if (depth < 2) return B.tri[ring].v.x;
+    const int4 n = B.tri[ring].n;
+    int acc = n.x;
+    for (int e = 0; e < 3; ++e) {
+        const int r2 = vget(n, e) >> 2;
+        if (!bad_slot(B, r2)) acc ^= B.tri[r2].v.x;
+    }
+    return acc;
+}
+
 __device__ __forceinline__ void prefetch_stars(const BlockView& B, const kdt_move_t* __restrict__ mv, int m0,
-                                               int m1) {
+                                               int m1, int depth) {
     const int lane = lane_id();
     int acc = 0;
     const int m = m0 + lane;
@@ -671,15 +682,15 @@ __device__ __forceinline__ void prefetch_stars(const BlockView& B, const kdt_mov
                 int last_ccw = t0, last_cw = t0;
                 for (int it = 0; it < KMAX / 2; ++it) {
                     const int cs = ccw >> 2, ws = cw >> 2;
-                    if (cs == last_cw || bad_slot(B, cs) || bad_slot(B, ws) || bad_slot(B, ring)) break;
+                    if (cs == last_cw || bad_slot(B, cs) || bad_slot(B, ws)) break;
                     const int4 vc = B.tri[cs].v, nc = B.tri[cs].n, vw = B.tri[ws].v, nw = B.tri[ws].n;
-                    acc ^= B.tri[ring].v.x;  // the previous round's ring record, in flight with these
+                    acc ^= touch_ring(B, ring, depth);  // the previous round's ring record, in flight with these
                     const int pc = ((ccw & 3) + 1) % 3, pw = ((cw & 3) + 2) % 3;
                     if (vget(vc, pc) != p || vget(vw, pw) != p) break;
                     ring = vget(nc, pc) >> 2;
                     const int ring_w = vget(nw, pw) >> 2;
                     if (ws == cs) break;
-                    if (!bad_slot(B, ring_w)) acc ^= B.tri[ring_w].v.x;
+                    acc ^= touch_ring(B, ring_w, depth);
                     last_ccw = cs;
                     last_cw = ws;
                     ccw = vget(nc, (pc + 1) % 3);
@@ -720,7 +731,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     const long long c0 = wall_clock64();
     int rc = ST_OK;
     if (branch == 0) {
-        if (k > 1 && s.prefetch) prefetch_stars(B, mv, m0, m1);
+        if (k > 1 && s.prefetch) prefetch_stars(B, mv, m0, m1, s.prefetch);
         for (int m = m0; m < m1; ++m) {
             int app = 0;
             if (m > m0) gsync();  // the previous move's stores are visible
@@ -1677,7 +1688,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
             M.np = np;
         }
     }
-    if (!M.defer_all && k > 1 && s.prefetch) prefetch_stars(B, mv, m0 + w * WAVE, h.m1);
+    if (!M.defer_all && k > 1 && s.prefetch) prefetch_stars(B, mv, m0 + w * WAVE, h.m1, s.prefetch);
     __syncthreads();
     // reservation rounds over the commuting moves
     while (!M.defer_all && M.np > 0 && M.fail == ST_OK) {
@@ -3243,9 +3254,9 @@ int kdt_set_repair(kdt_ctx* c, int32_t variant) {
     return KDT_OK;
 }
 
-int kdt_set_prefetch(kdt_ctx* c, int32_t on) {
-    if (!c || (on != 0 && on != 1)) return KDT_E_ARG;
-    c->dev.prefetch = on;
+int kdt_set_prefetch(kdt_ctx* c, int32_t depth) {
+    if (!c || depth < 0 || depth > 2) return KDT_E_ARG;
+    c->dev.prefetch = depth;
     c->epoch++;
     return KDT_OK;
 }

@@ -327,9 +327,10 @@ class KineticDT:
         """Repair variant: "delins" (delete + insert) or "flip" (move-and-flip)."""
         _check(_lib().kdt_set_repair(self.ctx, REPAIR[variant]), "kdt_set_repair")
 
-    def set_prefetch(self, on):
-        """Star prefetch before a block's moves (on by default; same results)."""
-        _check(_lib().kdt_set_prefetch(self.ctx, 1 if on else 0), "kdt_set_prefetch")
+    def set_prefetch(self, depth):
+        """Staging depth of the star prefetch before a block's moves: 0 off,
+        1 (default) star and the ring beyond it, 2 one ring more; same results."""
+        _check(_lib().kdt_set_prefetch(self.ctx, int(depth)), "kdt_set_prefetch")
 
     def set_block_order(self, order, heavy_cut=0):
         """Per-step launch schedule: blocks most moves first (order=1) and,

@@ -143,13 +143,15 @@ def calibrate_threshold_cp(X, Y, step, after=None, candidates=256):
     of the observed values, rebuild everything, rebuild nothing).  A choice
     that makes one block of a step slower costs the whole step; per-block
     sums would not see it.  after: per sample, whether its rebuild would run
-    after the step's kernel (None: none would)."""
+    after the step's kernel (None: none would).  Of equally good candidates
+    the largest is kept: on unseen blocks it rebuilds least, and a needless
+    rebuild costs far more than a missed one."""
     f = X[:, 3].astype(np.float64)
     cr, cb = np.exp2(Y[:, 0].astype(np.float64)), np.exp2(Y[:, 1].astype(np.float64))
     late = np.zeros(len(f), dtype=bool) if after is None else np.asarray(after, dtype=bool)
     cand = np.unique(np.concatenate([np.quantile(f, np.linspace(0, 1, candidates)), [f.min() - 1.0, f.max() + 1.0]]))
     best_tau, best = float(f.max() + 1.0), np.inf
-    for tau in cand:
+    for tau in cand[::-1]:
         rb = f > tau
         t = step_time(np.where(rb, cb, cr), step, rb & late)
         if t < best:

@@ -66,7 +66,7 @@ def test_launch_forms_bit_identical(uneven):
         assert got[3]["applied"] == ref[3]["applied"] and got[3]["errors"] == 0
     for graph, shape in [(False, {"order": 1}), (True, {"waves": 2, "order": 1}), (False, {"waves": 4, "order": 1}),
                          (True, {"waves": 4, "order": 1, "cut": 3}), (False, {"waves": 2, "order": 1, "cut": 2}),
-                         (True, {"order": 1, "prefetch": 0})]:
+                         (True, {"order": 1, "prefetch": 0}), (False, {"waves": 2, "order": 1, "prefetch": 2})]:
         got = _run(w, "step", graph, shape=shape)
         for i in range(3):
             assert np.array_equal(got[i], ref[i]), (graph, shape, i)

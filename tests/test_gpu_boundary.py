@@ -190,7 +190,7 @@ def test_schedule_knobs_check_their_arguments():
     assert L.kdt_set_block_order(dt.ctx, 2, 0) == K.E_ARG
     assert L.kdt_set_block_order(dt.ctx, 0, 5) == K.E_ARG  # classes need the order
     assert L.kdt_set_block_order(dt.ctx, 1, -1) == K.E_ARG
-    assert L.kdt_set_prefetch(dt.ctx, 2) == K.E_ARG
+    assert L.kdt_set_prefetch(dt.ctx, 3) == K.E_ARG and L.kdt_set_prefetch(dt.ctx, -1) == K.E_ARG
     assert L.kdt_set_block_order(dt.ctx, 1, 8) == K.OK and L.kdt_set_prefetch(dt.ctx, 0) == K.OK
     assert L.kdt_set_block_order(None, 1, 0) == K.E_ARG and L.kdt_set_prefetch(None, 1) == K.E_ARG
     dt.close()

@@ -45,3 +45,15 @@ def test_rebuilds_after_the_kernel_add_to_the_step():
     after = np.array([False, True, True])
     assert np.isclose(S.step_time(cost, step, after), 100.0 + 50.0)
     assert np.isclose(S.step_time(cost, step), 100.0)
+
+
+def test_ties_keep_the_largest_threshold():
+    # no rebuild pays: every threshold at or above the largest feature
+    # value is optimal, and the largest candidate (rebuild nothing, also on
+    # unseen larger values) is kept rather than the largest observed value
+    X = np.zeros((3, 16), np.float32)
+    X[:, 3] = [1.0, 5.0, 17.25]
+    Y = np.log2(np.array([[10.0, 900.0], [20.0, 800.0], [30.0, 700.0]])).astype(np.float32)
+    step = np.array([0, 0, 1])
+    tau = S.calibrate_threshold_cp(X, Y, step, np.ones(3, bool))
+    assert tau > 17.25
