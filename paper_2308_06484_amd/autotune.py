@@ -31,7 +31,7 @@ PER_STEP_CANDIDATES = (
     *({"mode": "step", "graph": True, "waves": nw, "order": 0} for nw in (2, 4)),
     {"mode": "step", "graph": True, "waves": 4, "order": 1},
     *({"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": c} for c in (24, 40)),
-    {"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": 32},
+    *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c} for c in (32, 40, 48)),
     *({"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": d} for d in (0, 2)),
 )
 DEFAULT_CANDIDATES = (

@@ -204,7 +204,8 @@ struct MovePlan {
     int fast;            // 1: star-only path
 };
 
-__device__ __forceinline__ int apply_move(BlockView& B, WaveLDS& S, const kdt_move_t mv, const int4 fr,
+template <class WL>
+__device__ __forceinline__ int apply_move(BlockView& B, WL& S, const kdt_move_t mv, const int4 fr,
                           BlockStats* st, int* applied, int mode = MV_APPLY, MovePlan* plan = nullptr,
                           bool flip = false) {
     const int lane = lane_id();
@@ -1552,10 +1553,19 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
 // commuting moves commute with them too, so the result is the sequential
 // rule's, and DT* (unique) is the same triangulation.
 constexpr int MW_MAX_WAVES = 4;
+// The rounds' wavefronts plan with a write-back table of MW_HT entries (a
+// move that needs more goes to the rest list, whose sequential path has the
+// full table): half the LDS of a step wavefront's, so that three
+// two-wavefront workgroups, or a four-wavefront one beside two one-wavefront
+// step workgroups, share a compute unit.  A plan then reads at most
+// MW_RSMAX slots: its star, its table entries, its walk.
+constexpr int MW_HT = 128;
+using MwWave = WaveLDST<MW_HT>;
+constexpr int MW_RSMAX = KMAX + MW_HT + WPMAX;
 // claim hash entries: every slot of one round's NW plans (a power of two)
 template <int NW>
-constexpr int mw_hash() { return NW * RSMAX <= 1024 ? 1024 : 2048; }
-static_assert(mw_hash<MW_MAX_WAVES>() >= MW_MAX_WAVES * RSMAX && mw_hash<2>() >= 2 * RSMAX,
+constexpr int mw_hash() { return NW * MW_RSMAX <= 512 ? 512 : (NW * MW_RSMAX <= 1024 ? 1024 : 2048); }
+static_assert(mw_hash<MW_MAX_WAVES>() >= MW_MAX_WAVES * MW_RSMAX && mw_hash<2>() >= 2 * MW_RSMAX,
               "claim hash smaller than the plans of one round");
 constexpr int MW_KMAX = 128;  // moves of a block's step the rounds take; a block with more runs in the rest launch
 constexpr int MWS_PEND = 0, MWS_DONE = 1, MWS_REST = 2;
@@ -1572,7 +1582,7 @@ struct RestBuf {
 
 template <int NW>
 struct MwLDS {
-    WaveLDS S[NW];
+    MwWave S[NW];
     BlockStats pst[NW];          // the counters of each wavefront's current plan
     int hkey[mw_hash<NW>()];     // slot, or -1
     int hprio[mw_hash<NW>()];    // lowest move index claiming it
@@ -1587,18 +1597,20 @@ struct MwLDS {
 
 template <int H>
 __device__ __forceinline__ int mw_home(int slot) {
-    static_assert(H == 1024 || H == 2048, "claim hash size");
-    return (int)(((unsigned)slot * 0x9E3779B1u) >> (H == 1024 ? 22 : 21));
+    static_assert(H == 512 || H == 1024 || H == 2048, "claim hash size");
+    return (int)(((unsigned)slot * 0x9E3779B1u) >> (32 - __builtin_ctz(H)));
 }
 
 // Slot i of a plan's read set: the star, then the table's entries, then the
 // walk's path.
-__device__ __forceinline__ int mw_read_slot(const WaveLDS& S, const MovePlan& pl, int i) {
+__device__ __forceinline__ int mw_read_slot(const MwWave& S, const MovePlan& pl, int i) {
     return i < pl.k ? S.star_slot[i] : (i < pl.k + pl.used ? S.tkey[S.tused[i - pl.k]] : S.wpath[i - pl.k - pl.used]);
 }
 
 static_assert(sizeof(MwLDS<4>) <= 160 * 1024, "four wavefronts' scratch exceeds a compute unit's LDS");
-static_assert(sizeof(MwLDS<2>) <= 80 * 1024, "two two-wavefront workgroups no longer share a compute unit");
+static_assert(3 * sizeof(MwLDS<2>) <= 160 * 1024, "three two-wavefront workgroups no longer share a compute unit");
+static_assert(sizeof(MwLDS<4>) + 2 * sizeof(WaveLDS) <= 160 * 1024,
+              "a four-wavefront workgroup and two step workgroups no longer share a compute unit");
 
 template <int NW>
 __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_move_t* __restrict__ mv,
@@ -1624,7 +1636,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     const int4 fr = h.fr;
     const int m0 = h.m0, k = h.m1 - h.m0;
     constexpr int NF = sizeof(BlockStats) / sizeof(long long);
-    WaveLDS& S = M.S[w];
+    MwWave& S = M.S[w];
     table_clear(S);
     if (lane < NF) reinterpret_cast<long long*>(&S.st)[lane] = 0;
     if (tid == 0) {
@@ -1702,7 +1714,7 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
             rc = apply_move(B, S, mv[m0 + i], fr, &M.pst[w], &app, MV_PLAN, &pl, s.repair == KDT_REPAIR_FLIP);
             if (rc == ST_OK && app == 2) {
                 total = pl.k + pl.used + pl.npath;
-                if (pl.npath > WPMAX || total > RSMAX) {
+                if (pl.npath > WPMAX || total > MW_RSMAX) {
                     rc = ST_CAPACITY;  // too large to reserve: the sequential path takes it
                 } else {
                     for (int e = lane; e < total; e += WAVE) {

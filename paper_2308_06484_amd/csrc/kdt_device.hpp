@@ -94,8 +94,13 @@ struct BlockStats {
     long long flips;    // edge flips of those moves
 };
 
-// per-wavefront scratch in LDS
-struct WaveLDS {
+// per-wavefront scratch in LDS; H write-back table entries (a power of two,
+// at most 256)
+template <int H>
+struct WaveLDST {
+    static constexpr int TN = H;                 // table entries
+    static constexpr int TLIMIT = H * 25 / 32;   // entries a move may use (keeps probe chains short)
+    static_assert(H <= 256 && (H & (H - 1)) == 0, "table entries are listed as bytes, hashed by bits");
     // star of the deleted point, counter-clockwise
     int star_slot[KMAX];
     int link[KMAX];      // link vertex q_s (star triangle s = (p, q_s, q_s+1))
@@ -106,10 +111,10 @@ struct WaveLDS {
     int hole_key[KMAX];  // packed link indices (i, j, l) of hole triangles
     int hole_ent[KMAX];  // table entry of hole triangle h
     // write-back table
-    int tkey[HT];  // slot, or -1
-    int tflag[HT];
-    Tri trec[HT];
-    uint8_t tused[HT];  // entries in use, in claim order (HT <= 256)
+    int tkey[H];  // slot, or -1
+    int tflag[H];
+    Tri trec[H];
+    uint8_t tused[H];  // entries in use, in claim order (H <= 256)
     // the directed edges (u, w) of the hole triangles: 4 * triangle + edge
     int emat[EMK * EMK];
     // Bowyer-Watson cavity: table entries, boundary edges (a, b) with the
@@ -127,6 +132,10 @@ struct WaveLDS {
     int wpath[WPMAX];  // slots a planned move's walks read (global mode)
     BlockStats st;  // the block's counters while its wavefront works on it
 };
+// the step kernels' scratch: a table that holds any move the path's other
+// capacities allow
+using WaveLDS = WaveLDST<HT>;
+static_assert(WaveLDS::TLIMIT == HT_LIMIT, "table limit");
 // The rebuild branch does not use the repair scratch (everything before
 // `st`) and lays its own arrays over it, so they cost no LDS of their own
 // (4 KB less lets five step wavefronts share a compute unit instead of four):
@@ -310,10 +319,14 @@ __device__ __forceinline__ bool conflicts(const Tri& t, int2 q, int rq) {
 
 // ---------------------------------------------------------------- table
 
-__device__ __forceinline__ int thash(int s) { return (int)(((unsigned)s * 0x9E3779B1u) >> 24); }
+template <int H>
+__device__ __forceinline__ int thash(int s) {
+    return (int)(((unsigned)s * 0x9E3779B1u) >> (32 - __builtin_ctz(H)));
+}
 
-__device__ __forceinline__ void table_clear(WaveLDS& S) {
-    for (int h = lane_id(); h < HT; h += WAVE) {
+template <class WL>
+__device__ __forceinline__ void table_clear(WL& S) {
+    for (int h = lane_id(); h < WL::TN; h += WAVE) {
         S.tkey[h] = -1;
         S.tflag[h] = 0;
     }
@@ -321,7 +334,8 @@ __device__ __forceinline__ void table_clear(WaveLDS& S) {
 }
 
 // Per-kernel setup of the wave's scratch: an empty table.
-__device__ __forceinline__ void scratch_init(WaveLDS& S) { table_clear(S); }
+template <class WL>
+__device__ __forceinline__ void scratch_init(WL& S) { table_clear(S); }
 
 // The t-th triple i < j < l < 16 in colex order (t < 560): l is the number
 // of tetrahedral numbers C(l'+1, 3) <= t, j the number of triangular numbers
@@ -340,13 +354,14 @@ __device__ __forceinline__ void triple_of(int t, int* i, int* j, int* l) {
 }
 
 // Entry of slot s, or -1.
-__device__ __forceinline__ int tfind(const WaveLDS& S, int s) {
-    int h = thash(s);
-    for (int i = 0; i < HT; ++i) {
+template <class WL>
+__device__ __forceinline__ int tfind(const WL& S, int s) {
+    int h = thash<WL::TN>(s);
+    for (int i = 0; i < WL::TN; ++i) {
         const int k = S.tkey[h];
         if (k == s) return h;
         if (k == -1) return -1;
-        h = (h + 1) & (HT - 1);
+        h = (h + 1) & (WL::TN - 1);
     }
     return -1;
 }
@@ -354,11 +369,12 @@ __device__ __forceinline__ int tfind(const WaveLDS& S, int s) {
 // Claim the entry of slot s for every lane with want set: found if present,
 // else created (linear probing, claimed by compare-and-swap).  *mine tells
 // the lane that created it.  -1 if the table is full.
-__device__ __forceinline__ int tclaim(WaveLDS& S, bool want, int s, bool* mine) {
+template <class WL>
+__device__ __forceinline__ int tclaim(WL& S, bool want, int s, bool* mine) {
     *mine = false;
     if (!want) return -1;
-    int h = thash(s);
-    for (int i = 0; i < HT; ++i) {
+    int h = thash<WL::TN>(s);
+    for (int i = 0; i < WL::TN; ++i) {
         const int k = S.tkey[h];
         if (k == s) return h;
         if (k == -1) {
@@ -366,7 +382,7 @@ __device__ __forceinline__ int tclaim(WaveLDS& S, bool want, int s, bool* mine) 
             if (old == -1) { *mine = true; return h; }
             if (old == s) return h;
         }
-        h = (h + 1) & (HT - 1);
+        h = (h + 1) & (WL::TN - 1);
     }
     return -1;
 }
@@ -375,13 +391,15 @@ __device__ __forceinline__ int tclaim(WaveLDS& S, bool want, int s, bool* mine) 
 // from memory if it is not in the table yet.  Called by the whole wave.
 // *used counts the entries in use (wave-uniform); returns -1 on a full table.
 // Record the entries the lanes with `mine` set just claimed.
-__device__ __forceinline__ void tnote(WaveLDS& S, bool mine, int e, int* used) {
+template <class WL>
+__device__ __forceinline__ void tnote(WL& S, bool mine, int e, int* used) {
     const uint64_t m = ballot(mine);
-    if (mine && *used + lanes_below(m) < HT) S.tused[*used + lanes_below(m)] = e;
+    if (mine && *used + lanes_below(m) < WL::TN) S.tused[*used + lanes_below(m)] = e;
     *used += __popcll(m);
 }
 
-__device__ __forceinline__ int tget(const BlockView& B, WaveLDS& S, bool want, int s, int* used) {
+template <class WL>
+__device__ __forceinline__ int tget(const BlockView& B, WL& S, bool want, int s, int* used) {
     bool mine;
     const int e = tclaim(S, want, s, &mine);
     if (mine) {
@@ -401,7 +419,8 @@ __device__ __forceinline__ int tget(const BlockView& B, WaveLDS& S, bool want, i
 }
 
 // Record of slot s as the move sees it (table first, memory else).
-__device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s) {
+template <class WL>
+__device__ __forceinline__ Tri tread(const BlockView& B, const WL& S, int s) {
     const int e = tfind(S, s);
     if (e >= 0) return S.trec[e];
     return load_tri(B.tri + s);
@@ -413,8 +432,8 @@ __device__ __forceinline__ Tri tread(const BlockView& B, const WaveLDS& S, int s
 // ghost whose half-plane holds q.  *hit gets the local index of a vertex
 // sitting exactly at q (-1 if none).  Returns -1 if the step limit is hit.
 // TABLE: read through the move's write-back table (after changes).
-template <bool TABLE>
-__device__ __forceinline__ int walk(const BlockView& B, const WaveLDS* S, int start, int2 q, int* hit, int* hops,
+template <bool TABLE, class WL>
+__device__ __forceinline__ int walk(const BlockView& B, const WL* S, int start, int2 q, int* hit, int* hops,
                     int* path = nullptr, int* npath = nullptr) {
     int cur = start, entry = -1;
     const int limit = 4 * B.ntri + 16;
@@ -475,7 +494,8 @@ __device__ __forceinline__ int3 fan_phys(int a, int b) {
 // frontier's neighbours, ballots and prefix counts compact the survivors.
 // *used: table entries in use; *nvt: pending incident-triangle updates.
 // Returns ST_OK or an error code (the table is then not to be written back).
-__device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int qv, int2 q, int seed, int nseed, int f0,
+template <class WL>
+__device__ __forceinline__ int insert_vertex(const BlockView& B, WL& S, int qv, int2 q, int seed, int nseed, int f0,
                              int f1, int* used, int* nvt, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, f0) || bad_slot(B, f1)) return ST_INTERNAL;
@@ -511,7 +531,7 @@ __device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int
             const bool okslot = act && !bad_slot(B, ns);
             if (ballot(act && !okslot)) return ST_INTERNAL;
             const int ne = tget(B, S, okslot, ns, used);
-            if (ballot(okslot && ne < 0) || *used > HT_LIMIT) return ST_CAPACITY;
+            if (ballot(okslot && ne < 0) || *used > WL::TLIMIT) return ST_CAPACITY;
             bool incav = false, conf = false, bad = false;
             if (act) {
                 incav = (S.tflag[ne] & F_CAV) != 0;
@@ -552,7 +572,7 @@ __device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int
     bool mine;
     const int fent = tclaim(S, lane < 2, lane == 0 ? f0 : f1, &mine);
     tnote(S, mine, fent, used);
-    if (ballot(lane < 2 && fent < 0) || *used > HT) return ST_CAPACITY;
+    if (ballot(lane < 2 && fent < 0) || *used > WL::TN) return ST_CAPACITY;
     const int fe0 = __shfl(fent, 0), fe1 = __shfl(fent, 1);
     wsync();
 
@@ -623,7 +643,8 @@ __device__ __forceinline__ int insert_vertex(const BlockView& B, WaveLDS& S, int
 // of the deletion, then those of the insertion (no point occurs twice in
 // one list; stores of one wavefront to one address land in program order,
 // so the insertion's value wins), and empty the table.
-__device__ __forceinline__ void commit(const BlockView& B, WaveLDS& S, int used, int nvt_del, int nvt) {
+template <class WL>
+__device__ __forceinline__ void commit(const BlockView& B, WL& S, int used, int nvt_del, int nvt) {
     const int lane = lane_id();
     for (int u = lane; u < used; u += WAVE) {
         const int h = S.tused[u];
@@ -648,7 +669,8 @@ __device__ __forceinline__ void commit(const BlockView& B, WaveLDS& S, int used,
 
 // Empty the table entries of the tused list without writing anything back
 // (a planned move that is not committed).
-__device__ __forceinline__ void table_drop(WaveLDS& S, int used) {
+template <class WL>
+__device__ __forceinline__ void table_drop(WL& S, int used) {
     wsync();
     for (int u = lane_id(); u < used; u += WAVE) {
         const int h = S.tused[u];
@@ -666,7 +688,8 @@ __device__ __forceinline__ void table_drop(WaveLDS& S, int used) {
 // and the triangles outside the link edges into the table.  Two walkers
 // turn around p in opposite directions and meet halfway.
 // t0: p's incident triangle.  Returns the degree k (>= 3) or an error code.
-__device__ __forceinline__ int gather_star(const BlockView& B, WaveLDS& S, int p, int t0, int* used, BlockStats* st) {
+template <class WL>
+__device__ __forceinline__ int gather_star(const BlockView& B, WL& S, int p, int t0, int* used, BlockStats* st) {
     const int lane = lane_id();
     if (bad_slot(B, t0)) return ST_INTERNAL;
     const Tri r0 = load_tri(B.tri + t0);
@@ -756,7 +779,8 @@ __device__ __forceinline__ int gather_star(const BlockView& B, WaveLDS& S, int p
 // Is q inside the closed region of p's star (p at position pp), and does it
 // sit on a link vertex?  Star triangle s is (p, q_s, q_s+1); a ghost one is
 // tested as the half-plane it stands for.
-__device__ __forceinline__ void locate_in_star(const WaveLDS& S, int k, int2 pp, int2 q,
+template <class WL>
+__device__ __forceinline__ void locate_in_star(const WL& S, int k, int2 pp, int2 q,
                                                bool* in_star, bool* on_vertex) {
     const int lane = lane_id();
     bool in = false, on = false;
@@ -777,7 +801,8 @@ __device__ __forceinline__ void locate_in_star(const WaveLDS& S, int k, int2 pp,
 // each once -- goes into S.cav_ent, flagged F_CAV.  The triangles a point
 // destroys form one connected region, so the cavity grows from these
 // without a walk.  Returns their number.
-__device__ __forceinline__ int seed_cavity(WaveLDS& S, int k, int2 q, int qv) {
+template <class WL>
+__device__ __forceinline__ int seed_cavity(WL& S, int k, int2 q, int qv) {
     const int lane = lane_id();
     const int he = lane < k - 2 ? S.hole_ent[lane] : -1;
     const bool ch = he >= 0 && conflicts(S.trec[he], q, qv);
@@ -813,7 +838,8 @@ __device__ __forceinline__ int seed_cavity(WaveLDS& S, int k, int2 q, int qv) {
 // hold it (in a grown triangle, not at its corner).  Returns the new vertex
 // count -- the polygon arrays rewritten, the grown triangles' slots after
 // the star's in S.star_slot -- or 0 with the star's polygon as it was.
-__device__ __forceinline__ int grow_region(const BlockView& B, WaveLDS& S, int k, int2 q, int qv, uint64_t cm,
+template <class WL>
+__device__ __forceinline__ int grow_region(const BlockView& B, WL& S, int k, int2 q, int qv, uint64_t cm,
                                            int* used, bool q_out) {
     const int lane = lane_id();
     // the star's polygon, put back if the growth stops short
@@ -972,7 +998,8 @@ struct TriCand {
 };
 
 // The candidate with the given indices (already oriented).
-__device__ __forceinline__ TriCand tri_cand_of(const WaveLDS& S, int k, int i, int j, int l, int qv, int2 q) {
+template <class WL>
+__device__ __forceinline__ TriCand tri_cand_of(const WL& S, int k, int i, int j, int l, int qv, int2 q) {
     TriCand c;
     c.i = i; c.j = j; c.l = l;
     c.vi = i == k ? qv : S.link[i];
@@ -989,7 +1016,8 @@ __device__ __forceinline__ TriCand tri_cand_of(const WaveLDS& S, int k, int i, i
 // Candidate t: the link triples first, then the pairs (q_i, q_j) with q,
 // then (p on the hull) the ghosts with q; ok tells whether it passes
 // orientation and, with q, keeps q out of its circle or half-plane.
-__device__ __forceinline__ TriCand tri_cand(const WaveLDS& S, int k, int t, int ntrip, int npair, int ncand,
+template <class WL>
+__device__ __forceinline__ TriCand tri_cand(const WL& S, int k, int t, int ntrip, int npair, int ncand,
                                             int qv, int2 q, bool with_q) {
     int i = 0, j = 1, l = 2, kind = 0;  // 0 link triple, 1 (q_i, q_j, q), 2 ghost with q
     bool ok = t < ncand;
@@ -1042,7 +1070,8 @@ __device__ __forceinline__ bool cand_killed_by(const TriCand& c, int m, int vm, 
                    : incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, pm, vm) >= 0;
 }
 
-__device__ __forceinline__ int fill_star(const BlockView& B, WaveLDS& S, int k, int qv, int2 q, bool with_q, int* used,
+template <class WL>
+__device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int qv, int2 q, bool with_q, int* used,
                          int* nvt, BlockStats* st, bool direct = false) {
     const int lane = lane_id();
     if (k < 3) return ST_INTERNAL;
@@ -1264,7 +1293,8 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WaveLDS& S, int k, 
 // changed), or ST_CAPACITY (too many flips, or the table is full; memory
 // unchanged).
 constexpr int FLIP_MAX = (VTMAX - 1) / 2;  // flips one move may do: two incident-triangle updates each
-__device__ __forceinline__ int move_and_flip(const BlockView& B, WaveLDS& S, int k, int p, int2 q, int* used,
+template <class WL>
+__device__ __forceinline__ int move_and_flip(const BlockView& B, WL& S, int k, int p, int2 q, int* used,
                                              int* nvt, int* nflips) {
     const int lane = lane_id();
     *nflips = 0;

@@ -76,7 +76,7 @@ struct AttView {
 __device__ int tplan(const BlockView& B, int v, int2 q, int hint, const AttView& A, int* nc_out,
                      int* nb_out) {
     int hit, hops = 0;
-    const int seed = walk<false>(B, nullptr, hint, q, &hit, &hops);
+    const int seed = walk<false, WaveLDS>(B, nullptr, hint, q, &hit, &hops);
     if (seed < 0) return ST_INTERNAL;
     if (hit >= 0) return ST_INTERNAL;  // duplicate points are rejected before building
     int nc = 1, nb = 0;
