@@ -77,6 +77,8 @@ def step_kernels(form, policy):
             ks.append("k_order")
         if w > 1:
             ks.append(f"k_step_mw<{w}>")
+        if form.get("mid"):
+            ks.append("k_step_mw<2>")
         if w == 1 or form.get("cut"):
             ks.append("k_step")
         if w > 1:
@@ -482,6 +484,8 @@ def form_name(f):
         n += "_ordered"
     if f.get("cut"):
         n += f"_cut{f['cut']}"
+    if f.get("mid"):
+        n += f"_mid{f['mid']}"
     if "prefetch" in f:
         n += f"_depth{f['prefetch']}"
     if f.get("repair"):
@@ -559,7 +563,8 @@ def headline(args):
     else:
         best = A.autotune(cal, steps=CAL_STEPS, candidates=headline_forms(), device=dev, use_cache=False,
                           policy=pol_mlp)
-        form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves", "order", "cut", "prefetch") if k in best}
+        form = {k: best[k] for k in ("mode", "graph", "per_cu", "waves", "order", "cut", "mid", "prefetch")
+                if k in best}
         autotune_table = {form_name(r): r["s_per_step"] * 1e3 for r in best["table"]}
         log("autotuner (calibration workload, MLP policy): " + ", ".join(
             f"{form_name(r)} {r['s_per_step'] * 1e3:.3f} ms" for r in best["table"]) + f" -> {form_name(form)}")

@@ -260,10 +260,14 @@ int kdt_set_block_waves(kdt_ctx* ctx, int32_t waves);
  * above 1): size classes -- only the blocks with at least heavy_cut moves
  * in the step get the several-wavefront workgroups, on a second stream of
  * the context, while the one-wavefront kernel takes the others at the same
- * time on the context's stream; the rest launch follows both.  Default
- * order 0, heavy_cut 0.  KDT_E_ARG for order outside {0, 1}, a negative
- * heavy_cut or heavy_cut > 0 with order 0; KDT_E_STATE in global mode. */
-int kdt_set_block_order(kdt_ctx* ctx, int32_t order, int32_t heavy_cut);
+ * time on the context's stream; the rest launch follows both.  mid_cut in
+ * 1 .. heavy_cut - 1 (with four wavefronts per block): a middle class --
+ * the blocks with mid_cut .. heavy_cut - 1 moves get two-wavefront
+ * workgroups on a third stream, at the same time.  Default order 0,
+ * heavy_cut 0, mid_cut 0.  KDT_E_ARG for order outside {0, 1}, a negative
+ * cut, heavy_cut > 0 with order 0, or mid_cut > 0 without
+ * 0 < mid_cut < heavy_cut; KDT_E_STATE in global mode. */
+int kdt_set_block_order(kdt_ctx* ctx, int32_t order, int32_t heavy_cut, int32_t mid_cut);
 
 /* The same n_steps steps captured once as a HIP graph and replayed by
  * kdt_graph_launch (each replay applies the same move stream again, from the

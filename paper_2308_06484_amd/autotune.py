@@ -4,7 +4,8 @@ Candidates are the launch forms of `kdt_run` and `kdt_graph_build`:
 one kernel per step with 1, 2 or 4 wavefronts per block (the workgroup
 size), the blocks taken in index order or most moves first, size classes
 (only the blocks with at least `cut` moves get several wavefronts, the
-others one, at once on two streams), the staging depth of the star
+others one -- or, with `mid`, two for the blocks from `mid` moves -- at once
+on separate streams), the staging depth of the star
 prefetch (0, 1 or 2 rings), the
 persistent launch with 1..8 workgroups per compute unit (the LDS of an
 MI355X compute unit holds 5), each either launched step by step or
@@ -32,6 +33,8 @@ PER_STEP_CANDIDATES = (
     {"mode": "step", "graph": True, "waves": 4, "order": 1},
     *({"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": c} for c in (24, 40)),
     *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c} for c in (32, 40, 48)),
+    *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c, "mid": m} for c, m in ((40, 16), (40, 24),
+                                                                                              (48, 16), (48, 24))),
     *({"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": d} for d in (0, 2)),
 )
 DEFAULT_CANDIDATES = (
@@ -48,7 +51,7 @@ def apply_form(dt, form):
     if form.get("waves", 1) > 1:
         dt.set_block_waves(form["waves"])
     if form.get("order") or form.get("cut"):
-        dt.set_block_order(form.get("order", 0), form.get("cut", 0))
+        dt.set_block_order(form.get("order", 0), form.get("cut", 0), form.get("mid", 0))
     if "prefetch" in form:
         dt.set_prefetch(form["prefetch"])
     if form.get("repair"):

@@ -791,9 +791,14 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
 // blocks are independent), for the per-step launches: the blocks that set
 // the step's length start first instead of wherever their index puts them.
 // order[B] = the number of blocks with at least `cut` moves (the heavy
-// class of the split launch: the first order[B] entries).
+// class of the split launch: the first order[B] entries), order[B + 1] the
+// number with at least `cut2` <= cut (heavy and middle classes).
 constexpr int ORD_BUCKETS = DRYMAX + 2;  // k = 0 .. DRYMAX, and more
-__global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int B, int cut, int* order) {
+__device__ __forceinline__ int ord_count(const int* base, int B, int cut) {
+    return cut <= 0 ? B : (cut > DRYMAX + 1 ? 0 : base[DRYMAX + 2 - cut]);
+}
+__global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int B, int cut, int cut2,
+                                                int* order) {
     __shared__ int cnt[ORD_BUCKETS];
     __shared__ int base[ORD_BUCKETS];
     const int tid = threadIdx.x;
@@ -819,7 +824,10 @@ __global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int
         }
     }
     __syncthreads();
-    if (tid == 0) order[B] = cut <= 0 ? B : (cut > DRYMAX + 1 ? 0 : base[DRYMAX + 2 - cut]);
+    if (tid == 0) {
+        order[B] = ord_count(base, B, cut);
+        order[B + 1] = ord_count(base, B, cut2);
+    }
     __syncthreads();
     for (int b = tid; b < B; b += blockDim.x) {
         const int k = min(max(off[b + 1] - off[b], 0), DRYMAX + 1);
@@ -829,14 +837,17 @@ __global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int
 
 // The block a per-step workgroup takes: its index (no order), or its rank
 // in the step's order over all blocks (part 0), over the heavy class (part
-// 1: the first order[B] ranks) or over the rest (part 2); -1: none.
-constexpr int PART_ALL = 0, PART_HEAVY = 1, PART_LIGHT = 2;
+// 1: ranks below order[B]), the middle class (part 3: ranks order[B] ..
+// order[B + 1]) or the light class (part 2: the ranks from order[B + 1]);
+// -1: none.
+constexpr int PART_ALL = 0, PART_HEAVY = 1, PART_LIGHT = 2, PART_MID = 3;
 __device__ __forceinline__ int pick_block(int B, const int* __restrict__ order, int part) {
     const int g = blockIdx.x;
     if (!order) return g < B ? g : -1;
-    const int r = part == PART_LIGHT ? order[B] + g : g;
-    if (r >= (part == PART_HEAVY ? order[B] : B)) return -1;
-    return order[r];
+    const int lo = part == PART_LIGHT ? order[B + 1] : (part == PART_MID ? order[B] : 0);
+    const int hi = part == PART_HEAVY ? order[B] : (part == PART_MID ? order[B + 1] : B);
+    const int r = lo + g;
+    return r < hi ? order[r] : -1;
 }
 
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
@@ -2316,7 +2327,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_app = take((size_t)std::max(max_staged, 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
-    L.sorder = take(sizeof(int) * (B + 1));
+    L.sorder = take(sizeof(int) * (B + 2));
     L.rest_mv = take(sizeof(kdt_move_t) * (size_t)B * DRYMAX);
     L.rest_idx = take(sizeof(int) * (size_t)B * DRYMAX);
     L.rest_app = take((size_t)B * DRYMAX);
@@ -2504,8 +2515,9 @@ struct kdt_ctx {
     int block_waves = 1;     // wavefronts per block of the per-step launch (1, 2 or 4)
     int block_order = 0;     // 1: the per-step launch takes blocks most moves first
     int heavy_cut = 0;       // > 0 (with block_waves > 1): only blocks of this many moves get several wavefronts
-    hipStream_t side = nullptr;                          // second stream of the split launch
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;     // its fork and join
+    int mid_cut = 0;         // > 0 (with block_waves 4): blocks of mid_cut .. heavy_cut - 1 moves get two
+    hipStream_t side = nullptr, side2 = nullptr;         // streams of the heavy and middle classes
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, join2_ev = nullptr;  // fork, joins
     RestBuf rest{};          // rest lists of the multi-wavefront launch
     // d-calculation over time (kdt_dcalc): running minimum of the squared
     // mindistance, every block's running maximum N-spread, for one N
@@ -3193,14 +3205,17 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             // its heavy class: the blocks with at least heavy_cut moves
             int* ord = nullptr;
             const bool split = c->block_waves > 1 && c->heavy_cut > 0;
+            const bool mid = split && c->block_waves == 4 && c->mid_cut > 0;
             if (c->block_order || split) {
                 ord = (int*)(w + c->L.sorder);
-                k_order<<<1, 1024, 0, c->stream>>>(off, c->B, split ? c->heavy_cut : DRYMAX + 2, ord);
+                const int cut = split ? c->heavy_cut : DRYMAX + 2;
+                k_order<<<1, 1024, 0, c->stream>>>(off, c->B, cut, mid ? c->mid_cut : cut, ord);
             }
             hipStream_t mws = c->stream;
-            if (split) {  // heavy blocks on the side stream, at the same time as the others
+            if (split) {  // heavy (and middle) blocks on side streams, at the same time as the others
                 if (check_hip(c, hipEventRecord(c->fork_ev, c->stream)) ||
-                    check_hip(c, hipStreamWaitEvent(c->side, c->fork_ev, 0)))
+                    check_hip(c, hipStreamWaitEvent(c->side, c->fork_ev, 0)) ||
+                    (mid && check_hip(c, hipStreamWaitEvent(c->side2, c->fork_ev, 0))))
                     return KDT_E_DEVICE;
                 mws = c->side;
             }
@@ -3210,11 +3225,17 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             else if (c->block_waves == 2)
                 k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), mws>>>(
                     c->dev, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
+            if (mid)
+                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), c->side2>>>(c->dev, moves, off, applied,
+                                                                            c->step_count, c->rest, ord, PART_MID);
             if (c->block_waves == 1 || split)
                 k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count, ord,
                                                                    split ? PART_LIGHT : PART_ALL);
             if (split && (check_hip(c, hipEventRecord(c->join_ev, c->side)) ||
                           check_hip(c, hipStreamWaitEvent(c->stream, c->join_ev, 0))))
+                return KDT_E_DEVICE;
+            if (mid && (check_hip(c, hipEventRecord(c->join2_ev, c->side2)) ||
+                        check_hip(c, hipStreamWaitEvent(c->stream, c->join2_ev, 0))))
                 return KDT_E_DEVICE;
             if (c->block_waves > 1)
                 k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, c->rest, applied,
@@ -3273,8 +3294,10 @@ int kdt_set_prefetch(kdt_ctx* c, int32_t depth) {
     return KDT_OK;
 }
 
-int kdt_set_block_order(kdt_ctx* c, int32_t order, int32_t heavy_cut) {
-    if (!c || (order != 0 && order != 1) || heavy_cut < 0 || (heavy_cut > 0 && !order)) return KDT_E_ARG;
+int kdt_set_block_order(kdt_ctx* c, int32_t order, int32_t heavy_cut, int32_t mid_cut) {
+    if (!c || (order != 0 && order != 1) || heavy_cut < 0 || (heavy_cut > 0 && !order) || mid_cut < 0 ||
+        (mid_cut > 0 && (heavy_cut == 0 || mid_cut >= heavy_cut)))
+        return KDT_E_ARG;
     if (c->global) return KDT_E_STATE;
     if (heavy_cut > 0 && !c->side) {
         if (check_hip(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) ||
@@ -3282,8 +3305,14 @@ int kdt_set_block_order(kdt_ctx* c, int32_t order, int32_t heavy_cut) {
             check_hip(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)))
             return KDT_E_DEVICE;
     }
+    if (mid_cut > 0 && !c->side2) {
+        if (check_hip(c, hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking)) ||
+            check_hip(c, hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming)))
+            return KDT_E_DEVICE;
+    }
     c->block_order = order;
     c->heavy_cut = heavy_cut;
+    c->mid_cut = mid_cut;
     c->epoch++;
     return KDT_OK;
 }
@@ -4039,12 +4068,13 @@ void kdt_destroy(kdt_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     release_events(c);
-    if (c->side) {
-        (void)hipStreamSynchronize(c->side);
-        (void)hipStreamDestroy(c->side);
-    }
-    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+    for (hipStream_t st : {c->side, c->side2})
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    for (hipEvent_t e : {c->fork_ev, c->join_ev, c->join2_ev})
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -332,11 +332,13 @@ class KineticDT:
         1 (default) star and the ring beyond it, 2 one ring more; same results."""
         _check(_lib().kdt_set_prefetch(self.ctx, int(depth)), "kdt_set_prefetch")
 
-    def set_block_order(self, order, heavy_cut=0):
+    def set_block_order(self, order, heavy_cut=0, mid_cut=0):
         """Per-step launch schedule: blocks most moves first (order=1) and,
         with several wavefronts per block, size classes split at heavy_cut
-        moves (run at once on two streams)."""
-        _check(_lib().kdt_set_block_order(self.ctx, int(order), int(heavy_cut)), "kdt_set_block_order")
+        moves (and, with four wavefronts, a two-wavefront middle class from
+        mid_cut moves), run at once on separate streams."""
+        _check(_lib().kdt_set_block_order(self.ctx, int(order), int(heavy_cut), int(mid_cut)),
+               "kdt_set_block_order")
 
     def set_block_waves(self, waves):
         """Wavefronts per block of the per-step launch (1, 2 or 4)."""

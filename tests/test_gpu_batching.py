@@ -66,7 +66,8 @@ def test_launch_forms_bit_identical(uneven):
         assert got[3]["applied"] == ref[3]["applied"] and got[3]["errors"] == 0
     for graph, shape in [(False, {"order": 1}), (True, {"waves": 2, "order": 1}), (False, {"waves": 4, "order": 1}),
                          (True, {"waves": 4, "order": 1, "cut": 3}), (False, {"waves": 2, "order": 1, "cut": 2}),
-                         (True, {"order": 1, "prefetch": 0}), (False, {"waves": 2, "order": 1, "prefetch": 2})]:
+                         (True, {"order": 1, "prefetch": 0}), (False, {"waves": 2, "order": 1, "prefetch": 2}),
+                         (True, {"waves": 4, "order": 1, "cut": 4, "mid": 2})]:
         got = _run(w, "step", graph, shape=shape)
         for i in range(3):
             assert np.array_equal(got[i], ref[i]), (graph, shape, i)
@@ -80,6 +81,8 @@ def test_graph_replays_apply_the_stream_again(uneven):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     # the split launch's fork and join replayed
     c = _run(w, "step", graph=True, repeat=2, shape={"waves": 2, "order": 1, "cut": 3})
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    c = _run(w, "step", graph=True, repeat=2, shape={"waves": 4, "order": 1, "cut": 3, "mid": 2})
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
     oracle = Kinetic(w["xy"], w["pt_off"], w["frame"])
     for _ in range(2):

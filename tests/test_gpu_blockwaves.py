@@ -1,8 +1,8 @@
 """Several wavefronts per block (kdt_set_block_waves 2 and 4): a block's
 commuting moves in reservation rounds, the others afterwards in list order;
 with the blocks taken most moves first and with size classes (only blocks
-with at least `cut` moves get several wavefronts, the others one, on two
-streams at once) (kdt_set_block_order).  Every step against the oracle
+with at least `cut` moves get several wavefronts, the others one -- or two
+from `mid` moves -- on separate streams at once) (kdt_set_block_order).  Every step against the oracle
 (triangulations, applied flags, positions), on workloads with many moves per
 block, dense lattices where moves share cells and are blocked, a point whose
 degree exceeds the repair path's capacity, and under the rebuilding
@@ -22,13 +22,13 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def run_waves(w, waves, policy=None, tau=0.0, mlp_w=None, label="", order=0, cut=0):
+def run_waves(w, waves, policy=None, tau=0.0, mlp_w=None, label="", order=0, cut=0, mid=0):
     from paper_2308_06484_amd.kdt import KineticDT
     T = w["mv_off"].shape[0]
     dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
     dt.set_block_waves(waves)
-    dt.set_block_order(order, cut)
-    label = f"{label} order {order} cut {cut}"
+    dt.set_block_order(order, cut, mid)
+    label = f"{label} order {order} cut {cut} mid {mid}"
     if policy:
         dt.set_policy(policy, tau, mlp_w)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
@@ -51,16 +51,17 @@ def run_waves(w, waves, policy=None, tau=0.0, mlp_w=None, label="", order=0, cut
     return st
 
 
-@pytest.mark.parametrize("waves,order,cut", [(2, 0, 0), (4, 0, 0), (2, 1, 0), (4, 1, 0), (2, 1, 6), (4, 1, 6)])
-def test_many_moves_per_block(waves, order, cut):
-    _say(f"multi-move blocks, {waves} wavefronts per block, order {order}, cut {cut}")
+@pytest.mark.parametrize("waves,order,cut,mid", [(2, 0, 0, 0), (4, 0, 0, 0), (2, 1, 0, 0), (4, 1, 0, 0), (2, 1, 6, 0),
+                                                 (4, 1, 6, 0), (4, 1, 20, 5)])
+def test_many_moves_per_block(waves, order, cut, mid):
+    _say(f"multi-move blocks, {waves} wavefronts per block, order {order}, cut {cut}, mid {mid}")
     w = W.multi2048(seed=9, steps=8, blocks=24, per_block=1024, side=4096, dcap=1024)
-    st = run_waves(w, waves, label="multi", order=order, cut=cut)
+    st = run_waves(w, waves, label="multi", order=order, cut=cut, mid=mid)
     assert st["applied"] > 1000
 
 
-@pytest.mark.parametrize("waves,order,cut", [(2, 0, 0), (4, 0, 0), (2, 1, 16)])
-def test_dense_lattice_shared_cells(waves, order, cut):
+@pytest.mark.parametrize("waves,order,cut,mid", [(2, 0, 0, 0), (4, 0, 0, 0), (2, 1, 16, 0), (4, 1, 20, 12)])
+def test_dense_lattice_shared_cells(waves, order, cut, mid):
     """Nearly full small lattices, 8..30 moves per block per step of 1..2
     units: many moves share cells (they go to the rest list) or are blocked."""
     rng = np.random.default_rng(17 + waves)
@@ -90,8 +91,8 @@ def test_dense_lattice_shared_cells(waves, order, cut):
             offs[t, b + 1] = base
     w = dict(xy=xy, pt_off=np.array(off, np.int64), frame=np.array(frame, np.int32),
              mv=np.concatenate(recs), mv_off=offs.astype(np.int32))
-    _say(f"dense lattices, {waves} wavefronts per block, order {order}, cut {cut}")
-    run_waves(w, waves, label="dense", order=order, cut=cut)
+    _say(f"dense lattices, {waves} wavefronts per block, order {order}, cut {cut}, mid {mid}")
+    run_waves(w, waves, label="dense", order=order, cut=cut, mid=mid)
 
 
 def test_capacity_overflow_with_block_waves():
@@ -146,22 +147,24 @@ def test_capacity_overflow_with_block_waves():
         assert st["rebuilt"] >= 1, st
 
 
-@pytest.mark.parametrize("policy,cut", [("rebuild", 0), ("threshold", 0), ("mlp", 0), ("mlp", 4), ("threshold", 4)])
-def test_block_waves_under_rebuilding_policies(policy, cut):
+@pytest.mark.parametrize("policy,cut,mid", [("rebuild", 0, 0), ("threshold", 0, 0), ("mlp", 0, 0), ("mlp", 4, 0),
+                                            ("threshold", 4, 0), ("mlp", 6, 3)])
+def test_block_waves_under_rebuilding_policies(policy, cut, mid):
     from paper_2308_06484_amd.kdt import MLP_PARAMS
     w = W.selector_mix(seed=4, steps=4, small=12, large=12)
     g = torch.Generator().manual_seed(9)
     wts = ((torch.rand(MLP_PARAMS, generator=g) - 0.5) * 0.5).to(DEV)
     kw = {"rebuild": {}, "threshold": {"tau": 50.0}, "mlp": {"mlp_w": wts}}[policy]
-    _say(f"selector_mix subset, 4 wavefronts per block, policy {policy}, cut {cut}")
-    run_waves(w, 4, policy=policy, label=policy, order=1 if cut else 0, cut=cut, **kw)
+    _say(f"selector_mix subset, 4 wavefronts per block, policy {policy}, cut {cut}, mid {mid}")
+    run_waves(w, 4, policy=policy, label=policy, order=1 if cut else 0, cut=cut, mid=mid, **kw)
 
 
 def test_block_waves_full_size_multi2048_every_step():
     """multi2048 at full size, 40 steps, 4 wavefronts per block for the
     blocks with at least 32 moves and one for the others, at once: a
     rotating subset of 128 blocks against the oracle after every step, all
-    blocks at the end."""
+    blocks at the end; then 40 steps with a two-wavefront middle class."""
     from tests.test_gpu_fullsize import rotating_parity
     w = W.multi2048(seed=1, steps=40)
     rotating_parity(w, 40, waves=4, order=1, cut=32, label="multi2048 4 waves, cut 32")
+    rotating_parity(w, 40, waves=4, order=1, cut=48, mid=16, seed=5, label="multi2048 4 waves, cut 48, mid 16")

@@ -187,17 +187,21 @@ def test_schedule_knobs_check_their_arguments():
     w = W.lattice256(seed=4, steps=2)
     dt = K.KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
     L = K.lib()
-    assert L.kdt_set_block_order(dt.ctx, 2, 0) == K.E_ARG
-    assert L.kdt_set_block_order(dt.ctx, 0, 5) == K.E_ARG  # classes need the order
-    assert L.kdt_set_block_order(dt.ctx, 1, -1) == K.E_ARG
+    assert L.kdt_set_block_order(dt.ctx, 2, 0, 0) == K.E_ARG
+    assert L.kdt_set_block_order(dt.ctx, 0, 5, 0) == K.E_ARG  # classes need the order
+    assert L.kdt_set_block_order(dt.ctx, 1, -1, 0) == K.E_ARG
+    assert L.kdt_set_block_order(dt.ctx, 1, 8, 8) == K.E_ARG  # the middle class lies below the heavy one
+    assert L.kdt_set_block_order(dt.ctx, 1, 0, 4) == K.E_ARG
+    assert L.kdt_set_block_order(dt.ctx, 1, 8, -1) == K.E_ARG
     assert L.kdt_set_prefetch(dt.ctx, 3) == K.E_ARG and L.kdt_set_prefetch(dt.ctx, -1) == K.E_ARG
-    assert L.kdt_set_block_order(dt.ctx, 1, 8) == K.OK and L.kdt_set_prefetch(dt.ctx, 0) == K.OK
-    assert L.kdt_set_block_order(None, 1, 0) == K.E_ARG and L.kdt_set_prefetch(None, 1) == K.E_ARG
+    assert L.kdt_set_block_order(dt.ctx, 1, 8, 0) == K.OK and L.kdt_set_prefetch(dt.ctx, 0) == K.OK
+    assert L.kdt_set_block_order(dt.ctx, 1, 8, 4) == K.OK
+    assert L.kdt_set_block_order(None, 1, 0, 0) == K.E_ARG and L.kdt_set_prefetch(None, 1) == K.E_ARG
     dt.close()
     from paper_2308_06484_amd.kdt import GlobalDT
     pts = np.unique(np.random.default_rng(3).integers(0, 1 << 12, size=(600, 2)), axis=0)[:512].astype(np.int32)
     G = GlobalDT(pts, [0, 0, 1 << 12, 1 << 12], 1, 16, device=DEV)
-    assert L.kdt_set_block_order(G.ctx, 1, 0) == K.E_STATE
+    assert L.kdt_set_block_order(G.ctx, 1, 0, 0) == K.E_STATE
     G.close()
 
 

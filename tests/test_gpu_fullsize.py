@@ -26,7 +26,7 @@ def _say(*a):
 
 
 def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0, label="", waves=1,
-                    repair=None, order=0, cut=0):
+                    repair=None, order=0, cut=0, mid=0):
     """Run w's first T steps one step per call; after every step compare the
     applied flags and a rotating subset of SUBSET blocks; at the end, all."""
     from paper_2308_06484_amd.kdt import KineticDT
@@ -37,7 +37,7 @@ def rotating_parity(w, T, mode="step", policy=None, tau=0.0, mlp_w=None, seed=0,
     if waves > 1:
         dt.set_block_waves(waves)
     if order or cut:
-        dt.set_block_order(order, cut)
+        dt.set_block_order(order, cut, mid)
     if repair:
         dt.set_repair(repair)
     ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
