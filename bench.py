@@ -137,18 +137,22 @@ def cpu_baseline(w, threads, budget_s=12.0, max_steps=16, blocks=None):
                 cpu_model=cpu_model())
 
 
-def time_form(w, steps, mode, graph, per_cu, dev):
+def time_form(w, steps, mode, graph, per_cu, dev, shape=None):
     """Seconds and applied moves of `steps` steps of w from its initial
-    state under one launch form (fresh context, own stream)."""
+    state under one launch form (fresh context, own stream; shape: an
+    autotuner candidate's other keys)."""
     import numpy as np
     import torch
 
+    from paper_2308_06484_amd import autotune as A
     from paper_2308_06484_amd.kdt import KineticDT
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         dt = KineticDT(w["xy"], w["pt_off"], w["frame"], device=dev)
         if per_cu:
             dt.set_launch(per_cu)
+        if shape:
+            A.apply_form(dt, shape)
         mv = torch.from_numpy(w["mv"]).to(dev)
         off = torch.from_numpy(np.ascontiguousarray(w["mv_off"][:steps])).to(dev)
         g = dt.graph(mv, off, mode=mode) if graph else None
@@ -215,20 +219,21 @@ def other_workload(args):
     else:
         w = W.uneven4096(seed=args.seed, steps=args.other_steps or 500)
     T = w["mv_off"].shape[0]
-    forms = [("per_step", "step", False, None), ("graph_per_step", "step", True, None),
-             ("persistent_lpt", "persistent", False, None), ("graph_persistent_lpt", "persistent", True, None),
-             ("fused", "fused", False, None)]
+    forms = [("per_step", "step", False, None, None), ("graph_per_step", "step", True, None, None),
+             ("persistent_lpt", "persistent", False, None, None),
+             ("graph_persistent_lpt", "persistent", True, None, None), ("fused", "fused", False, None, None)]
     res = {}
     if name == "uneven4096":
         cal = W.uneven4096(seed=100 + args.seed, steps=60)
         best = A.autotune(cal, steps=50, use_cache=False)
         log("autotuner: " + json.dumps({k: v for k, v in best.items() if k != "table"}))
-        forms.append(("autotuned", best["mode"], best["graph"], best.get("per_cu")))
+        shape = {k: best[k] for k in ("waves", "order", "cut", "mid", "prefetch") if k in best}
+        forms.append(("autotuned", best["mode"], best["graph"], best.get("per_cu"), shape))
         res["autotune_table"] = best["table"]
-    for fname, mode, graph, per_cu in forms:
-        secs, napp, st = time_form(w, T, mode, graph, per_cu, dev)
+    for fname, mode, graph, per_cu, shape in forms:
+        secs, napp, st = time_form(w, T, mode, graph, per_cu, dev, shape)
         res[fname] = {"moves_per_s": napp / secs, "ms_per_step": secs * 1e3 / T, "mode": mode,
-                      "graph": graph, "per_cu": per_cu, "errors": st["errors"]}
+                      "graph": graph, "per_cu": per_cu, "shape": shape, "errors": st["errors"]}
         log(f"{name} {fname}: {napp / secs:.3e} moves/s, {secs * 1e3 / T:.3f} ms/step")
     sizes = np.diff(w["pt_off"])
     print(json.dumps({"workload": name, "blocks": int(len(sizes)), "points": int(sizes.sum()),
