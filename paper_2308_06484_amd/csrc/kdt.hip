@@ -1285,9 +1285,16 @@ __global__ void k_g_classify(DevState s, GlobalDev g, const kdt_move_t* __restri
     }
 }
 
+// Plans (the global mode's rounds and the multi-wavefront rounds) use a
+// write-back table of PLAN_HT entries: a plan that needs more goes to the
+// sequential path, which has the full table; two thirds of a step
+// wavefront's LDS, so more planning wavefronts share a compute unit.
+constexpr int PLAN_HT = 128;
+using PlanWave = WaveLDST<PLAN_HT>;
+
 __global__ void __launch_bounds__(WAVE) k_g_plan(DevState s, GlobalDev g,
                                                  const kdt_move_t* __restrict__ mv, int M, int round) {
-    __shared__ WaveLDS S;
+    __shared__ PlanWave S;
     const int lane = lane_id();
     BlockView B = view_of(s, 0);
     if (round == 0) {  // the step's cell hash has been read: empty it for the next step
@@ -1570,8 +1577,8 @@ constexpr int MW_MAX_WAVES = 4;
 // two-wavefront workgroups, or a four-wavefront one beside two one-wavefront
 // step workgroups, share a compute unit.  A plan then reads at most
 // MW_RSMAX slots: its star, its table entries, its walk.
-constexpr int MW_HT = 128;
-using MwWave = WaveLDST<MW_HT>;
+constexpr int MW_HT = PLAN_HT;
+using MwWave = PlanWave;
 constexpr int MW_RSMAX = KMAX + MW_HT + WPMAX;
 // claim hash entries: every slot of one round's NW plans (a power of two)
 template <int NW>
@@ -2508,7 +2515,7 @@ struct kdt_ctx {
     int sticky;
     int device = 0;
     int cus = 256;
-    int wpc = 4;  // step workgroups (one wavefront each) that fit a compute unit's LDS
+    int wpc = 4;  // workgroups (one wavefront each) that fit a compute unit's LDS: step ones, or the global rounds' planning ones
     long long step_count = 0;  // time steps launched so far (log index)
     long long epoch = 0;       // changes of policy, log or launch shape (graphs record theirs)
     int persist_per_cu = 4;  // workgroups per compute unit of the persistent launch
@@ -2588,13 +2595,15 @@ void release_events(kdt_ctx* c) {
     c->ev_used = 0;
 }
 
-// Step workgroups per compute unit that the LDS holds (each takes a WaveLDS).
-int step_wg_per_cu(int dev) {
+// Workgroups per compute unit that the LDS holds, each taking `bytes`.
+int wg_per_cu(int dev, size_t bytes) {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || lds < 1)
         lds = 160 * 1024;
-    return std::max(1, lds / (int)sizeof(WaveLDS));
+    return std::max(1, lds / (int)bytes);
 }
+// Step workgroups per compute unit (each takes a WaveLDS).
+int step_wg_per_cu(int dev) { return wg_per_cu(dev, sizeof(WaveLDS)); }
 
 // Dynamic LDS for the block build: PB_LDS_BYTES if the device lets a
 // kernel have that much, else the default limit.
@@ -3839,7 +3848,7 @@ static int init_global(kdt_ctx** out, const int32_t* xy, int64_t n, int32_t dept
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
             c->cus = cus;
-        c->wpc = step_wg_per_cu(c->device);
+        c->wpc = wg_per_cu(c->device, sizeof(PlanWave));  // planning workgroups of the rounds
     }
     c->pt_off = {0, (long long)n};
     c->tri_off = {0, 2 * (long long)n - 2};
