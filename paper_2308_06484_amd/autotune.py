@@ -30,7 +30,7 @@ PER_STEP_CANDIDATES = (
     *({"mode": "step", "graph": g, "order": o} for o in (0, 1) for g in (False, True)),
     *({"mode": "step", "graph": g, "waves": 2, "order": 1} for g in (False, True)),
     *({"mode": "step", "graph": True, "waves": nw, "order": 0} for nw in (2, 4)),
-    {"mode": "step", "graph": True, "waves": 4, "order": 1},
+    *({"mode": "step", "graph": g, "waves": 4, "order": 1} for g in (False, True)),
     *({"mode": "step", "graph": True, "waves": 2, "order": 1, "cut": c} for c in (24, 40)),
     *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c} for c in (32, 40, 48)),
     *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c, "mid": m} for c, m in ((40, 16), (40, 24),

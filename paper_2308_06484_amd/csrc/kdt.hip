@@ -1572,20 +1572,21 @@ __global__ void __launch_bounds__(WAVE) k_g_serial(DevState s, GlobalDev g,
 // rule's, and DT* (unique) is the same triangulation.
 constexpr int MW_MAX_WAVES = 4;
 // The rounds' wavefronts plan with a write-back table of MW_HT entries (a
-// move that needs more goes to the rest list, whose sequential path has the
-// full table): half the LDS of a step wavefront's, so that three
-// two-wavefront workgroups, or a four-wavefront one beside two one-wavefront
-// step workgroups, share a compute unit.  A plan then reads at most
-// MW_RSMAX slots: its star, its table entries, its walk.
-constexpr int MW_HT = PLAN_HT;
-using MwWave = PlanWave;
+// move that needs more -- a long walk, a large cavity; the star-only moves
+// take a few dozen -- goes to the rest list, whose sequential path has the
+// full table): about half the LDS of a step wavefront's, so that four
+// two-wavefront workgroups, or two four-wavefront ones, share a compute
+// unit.  A plan then reads at most MW_RSMAX slots: its star, its table
+// entries, its walk.
+constexpr int MW_HT = 64;
+using MwWave = WaveLDST<MW_HT>;
 constexpr int MW_RSMAX = KMAX + MW_HT + WPMAX;
 // claim hash entries: every slot of one round's NW plans (a power of two)
 template <int NW>
 constexpr int mw_hash() { return NW * MW_RSMAX <= 512 ? 512 : (NW * MW_RSMAX <= 1024 ? 1024 : 2048); }
 static_assert(mw_hash<MW_MAX_WAVES>() >= MW_MAX_WAVES * MW_RSMAX && mw_hash<2>() >= 2 * MW_RSMAX,
               "claim hash smaller than the plans of one round");
-constexpr int MW_KMAX = 128;  // moves of a block's step the rounds take; a block with more runs in the rest launch
+constexpr int MW_KMAX = 64;  // moves of a block's step the rounds take; a block with more runs in the rest launch
 constexpr int MWS_PEND = 0, MWS_DONE = 1, MWS_REST = 2;
 constexpr int REST_ALL = -1;  // rest count of a block deferred whole
 
@@ -1626,9 +1627,8 @@ __device__ __forceinline__ int mw_read_slot(const MwWave& S, const MovePlan& pl,
 }
 
 static_assert(sizeof(MwLDS<4>) <= 160 * 1024, "four wavefronts' scratch exceeds a compute unit's LDS");
-static_assert(3 * sizeof(MwLDS<2>) <= 160 * 1024, "three two-wavefront workgroups no longer share a compute unit");
-static_assert(sizeof(MwLDS<4>) + 2 * sizeof(WaveLDS) <= 160 * 1024,
-              "a four-wavefront workgroup and two step workgroups no longer share a compute unit");
+static_assert(4 * sizeof(MwLDS<2>) <= 160 * 1024, "four two-wavefront workgroups no longer share a compute unit");
+static_assert(2 * sizeof(MwLDS<4>) <= 160 * 1024, "two four-wavefront workgroups no longer share a compute unit");
 
 template <int NW>
 __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_move_t* __restrict__ mv,
