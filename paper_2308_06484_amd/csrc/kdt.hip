@@ -1667,14 +1667,20 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     }
     const bool need_f = s.policy != KDT_POLICY_REPAIR || s.log;
     __syncthreads();
-    if (need_f && !M.defer_all && w == 0) {
-        float f[MLP_IN];
-        block_features(B.n, fr, mv, m0, h.m1, s.dlim, f);
-        const int br = choose_branch(s, f);
-        if (lane == 0) {
-            if (br != 0) M.defer_all = 1;  // the rebuild branch runs in k_step_rest
-            for (int i = 0; i < MLP_IN; ++i) M.f[i] = f[i];
+    // wavefront 0 chooses the branch while the others warm the caches with
+    // the movers' stars (a read-only hint, whatever the branch)
+    if (w == 0) {
+        if (need_f && !M.defer_all) {
+            float f[MLP_IN];
+            block_features(B.n, fr, mv, m0, h.m1, s.dlim, f);
+            const int br = choose_branch(s, f);
+            if (lane == 0) {
+                if (br != 0) M.defer_all = 1;  // the rebuild branch runs in k_step_rest
+                for (int i = 0; i < MLP_IN; ++i) M.f[i] = f[i];
+            }
         }
+    } else if (k > 1 && k <= MW_KMAX && s.prefetch) {
+        prefetch_stars(B, mv, m0 + (w - 1) * WAVE, h.m1, s.prefetch);
     }
     __syncthreads();
     const long long c0 = wall_clock64();
@@ -1718,7 +1724,6 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
             M.np = np;
         }
     }
-    if (!M.defer_all && k > 1 && s.prefetch) prefetch_stars(B, mv, m0 + w * WAVE, h.m1, s.prefetch);
     __syncthreads();
     // reservation rounds over the commuting moves
     while (!M.defer_all && M.np > 0 && M.fail == ST_OK) {
