@@ -104,9 +104,9 @@ def test_multi2048_full_size_every_step_all_policies():
     w = W.multi2048(seed=1, steps=100)
     rotating_parity(w, 100, label="multi2048 repair")
     rotating_parity(w, 100, policy="mlp", mlp_w=wts, seed=1, label="multi2048 mlp")
-    # the benchmark's launch shape: two wavefronts per block, most moves first
-    rotating_parity(w, 100, policy="mlp", mlp_w=wts, seed=4, waves=2, order=1,
-                    label="multi2048 mlp, 2 waves, ordered")
+    # the benchmark's launch shape: four wavefronts per block, most moves first
+    rotating_parity(w, 100, policy="mlp", mlp_w=wts, seed=4, waves=4, order=1,
+                    label="multi2048 mlp, 4 waves, ordered")
     st = rotating_parity(w, 100, policy="threshold", tau=tau_lo, seed=2, label="multi2048 threshold")
     assert st["rebuilt"] > 0
     st = rotating_parity(w, 10, policy="rebuild", seed=3, label="multi2048 rebuild")
