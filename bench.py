@@ -447,6 +447,7 @@ def grid_report(args):
         },
         "applied_moves": applied,
         "variants": variants,
+        "selector_taus": {"threshold_critical_path": tau, "threshold_summed": tau_sum, "dlimit": tau_d},
         "phase_us_per_move": phases,
         "move_time_hist": {f"<{(2 ** (i + 1)) / khz * 1e3:.2f}us": c
                            for i, c in enumerate([a - b for a, b in zip(s1["hist"], s0["hist"])]) if c},
@@ -556,10 +557,11 @@ def headline(args):
     X, Y, cal_step, cal_after = S.collect_steps(cal, CAL_STEPS, dev)
     mlp = torch.from_numpy(S.train(X, Y, epochs=200, batch=2048, lr=0.02, device=dev)).to(dev)
     tau = S.calibrate_threshold_cp(X, Y, cal_step, cal_after)  # on the step's critical path
+    tau_d = S.calibrate_threshold_cp(X, Y, cal_step, cal_after, feature=15)  # the d-limit rule's
     tau_sum = S.calibrate_threshold(X, Y)           # on summed block costs, for comparison
     log(f"selector trained on {len(X)} block-steps of seed {100 + args.seed} "
-        f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.2f} on the critical path, "
-        f"{tau_sum:.2f} on summed costs")
+        f"({time.perf_counter() - t0:.1f} s); threshold tau = {tau:.3g} on the critical path, "
+        f"{tau_sum:.3g} on summed costs; d-limit tau = {tau_d:.3g} (3e+38: never rebuild)")
     pol_mlp = ("mlp", 0.0, mlp)
     if args.form:  # a fixed launch form (profiling runs): a candidate's name
         forms = {form_name(f): f for f in headline_forms()}
@@ -603,7 +605,8 @@ def headline(args):
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),
                  (form_name(form) + "_threshold_summed_tau", form, ("threshold", tau_sum, None), K),
-                 (form_name(form) + "_dlimit", form, ("dlimit", 1.0, None), K),
+                 (form_name(form) + "_dlimit", form, ("dlimit", tau_d, None), K),
+                 (form_name(form) + "_dlimit_tau1", form, ("dlimit", 1.0, None), K),
                 (form_name(dict(form, repair="flip")) + "_mlp", dict(form, repair="flip"), pol_mlp, K),
                  ("per_step_rebuild_only", {"mode": "step", "graph": False}, ("rebuild", 0.0, None), min(10, K))]
         for name, f, pol, steps in runs:
@@ -676,6 +679,7 @@ def headline(args):
         "blocked_moves": blocked,
         "rebuilt_block_steps": rebuilt,
         "variants": variants,
+        "selector_taus": {"threshold_critical_path": tau, "threshold_summed": tau_sum, "dlimit": tau_d},
         "autotune_ms_per_step": autotune_table,
         "d_calculation": dcal,
         "phase_us_per_move": phases,

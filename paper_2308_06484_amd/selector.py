@@ -137,16 +137,22 @@ def step_time(cost, step, after=None):
     return float(during.sum() + later.sum())
 
 
-def calibrate_threshold_cp(X, Y, step, after=None, candidates=256):
-    """tau for "rebuild iff sum d/s > tau" that minimises the step time of
+NEVER = 3.0e38  # a threshold no feature value exceeds: the rule never rebuilds
+
+
+def calibrate_threshold_cp(X, Y, step, after=None, candidates=256, feature=3):
+    """tau for "rebuild iff feature > tau" (feature 3: sum d/s, the threshold
+    rule; 15: max d / d, the d-limit rule) that minimises the step time of
     step_time -- the critical path -- on the samples (candidates: quantiles
     of the observed values, rebuild everything, rebuild nothing).  A choice
     that makes one block of a step slower costs the whole step; per-block
     sums would not see it.  after: per sample, whether its rebuild would run
     after the step's kernel (None: none would).  Of equally good candidates
     the largest is kept: on unseen blocks it rebuilds least, and a needless
-    rebuild costs far more than a missed one."""
-    f = X[:, 3].astype(np.float64)
+    rebuild costs far more than a missed one; when rebuilding no sample is
+    best, no rebuild paid on the samples and the rule never rebuilds
+    (NEVER), rather than rebuilding the first unseen larger value."""
+    f = X[:, feature].astype(np.float64)
     cr, cb = np.exp2(Y[:, 0].astype(np.float64)), np.exp2(Y[:, 1].astype(np.float64))
     late = np.zeros(len(f), dtype=bool) if after is None else np.asarray(after, dtype=bool)
     cand = np.unique(np.concatenate([np.quantile(f, np.linspace(0, 1, candidates)), [f.min() - 1.0, f.max() + 1.0]]))
@@ -156,7 +162,7 @@ def calibrate_threshold_cp(X, Y, step, after=None, candidates=256):
         t = step_time(np.where(rb, cb, cr), step, rb & late)
         if t < best:
             best, best_tau = t, float(tau)
-    return best_tau
+    return NEVER if best_tau >= f.max() else best_tau
 
 
 def calibrate_threshold(X, Y):

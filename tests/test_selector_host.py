@@ -57,3 +57,16 @@ def test_ties_keep_the_largest_threshold():
     step = np.array([0, 0, 1])
     tau = S.calibrate_threshold_cp(X, Y, step, np.ones(3, bool))
     assert tau > 17.25
+    # no rebuild paid on the samples: the rule never rebuilds
+    assert tau == S.NEVER and not (np.float32(1e30) > np.float32(tau))
+
+
+def test_dlimit_feature_calibrates_on_its_own_column():
+    X = np.zeros((4, 16), np.float32)
+    X[:, 3] = [1.0, 1.0, 1.0, 1.0]
+    X[:, 15] = [0.5, 0.7, 3.0, 4.0]
+    # the two blocks that move farthest relative to d are cheaper rebuilt
+    Y = np.log2(np.array([[10.0, 50.0], [10.0, 50.0], [400.0, 20.0], [400.0, 20.0]])).astype(np.float32)
+    step = np.array([0, 1, 2, 3])
+    tau = S.calibrate_threshold_cp(X, Y, step, feature=15)
+    assert 0.7 <= tau < 3.0
