@@ -1610,7 +1610,7 @@ struct MwLDS {
     int2 cs[MW_KMAX], ct[MW_KMAX];  // source and target cells (ct.x < 0: target outside the frame)
     int pt[MW_KMAX];             // moved point
     int outcome[NW];
-    int np, defer_all, fail, nrest;
+    int np, head, defer_all, fail, nrest;  // pending moves: list[head .. np)
     float f[MLP_IN];
 };
 
@@ -1660,6 +1660,8 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     if (tid == 0) {
         M.defer_all = k > MW_KMAX ? 1 : 0;
         M.fail = ST_OK;
+        M.np = 0;
+        M.head = 0;
     }
     for (int i = tid; i < HS; i += NT) {
         M.hkey[i] = -1;
@@ -1717,18 +1719,19 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
             if (again) M.defer_all = 1;
         }
         __syncthreads();
-        if (tid == 0) {
-            int np = 0;
-            for (int i = 0; i < k; ++i)
-                if (M.mstate[i] == MWS_PEND) M.list[np++] = i;
-            M.np = np;
+        if (w == 0) {  // the pending moves in list order (k <= MW_KMAX = one wavefront)
+            static_assert(MW_KMAX <= WAVE, "the pending list is compacted by one ballot");
+            const bool pend = lane < k && M.mstate[lane] == MWS_PEND;
+            const uint64_t pm = ballot(pend);
+            if (pend) M.list[lanes_below(pm)] = lane;
+            if (lane == 0) M.np = __popcll(pm);
         }
     }
     __syncthreads();
     // reservation rounds over the commuting moves
-    while (!M.defer_all && M.np > 0 && M.fail == ST_OK) {
-        const int np = M.np;
-        const int i = w < np ? M.list[w] : -1;  // offset of this wavefront's move
+    while (!M.defer_all && M.np > M.head && M.fail == ST_OK) {
+        const int head = M.head, np = M.np;
+        const int i = w < np - head ? M.list[head + w] : -1;  // offset of this wavefront's move
         MovePlan pl{};
         int app = 0, rc = ST_OK, total = 0;
         if (i >= 0) {
@@ -1809,12 +1812,16 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
         if (lane == 0) M.outcome[w] = i >= 0 ? outc : 2;
         __syncthreads();  // commits done, outcomes known
         if (tid == 0) {
-            int n = 0;
-            for (int j = 0; j < np; ++j) {
-                const int mi = M.list[j];
-                const int o = j < NW ? M.outcome[j] : 2;
+            // the round took list[head .. head + nt); the plans that lost go
+            // back just before the moves no wavefront took (list order kept)
+            const int nt = min(NW, np - head);
+            int keep[NW];
+            int nk = 0;
+            for (int j = 0; j < nt; ++j) {
+                const int mi = M.list[head + j];
+                const int o = M.outcome[j];
                 if (o == 2) {
-                    M.list[n++] = mi;
+                    keep[nk++] = mi;
                 } else if (o == 3) {
                     M.mstate[mi] = MWS_REST;
                 } else if (o < 0) {
@@ -1823,7 +1830,9 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
                     M.mstate[mi] = MWS_DONE;
                 }
             }
-            M.np = n;
+            const int nh = head + nt - nk;
+            for (int j = 0; j < nk; ++j) M.list[nh + j] = keep[j];
+            M.head = nh;
         }
         __syncthreads();
     }
@@ -3313,16 +3322,22 @@ int kdt_set_block_order(kdt_ctx* c, int32_t order, int32_t heavy_cut, int32_t mi
         (mid_cut > 0 && (heavy_cut == 0 || mid_cut >= heavy_cut)))
         return KDT_E_ARG;
     if (c->global) return KDT_E_STATE;
-    if (heavy_cut > 0 && !c->side) {
-        if (check_hip(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) ||
-            check_hip(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) ||
-            check_hip(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)))
-            return KDT_E_DEVICE;
-    }
-    if (mid_cut > 0 && !c->side2) {
-        if (check_hip(c, hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking)) ||
-            check_hip(c, hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming)))
-            return KDT_E_DEVICE;
+    // the class streams and events belong to the context's device
+    int cur = 0;
+    if ((heavy_cut > 0 && !c->side) || (mid_cut > 0 && !c->side2)) {
+        if (check_hip(c, hipGetDevice(&cur)) || check_hip(c, hipSetDevice(c->device))) return KDT_E_DEVICE;
+        int rc = KDT_OK;
+        if (heavy_cut > 0 && !c->side &&
+            (check_hip(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) ||
+             check_hip(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) ||
+             check_hip(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming))))
+            rc = KDT_E_DEVICE;
+        if (rc == KDT_OK && mid_cut > 0 && !c->side2 &&
+            (check_hip(c, hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking)) ||
+             check_hip(c, hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming))))
+            rc = KDT_E_DEVICE;
+        if (check_hip(c, hipSetDevice(cur))) rc = KDT_E_DEVICE;
+        if (rc != KDT_OK) return rc;
     }
     c->block_order = order;
     c->heavy_cut = heavy_cut;
