@@ -243,9 +243,12 @@ int kdt_set_prefetch(kdt_ctx* ctx, int32_t depth);
  * writing, claims every triangle its plan read, and the plans whose claims
  * no lower move index contests are written; the others plan again -- and
  * the remaining moves (sharing a cell with another, beyond the rounds'
- * capacities, or of a block taking the rebuild branch, or all of a block
- * whose step moves some point more than once) follow one after another in
- * list order, in a second launch.  Same triangulations and
+ * capacities -- a plan keeps at most 50 records in its wavefront's table,
+ * a quarter of the sequential path's, so that more workgroups share a
+ * compute unit -- or of a block taking the rebuild branch, or all of a
+ * block with more than 64 moves in the step or whose step moves some point
+ * more than once) follow one after another in list order, in a second
+ * launch.  Same triangulations and
  * applied flags as one wavefront.  The per-step log then records, for a
  * block, the rounds' ticks; the rest launch logs blocks all of whose moves
  * it ran.  KDT_E_ARG for another count, KDT_E_STATE in global mode. */

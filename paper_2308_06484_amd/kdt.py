@@ -30,7 +30,8 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_set_policy", "kdt_set_log", "kdt_mlp_forward", "kdt_mlp_grad", "kdt_mlp_train",
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
-           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair", "kdt_set_prefetch", "kdt_set_block_order",
+           "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair",
+           "kdt_set_prefetch", "kdt_set_block_order",
            "kdt_workspace_size_global_qt", "kdt_init_global_qt", "kdt_quadtree", "kdt_repartition",
            "kdt_set_repartition")
 REPAIR = {"delins": 0, "flip": 1}
@@ -100,6 +101,8 @@ def _lib():
         L.kdt_set_launch.argtypes = [vp, i32]
         L.kdt_set_block_waves.argtypes = [vp, i32]
         L.kdt_set_repair.argtypes = [vp, i32]
+        L.kdt_set_prefetch.argtypes = [vp, i32]
+        L.kdt_set_block_order.argtypes = [vp, i32, i32, i32]
         L.kdt_workspace_size_global_qt.argtypes = [vp, i64, vp, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
         L.kdt_init_global_qt.argtypes = [ctypes.POINTER(vp), vp, i64, vp, i64, i32, vp, ctypes.c_size_t, vp]
         L.kdt_quadtree.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
