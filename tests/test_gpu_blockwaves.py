@@ -168,3 +168,55 @@ def test_block_waves_full_size_multi2048_every_step():
     w = W.multi2048(seed=1, steps=40)
     rotating_parity(w, 40, waves=4, order=1, cut=32, label="multi2048 4 waves, cut 32")
     rotating_parity(w, 40, waves=4, order=1, cut=48, mid=16, seed=5, label="multi2048 4 waves, cut 48, mid 16")
+
+
+@pytest.mark.parametrize("waves,cut", [(4, 0), (4, 6), (2, 0)])
+def test_empty_steps_and_a_failed_block_under_the_schedules(waves, cut):
+    """Steps in which no block moves, or only one does, pass through the
+    ordered and split launches unchanged; a move with an out-of-range point
+    fails its block (KDT_E_ARG) and every other block still matches the
+    oracle after every later step."""
+    K = __import__("paper_2308_06484_amd.kdt", fromlist=["KineticDT"])
+    w = W.multi2048(seed=13, steps=6, blocks=16, per_block=512, side=2048, dcap=512)
+    mv = w["mv"].copy()
+    off = w["mv_off"].copy()
+    B = len(w["pt_off"]) - 1
+    # step 1: no moves at all; step 2: only block 5 moves
+    base = int(off[1, 0])
+    off[1, :] = base
+    keep = off[2, 6] - off[2, 5]
+    off[2, :6] = off[2, 5]
+    off[2, 6:] = off[2, 5] + keep
+    # step 4: block 9's first move names a point outside the block
+    bad_b = 9
+    mv[int(off[4, bad_b]), 0] = 10 ** 6
+    # the oracle skips the failed block from step 4 on: compare the others
+    ref = Kinetic(w["xy"], w["pt_off"], w["frame"])
+    dt = K.KineticDT(w["xy"], w["pt_off"], w["frame"], device=DEV)
+    dt.set_block_waves(waves)
+    dt.set_block_order(1, cut, 0)
+    mvt = torch.from_numpy(mv).to(DEV)
+    offt = torch.from_numpy(np.ascontiguousarray(off)).to(DEV)
+    others = np.array([b for b in range(B) if b != bad_b], np.int32)
+    for t in range(4):  # every block, every step, until the failure
+        dt.run(mvt, offt[t:t + 1].contiguous())
+        ref.apply_step(mv, off[t])
+        tris, _, bo = dt.query_blocks(np.arange(B, dtype=np.int32))
+        for b in range(B):
+            assert np.array_equal(tris[bo[b]:bo[b + 1]], ref.block_dt(b)), (waves, cut, t, b)
+    # steps 4 and 5 in one call: the failure of step 4 is read afterwards
+    dt.run(mvt, offt[4:6].contiguous())
+    for t in (4, 5):  # the oracle without the failed block's moves
+        lo, hi = int(off[t, bad_b]), int(off[t, bad_b + 1])
+        mv_ref = np.delete(mv, np.arange(lo, hi), axis=0)
+        row = off[t].copy()
+        row[bad_b + 1:] -= hi - lo
+        ref.apply_step(mv_ref, row)
+    with pytest.raises(K.KDTError):
+        dt.sync()
+    tris, _, bo = dt.query_blocks(others)
+    for i, b in enumerate(others):
+        assert np.array_equal(tris[bo[i]:bo[i + 1]], ref.block_dt(b)), (waves, cut, b)
+    st = dt.block_status()
+    assert st[bad_b] == K.E_ARG and np.count_nonzero(st) == 1
+    dt.close()
