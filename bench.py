@@ -600,7 +600,19 @@ def headline(args):
 
     variants = {}
     if not args.no_variants:
-        runs = [(form_name(f) + "_mlp", f, pol_mlp, K) for f in headline_forms() if f != form]
+        # the other launch forms the schedule is built from, one per idea (the
+        # autotuner's table above times every candidate on the calibration
+        # workload)
+        shown = [{"mode": "step", "graph": False}, {"mode": "step", "graph": False, "order": 1},
+                 {"mode": "step", "graph": False, "waves": 2, "order": 1},
+                 {"mode": "step", "graph": True, "waves": 4, "order": 0},
+                 {"mode": "step", "graph": False, "waves": 4, "order": 1},
+                 {"mode": "step", "graph": True, "waves": 4, "order": 1},
+                 {"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": 32},
+                 {"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": 40, "mid": 16},
+                 {"mode": "step", "graph": True, "waves": 4, "order": 1, "prefetch": 0},
+                 {"mode": "persistent", "graph": False, "per_cu": 8}, {"mode": "fused", "graph": False}]
+        runs = [(form_name(f) + "_mlp", f, pol_mlp, K) for f in shown if f != form]
         runs += [(form_name(form) + "_repair_only", form, ("repair", 0.0, None), K),
                  ("per_step_repair_only", {"mode": "step", "graph": False}, ("repair", 0.0, None), K),
                  (form_name(form) + "_threshold", form, ("threshold", tau, None), K),

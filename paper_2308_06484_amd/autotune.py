@@ -35,7 +35,7 @@ PER_STEP_CANDIDATES = (
     *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c} for c in (32, 40, 48)),
     *({"mode": "step", "graph": True, "waves": 4, "order": 1, "cut": c, "mid": m} for c, m in ((40, 16), (40, 24),
                                                                                               (48, 16), (48, 24))),
-    *({"mode": "step", "graph": True, "waves": 2, "order": 1, "prefetch": d} for d in (0, 2)),
+    *({"mode": "step", "graph": True, "waves": w, "order": 1, "prefetch": d} for w in (2, 4) for d in (0, 2)),
 )
 DEFAULT_CANDIDATES = (
     *PER_STEP_CANDIDATES,
