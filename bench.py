@@ -447,7 +447,6 @@ def grid_report(args):
         },
         "applied_moves": applied,
         "variants": variants,
-        "selector_taus": {"threshold_critical_path": tau, "threshold_summed": tau_sum, "dlimit": tau_d},
         "phase_us_per_move": phases,
         "move_time_hist": {f"<{(2 ** (i + 1)) / khz * 1e3:.2f}us": c
                            for i, c in enumerate([a - b for a, b in zip(s1["hist"], s0["hist"])]) if c},
