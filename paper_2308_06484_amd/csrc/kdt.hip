@@ -64,6 +64,9 @@ struct DevState {
     int pad_;
     BlockStats* stats;
     float* log;  // per step and block: LOG_FIELDS floats, or null
+    // the branch of every block for this step chosen before the step kernels
+    // (k_choose; its features logged there), or null: chosen by the block
+    const int8_t* choice;
 };
 static_assert(offsetof(DevState, step_lds) < 64 && offsetof(DevState, stats) >= 128, "move fields off their lines");
 
@@ -721,14 +724,15 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     if (lane < NF) reinterpret_cast<long long*>(&S.st)[lane] = 0;
     wsync();
     const int k = m1 - m0;
-    const bool need_f = k > 0 && (s.policy != KDT_POLICY_REPAIR || s.log);
+    const bool pre = s.choice != nullptr && k > 0;  // chosen (and its features logged) by k_choose
+    const bool need_f = k > 0 && !pre && (s.policy != KDT_POLICY_REPAIR || s.log);
     float f[MLP_IN];
-    int branch = 0;
+    int branch = pre ? s.choice[b] : 0;
     if (need_f) {
         block_features(B.n, fr, mv, m0, m1, s.dlim, f);
         branch = choose_branch(s, f);
-        if (k > DRYMAX) branch = 0;  // more moves than the dry run holds: repair
     }
+    if (k > DRYMAX) branch = 0;  // more moves than the dry run holds: repair
     const long long c0 = wall_clock64();
     int rc = ST_OK;
     if (branch == 0) {
@@ -761,7 +765,7 @@ __device__ __forceinline__ int run_block_moves(const DevState& s, WaveLDS& S, in
     // (persistent launch) must find it empty
     if (rc != ST_OK) table_clear(S);
     wsync();
-    if (need_f && s.log && s.log_cap > 0 && lane < LOG_FIELDS) {
+    if ((need_f || pre) && s.log && s.log_cap > 0 && lane < LOG_FIELDS && !(pre && lane < MLP_IN)) {
         const long long nb = (long long)(s.n_blocks);
         float* rec = s.log + ((step % s.log_cap) * nb + b) * LOG_FIELDS;
         float v = 0.f;
@@ -848,6 +852,29 @@ __device__ __forceinline__ int pick_block(int B, const int* __restrict__ order, 
     const int hi = part == PART_HEAVY ? order[B] : (part == PART_MID ? order[B + 1] : B);
     const int r = lo + g;
     return r < hi ? order[r] : -1;
+}
+
+// The branch of every block with moves in this step, before the step
+// kernels (one wavefront per block, all blocks at once): the policy's
+// features and choice off the step's critical path, the features logged
+// here.  A failed block, or one without moves, repairs (nothing to do).
+__global__ void __launch_bounds__(WAVE) k_choose(DevState s, const kdt_move_t* __restrict__ mv,
+                                                 const int* __restrict__ off, long long step, int8_t* choice) {
+    const int b = blockIdx.x;
+    const int lane = lane_id();
+    const int m0 = off[b], m1 = off[b + 1];
+    int branch = 0;
+    if (m1 > m0 && s.status[b] == 0) {
+        float f[MLP_IN];
+        block_features((int)(s.pt_off[b + 1] - s.pt_off[b]), s.frame[b], mv, m0, m1, s.dlim, f);
+        branch = choose_branch(s, f);
+        if (s.log && s.log_cap > 0 && lane < MLP_IN) {
+            float v = 0.f;
+            for (int i = 0; i < MLP_IN; ++i) v = lane == i ? f[i] : v;
+            s.log[((step % s.log_cap) * (long long)s.n_blocks + b) * LOG_FIELDS + lane] = v;
+        }
+    }
+    if (lane == 0) choice[b] = (int8_t)branch;
 }
 
 __global__ void __launch_bounds__(WAVE) k_step(DevState s, const kdt_move_t* __restrict__ mv,
@@ -1667,12 +1694,15 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
         M.hkey[i] = -1;
         M.hprio[i] = 0x7fffffff;
     }
-    const bool need_f = s.policy != KDT_POLICY_REPAIR || s.log;
+    const bool pre = s.choice != nullptr;  // chosen (and its features logged) by k_choose
+    const bool need_f = !pre && (s.policy != KDT_POLICY_REPAIR || s.log);
     __syncthreads();
     // wavefront 0 chooses the branch while the others warm the caches with
     // the movers' stars (a read-only hint, whatever the branch)
     if (w == 0) {
-        if (need_f && !M.defer_all) {
+        if (pre) {
+            if (lane == 0 && k > 0 && s.choice[b] != 0) M.defer_all = 1;  // the rebuild branch runs in k_step_rest
+        } else if (need_f && !M.defer_all) {
             float f[MLP_IN];
             block_features(B.n, fr, mv, m0, h.m1, s.dlim, f);
             const int br = choose_branch(s, f);
@@ -1868,7 +1898,8 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
     if (M.fail != ST_OK && tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&s.stats[b].errors), 1ull);
     // the log: features, branch (repair) and the rounds' ticks; a block whose
     // moves all went to the rest list is logged by k_step_rest
-    if (need_f && s.log && s.log_cap > 0 && !M.defer_all && k > 0 && tid < LOG_FIELDS) {
+    if ((need_f || pre) && s.log && s.log_cap > 0 && !M.defer_all && k > 0 && tid < LOG_FIELDS &&
+        !(pre && tid < MLP_IN)) {
         float* rec = s.log + ((step % s.log_cap) * (long long)s.n_blocks + b) * LOG_FIELDS;
         float v = 0.f;
         if (tid < MLP_IN) v = M.f[tid];
@@ -2318,7 +2349,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Layout {
     size_t tri, xy, vtri, order, pt_off, tri_off, frame, status, stats, qmap, own2, rb_flag, qcount, qoff,
         qtris, qadj, qlist, stage_mv, stage_off, stage_app, sticky, lpt, sorder, rest_mv, rest_idx, rest_app,
-        rest_cnt, dc_mind2, dc_diam2, dc_g, total;
+        rest_cnt, dc_mind2, dc_diam2, dc_g, choice, total;
 };
 
 Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
@@ -2338,6 +2369,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.qmap = take(sizeof(int) * ntri);
     L.own2 = take(sizeof(int) * ntri);
     L.rb_flag = take(sizeof(int) * (B + 2));
+    L.choice = take((size_t)B);
     L.qcount = take(sizeof(int) * B);
     L.qoff = take(sizeof(long long) * (B + 1));
     L.qtris = take(sizeof(int) * 3 * ntri);
@@ -3224,6 +3256,14 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             k_step_persist<<<grid, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, (const int*)(w + c->L.lpt),
                                                                        c->B, applied, c->step_count);
         } else {
+            // a rebuilding policy: every block's branch chosen first, by all
+            // blocks at once, so the step kernels only read it
+            DevState dv = c->dev;
+            if (c->dev.policy != KDT_POLICY_REPAIR) {
+                int8_t* ch = (int8_t*)(w + c->L.choice);
+                k_choose<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, c->step_count, ch);
+                dv.choice = ch;
+            }
             // the step's order (most moves first) and, for the split launch,
             // its heavy class: the blocks with at least heavy_cut moves
             int* ord = nullptr;
@@ -3244,15 +3284,15 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             }
             if (c->block_waves == 4)
                 k_step_mw<4><<<c->B, 4 * WAVE, sizeof(MwLDS<4>), mws>>>(
-                    c->dev, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
+                    dv, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
             else if (c->block_waves == 2)
                 k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), mws>>>(
-                    c->dev, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
+                    dv, moves, off, applied, c->step_count, c->rest, ord, split ? PART_HEAVY : PART_ALL);
             if (mid)
-                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), c->side2>>>(c->dev, moves, off, applied,
+                k_step_mw<2><<<c->B, 2 * WAVE, sizeof(MwLDS<2>), c->side2>>>(dv, moves, off, applied,
                                                                             c->step_count, c->rest, ord, PART_MID);
             if (c->block_waves == 1 || split)
-                k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, applied, c->step_count, ord,
+                k_step<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(dv, moves, off, applied, c->step_count, ord,
                                                                    split ? PART_LIGHT : PART_ALL);
             if (split && (check_hip(c, hipEventRecord(c->join_ev, c->side)) ||
                           check_hip(c, hipStreamWaitEvent(c->stream, c->join_ev, 0))))
@@ -3261,7 +3301,7 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
                         check_hip(c, hipStreamWaitEvent(c->stream, c->join2_ev, 0))))
                 return KDT_E_DEVICE;
             if (c->block_waves > 1)
-                k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(c->dev, moves, off, c->rest, applied,
+                k_step_rest<<<c->B, WAVE, c->dev.step_lds, c->stream>>>(dv, moves, off, c->rest, applied,
                                                                         c->step_count);
         }
         if (c->dev.policy != KDT_POLICY_REPAIR && c->follow)  // blocks the rebuild branch listed
