@@ -854,14 +854,22 @@ __device__ __forceinline__ int pick_block(int B, const int* __restrict__ order, 
     return r < hi ? order[r] : -1;
 }
 
-// The branch of every block with moves in this step, before the step
-// kernels (one wavefront per block, all blocks at once): the policy's
-// features and choice off the step's critical path, the features logged
-// here.  A failed block, or one without moves, repairs (nothing to do).
+// The branch of every block with moves, before the step kernels, for the
+// steps blockIdx.y of a chunk starting at step `step` (one wavefront per
+// block and step, all at once): the features read only the block's size,
+// frame and the step's move distances, so the choices of several steps can
+// be taken ahead, off the steps' critical path.  With a log, the chunk is
+// one step and the features are logged here.  A failed block, or one
+// without moves, repairs (nothing to do).
+constexpr int CHOOSE_STEPS = 64;  // steps whose choices one launch takes
 __global__ void __launch_bounds__(WAVE) k_choose(DevState s, const kdt_move_t* __restrict__ mv,
-                                                 const int* __restrict__ off, long long step, int8_t* choice) {
+                                                 const int* __restrict__ step_off, long long step,
+                                                 int8_t* choice) {
     const int b = blockIdx.x;
     const int lane = lane_id();
+    const int* off = step_off + (long long)blockIdx.y * (s.n_blocks + 1);
+    choice += (long long)blockIdx.y * s.n_blocks;
+    step += blockIdx.y;
     const int m0 = off[b], m1 = off[b + 1];
     int branch = 0;
     if (m1 > m0 && s.status[b] == 0) {
@@ -2369,7 +2377,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.qmap = take(sizeof(int) * ntri);
     L.own2 = take(sizeof(int) * ntri);
     L.rb_flag = take(sizeof(int) * (B + 2));
-    L.choice = take((size_t)B);
+    L.choice = take((size_t)B * CHOOSE_STEPS);
     L.qcount = take(sizeof(int) * B);
     L.qoff = take(sizeof(long long) * (B + 1));
     L.qtris = take(sizeof(int) * 3 * ntri);
@@ -3260,9 +3268,14 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             // blocks at once, so the step kernels only read it
             DevState dv = c->dev;
             if (c->dev.policy != KDT_POLICY_REPAIR) {
+                // a chunk of steps at a time (one step when logging: the log
+                // ring may hold fewer steps than a chunk)
+                const int chunk = c->dev.log ? 1 : CHOOSE_STEPS;
                 int8_t* ch = (int8_t*)(w + c->L.choice);
-                k_choose<<<c->B, WAVE, 0, c->stream>>>(c->dev, moves, off, c->step_count, ch);
-                dv.choice = ch;
+                if (t % chunk == 0)
+                    k_choose<<<dim3(c->B, std::min(chunk, n_steps - t)), WAVE, 0, c->stream>>>(
+                        c->dev, moves, off, c->step_count, ch);
+                dv.choice = ch + (long long)(t % chunk) * c->B;
             }
             // the step's order (most moves first) and, for the split launch,
             // its heavy class: the blocks with at least heavy_cut moves
