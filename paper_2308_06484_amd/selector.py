@@ -4,17 +4,18 @@ The paper weighs updating the triangulation against rebuilding it when
 points move far (Sec. I, abstract).  Here that choice is made per block and
 time step by a small network (16 -> 32 -> 32 -> 2) that predicts the log2
 device-clock cost of each branch from the block's features; a threshold on
-the summed move distance (in units of the block's point spacing) is the
-fallback.  Every block of a step runs at once, so a step lasts as long as
-its slowest block: choosing the cheaper branch for every block also
-minimises each step's slowest block, so the network predicts per-block
-costs, while the threshold is calibrated and the choices are judged on
-that critical path (the sum over steps of the slowest block's cost, plus the
-slowest rebuild too large for the step's kernel, which runs after it).  Features, costs and branch choices are produced by the library's
-kernels (the per-step log), and the network is trained by the library's own
-forward/backward/SGD kernels; this module only arranges the runs, the
-feature normalisation (folded into the first layer afterwards) and the
-bookkeeping of the regret.
+the summed move distance (in units of the block's point spacing), or on the
+longest move against d of the d-calculation, is the fallback.  Every block of
+a step runs at once, so a step lasts as long as its slowest block: choosing
+the cheaper branch for every block also minimises each step's slowest block,
+so the network predicts per-block costs, while the thresholds are calibrated
+and the choices are judged on that critical path (the sum over steps of the
+slowest block's cost, plus the slowest rebuild too large for the step's
+kernel, which runs after it).  Features, costs and branch choices are
+produced by the library's kernels (the per-step log), and the network is
+trained by the library's own forward/backward/SGD kernels; this module only
+arranges the runs, the feature normalisation (folded into the first layer
+afterwards) and the bookkeeping of the regret.
 """
 from __future__ import annotations
 
