@@ -284,16 +284,33 @@ def global_report(args):
             G.rebuild()
             rb.append(time.perf_counter() - t0)
         G.close()
+        # the same timed steps replayed from a HIP graph on a fresh context
+        G = GlobalDT(w["xy"], [0, 0, w["side"], w["side"]], w["depth"], 1 << w["depth"], device=dev,
+                     stream=stream)
+        G.run(mv, w["step_off"][:warm + 1])
+        g = G.graph(mv, w["step_off"][warm:])
+        stream.synchronize()
+        sg0 = G.stats()
+        e0.record(stream)
+        g.launch()
+        e1.record(stream)
+        stream.synchronize()
+        secs_g = e0.elapsed_time(e1) / 1e3
+        applied_g = G.stats()["applied"] - sg0["applied"]
+        g.close()
+        G.close()
     moves_per_step = int(w["step_off"][1] - w["step_off"][0])
     out = {"workload": "global4m: one DT* of 4,194,304 uniform points on [0,65536)^2, 4096 kd cells "
                        "(median splits), one move per cell per step of 1..16 units",
            "steps_timed": timed, "warmup": warm, "moves_per_s": applied / secs,
            "ms_per_step": secs * 1e3 / timed, "applied": int(applied),
+           "graph_moves_per_s": applied_g / secs_g, "graph_ms_per_step": secs_g * 1e3 / timed,
            "blocked": int(st["blocked"] - st0["blocked"]), "init_build_s": init_s,
            "full_rebuild_s": min(rb), "full_rebuild_moves_per_s": moves_per_step / min(rb),
            "speedup_vs_rebuild_per_step": (applied / secs) / (moves_per_step / min(rb)),
            "global_counters": gs}
-    log(f"global4m: {applied / secs:.3e} moves/s ({secs * 1e3 / timed:.3f} ms/step); full rebuild "
+    log(f"global4m: {applied / secs:.3e} moves/s ({secs * 1e3 / timed:.3f} ms/step), from a graph "
+        f"{applied_g / secs_g:.3e} ({secs_g * 1e3 / timed:.3f} ms/step); full rebuild "
         f"{min(rb) * 1e3:.1f} ms; init {init_s:.2f} s; counters {gs}")
     print(json.dumps(out), flush=True)
 

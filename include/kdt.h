@@ -536,6 +536,17 @@ int kdt_set_repartition(kdt_ctx* ctx, int32_t every_step);
 int kdt_run_global(kdt_ctx* ctx, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
                    int8_t* applied);
 
+/* The same n_steps global steps captured once as a HIP graph (replayed by
+ * kdt_graph_launch, released by kdt_graph_destroy, as for kdt_graph_build):
+ * the step's nine launches without the host between them.  Arguments as for
+ * kdt_run_global; the move stream's pointers and step sizes are recorded.
+ * KDT_E_STATE for the null stream, a context not in global mode, or one
+ * that re-partitions after every step (kdt_set_repartition: that
+ * synchronises); a graph captured before a later kdt_set_repartition is
+ * refused by kdt_graph_launch (KDT_E_STATE). */
+int kdt_graph_build_global(kdt_ctx* ctx, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                           int8_t* applied, kdt_graph** out);
+
 /* Rebuild the whole DT* from scratch from the current positions with the
  * device builder (the full-rebuild alternative the paper weighs against
  * updating, Sec. I).  Synchronises. */

@@ -4076,11 +4076,15 @@ int kdt_set_repartition(kdt_ctx* c, int32_t every_step) {
     if (!c || every_step < 0 || every_step > 1) return KDT_E_ARG;
     if (!c->global || !c->g.qt) return KDT_E_STATE;
     c->qt_every_step = every_step != 0;
+    c->epoch++;
     return KDT_OK;
 }
 
-int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
-                   int8_t* applied) {
+}  // extern "C"
+
+namespace {
+
+int check_global_steps(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps) {
     if (!c || n_steps < 0 || (n_steps > 0 && (!moves || !step_off))) return KDT_E_ARG;
     if (!c->global || c->sticky != KDT_OK) return KDT_E_STATE;
     for (int32_t t = 0; t < n_steps; ++t) {
@@ -4088,13 +4092,20 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
         if (step_off[t] < 0 || M < 0) return KDT_E_ARG;
         if (M > c->max_moves) return KDT_E_CAPACITY;
     }
+    return KDT_OK;
+}
+
+// Enqueue n_steps global steps on the context's stream (timing events and
+// the per-step re-partition, which synchronises, only when not captured).
+int enqueue_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                   int8_t* applied, bool captured) {
     hipStream_t st = c->stream;
     for (int32_t t = 0; t < n_steps; ++t) {
         const int M = (int)(step_off[t + 1] - step_off[t]);
         if (M == 0) continue;
         const kdt_move_t* mv = moves + step_off[t];
         int8_t* ap = applied ? applied + step_off[t] : nullptr;
-        hipEvent_t e0 = timing_begin(c);
+        hipEvent_t e0 = captured ? nullptr : timing_begin(c);
         k_g_prep<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M, ap);
         k_g_classify<<<(M + 255) / 256, 256, 0, st>>>(c->dev, c->g, mv, M);
         const int parts = std::min(M, std::min(8 * c->cus, G_PART_MAX));
@@ -4103,17 +4114,61 @@ int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off,
             k_g_commit<<<parts, WAVE, 0, st>>>(c->dev, c->g, mv, M, r, r == G_ROUNDS - 1 ? 1 : 0, ap);
         }
         k_g_serial<<<1, WAVE, 0, st>>>(c->dev, c->g, mv, M, ap, parts);
-        if (c->qt_every_step) {  // Quad-treeDvision after the step (Fig. 4)
+        if (c->qt_every_step && !captured) {  // Quad-treeDvision after the step (Fig. 4)
             const int rc = qt_repartition(c);
             if (rc != KDT_OK) {
                 c->sticky = rc;
                 return rc;
             }
         }
-        timing_end(c, e0);
+        if (!captured) timing_end(c, e0);
         if (check_hip(c, hipGetLastError()) != KDT_OK) return KDT_E_DEVICE;
         c->step_count++;
     }
+    return KDT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kdt_run_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                   int8_t* applied) {
+    const int rc = check_global_steps(c, moves, step_off, n_steps);
+    return rc != KDT_OK ? rc : enqueue_global(c, moves, step_off, n_steps, applied, false);
+}
+
+int kdt_graph_build_global(kdt_ctx* c, const kdt_move_t* moves, const int64_t* step_off, int32_t n_steps,
+                           int8_t* applied, kdt_graph** out) {
+    if (!out || n_steps < 1) return KDT_E_ARG;
+    *out = nullptr;
+    int rc = check_global_steps(c, moves, step_off, n_steps);
+    if (rc != KDT_OK) return rc;
+    if (c->stream == nullptr || c->qt_every_step) return KDT_E_STATE;  // the re-partition synchronises
+    kdt_graph* g = new (std::nothrow) kdt_graph();
+    if (!g) return KDT_E_CAPACITY;
+    g->ctx = c;
+    g->epoch = c->epoch;
+    if (check_hip(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal))) {
+        delete g;
+        return KDT_E_DEVICE;
+    }
+    rc = enqueue_global(c, moves, step_off, n_steps, applied, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (rc != KDT_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        c->sticky = KDT_E_DEVICE;
+        return KDT_E_DEVICE;
+    }
+    g->graph = graph;
+    if (check_hip(c, hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0))) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return KDT_E_DEVICE;
+    }
+    *out = g;
     return KDT_OK;
 }
 

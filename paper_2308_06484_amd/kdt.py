@@ -31,7 +31,7 @@ EXPORTS = ("kdt_workspace_size", "kdt_init", "kdt_move", "kdt_step", "kdt_run", 
            "kdt_workspace_size_global", "kdt_init_global", "kdt_run_global", "kdt_rebuild_global",
            "kdt_owner", "kdt_global_stats", "kdt_moves", "kdt_step_status", "kdt_query_blocks",
            "kdt_partition", "kdt_mlp_train_noalloc", "kdt_set_block_waves", "kdt_dcalc", "kdt_set_repair",
-           "kdt_set_prefetch", "kdt_set_block_order",
+           "kdt_set_prefetch", "kdt_set_block_order", "kdt_graph_build_global",
            "kdt_workspace_size_global_qt", "kdt_init_global_qt", "kdt_quadtree", "kdt_repartition",
            "kdt_set_repartition")
 REPAIR = {"delins": 0, "flip": 1}
@@ -111,6 +111,7 @@ def _lib():
         L.kdt_dcalc.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.kdt_graph_build.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(vp)]
         L.kdt_graph_launch.argtypes = [vp, vp]
+        L.kdt_graph_build_global.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(vp)]
         L.kdt_graph_destroy.argtypes = [vp]
         L.kdt_graph_destroy.restype = None
         L.kdt_workspace_size_global.argtypes = [i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -531,6 +532,21 @@ class GlobalDT(KineticDT):
                                      len(step_off) - 1,
                                      ctypes.c_void_p(applied.data_ptr()) if applied is not None else None),
                "kdt_run_global")
+
+    def graph(self, moves, step_off, applied=None):
+        """The steps captured once as a HIP graph (needs a non-null stream;
+        not with re-partition every step); returns a Graph with launch() and
+        close()."""
+        assert moves.dtype == torch.int32 and moves.is_cuda and moves.is_contiguous()
+        step_off = np.ascontiguousarray(step_off, dtype=np.int64)
+        if applied is not None:
+            assert applied.dtype == torch.int8 and applied.is_cuda
+        g = ctypes.c_void_p()
+        _check(_lib().kdt_graph_build_global(self.ctx, ctypes.c_void_p(moves.data_ptr()), _ptr(step_off),
+                                             len(step_off) - 1,
+                                             ctypes.c_void_p(applied.data_ptr()) if applied is not None else None,
+                                             ctypes.byref(g)), "kdt_graph_build_global")
+        return Graph(self, g, (moves, step_off, applied))
 
     def rebuild(self):
         _check(_lib().kdt_rebuild_global(self.ctx), "kdt_rebuild_global")

@@ -162,3 +162,46 @@ def test_global_point_moved_twice_in_a_step():
     w = dict(xy=xy, side=16, depth=1, mv=mv, step_off=np.array([0, 4], np.int64))
     G, K = run_compare(w, 1)
     assert K.xy[0].tolist() == [4, 1] and K.xy[1].tolist() == [2, 4]
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_global_graph_replays(dense):
+    """The global steps captured as a HIP graph and replayed twice (the
+    second replay applies the same move stream again from where the first
+    left off) equal the oracle applying the stream twice: triangulation,
+    positions, kd cells, applied flags of the last replay; a change of the
+    re-partition setting refuses the graph."""
+    from paper_2308_06484_amd.kdt import GlobalDT, KDTError
+    w = _dense(7, 8) if dense else W.global_small(seed=8, steps=8)
+    T = len(w["step_off"]) - 1
+    _say(f"global graph, {'dense' if dense else 'global_small'}: {T} steps, two replays")
+    M = max(1, int(np.diff(w["step_off"]).max()))
+    stream = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(stream):
+        G = GlobalDT(w["xy"], [0, 0, w["side"], w["side"]], w["depth"], M, device=DEV, stream=stream)
+        mv = torch.from_numpy(np.ascontiguousarray(w["mv"])).to(DEV)
+        ap = torch.full((len(w["mv"]),), -1, dtype=torch.int8, device=DEV)
+        g = G.graph(mv, w["step_off"], ap)
+        K = KineticGlobal(w["xy"], w["side"], w["depth"])
+        for rep in range(2):
+            g.launch()
+            want = np.concatenate([K.apply_step(w["mv"][int(w["step_off"][t]):int(w["step_off"][t + 1])])
+                                   for t in range(T)])
+            stream.synchronize()
+            assert np.array_equal(ap.cpu().numpy().astype(bool), want), rep
+            assert np.array_equal(G.positions(), K.xy), rep
+            assert np.array_equal(G.query_canonical(), K.dt()), rep
+            assert np.array_equal(G.owner(), K.owner()), rep
+        g.close()
+        G.close()
+        # quad-tree cells: no graph while re-partitioning every step, and a
+        # graph captured before the setting changed is refused
+        Q = GlobalDT(w["xy"], [0, 0, w["side"], w["side"]], 0, M, device=DEV, stream=stream, quadtree=64)
+        g = Q.graph(mv, w["step_off"], ap)
+        Q.set_repartition(True)
+        with pytest.raises(KDTError):
+            g.launch()
+        g.close()
+        with pytest.raises(KDTError):
+            Q.graph(mv, w["step_off"], ap)
+        Q.close()
