@@ -101,17 +101,30 @@ def fold_normalisation(w, mu, sd):
     return w.astype(np.float32)
 
 
-def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0"):
+# Features the network does not see: 15 (max d over d of the d-calculation)
+# divides by a minimum over the whole point set, an extreme value that
+# changes from one data set to the next (on selector_mix, d = 17 for one seed
+# and 7.6 for another): a network trained on one set would read the other's
+# blocks as moving more than twice as far.  The d-limit rule uses it.
+NET_DROP = (15,)
+
+
+def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0", drop=NET_DROP):
     """Train on the device (the library's kernels) and return float32
-    weights for raw features, plus the final mean loss."""
+    weights for raw features.  The features in `drop` are held at zero
+    during training and their first-layer weights set to zero, so the
+    network ignores them."""
     mu = X.mean(axis=0).astype(np.float64)
     sd = X.std(axis=0).astype(np.float64)
     sd[sd < 1e-6] = 1.0  # constant features: centred to zero, left unscaled
     Xn = ((X - mu) / sd).astype(np.float32)
+    drop = list(drop)
+    Xn[:, drop] = 0.0
     ym = Y.mean(axis=0)
     Yc = (Y - ym).astype(np.float32)
     w0 = init_weights(seed)
     w0[-2:] = 0.0
+    w0[:H * IN].reshape(H, IN)[:, drop] = 0.0
     wt = torch.from_numpy(w0).to(device)
     xt = torch.from_numpy(Xn).to(device)
     yt = torch.from_numpy(Yc).to(device)
@@ -121,6 +134,7 @@ def train(X, Y, epochs=200, batch=4096, lr=0.02, seed=0, device="cuda:0"):
     torch.cuda.synchronize()
     w = wt.cpu().numpy()
     w[-2:] += ym.astype(np.float32)  # output bias back to the label scale
+    w[:H * IN].reshape(H, IN)[:, drop] = 0.0  # (their gradient was zero: still zero)
     return fold_normalisation(w, mu, sd)
 
 
