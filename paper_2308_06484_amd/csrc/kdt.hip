@@ -801,10 +801,16 @@ constexpr int ORD_BUCKETS = DRYMAX + 2;  // k = 0 .. DRYMAX, and more
 __device__ __forceinline__ int ord_count(const int* base, int B, int cut) {
     return cut <= 0 ? B : (cut > DRYMAX + 1 ? 0 : base[DRYMAX + 2 - cut]);
 }
-__global__ void __launch_bounds__(1024) k_order(const int* __restrict__ off, int B, int cut, int cut2,
+// One workgroup per step of a chunk (blockIdx.x): the move counts of a
+// stream are known ahead, so the orders of several steps are taken in one
+// launch, step s's at order + s * (B + 2).
+constexpr int ORDER_STEPS = 64;  // steps whose orders one launch takes
+__global__ void __launch_bounds__(1024) k_order(const int* __restrict__ step_off, int B, int cut, int cut2,
                                                 int* order) {
     __shared__ int cnt[ORD_BUCKETS];
     __shared__ int base[ORD_BUCKETS];
+    const int* off = step_off + (long long)blockIdx.x * (B + 1);
+    order += (long long)blockIdx.x * (B + 2);
     const int tid = threadIdx.x;
     for (int i = tid; i < ORD_BUCKETS; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
@@ -2388,7 +2394,7 @@ Layout make_layout(int64_t n, int32_t B, int32_t max_staged) {
     L.stage_app = take((size_t)std::max(max_staged, 1));
     L.sticky = take(sizeof(int) * 4);
     L.lpt = take(sizeof(int) * (B + 1));
-    L.sorder = take(sizeof(int) * (B + 2));
+    L.sorder = take(sizeof(int) * (size_t)(B + 2) * ORDER_STEPS);
     L.rest_mv = take(sizeof(kdt_move_t) * (size_t)B * DRYMAX);
     L.rest_idx = take(sizeof(int) * (size_t)B * DRYMAX);
     L.rest_app = take((size_t)B * DRYMAX);
@@ -3283,9 +3289,13 @@ int enqueue_steps(kdt_ctx* c, const kdt_move_t* moves, const int32_t* step_off, 
             const bool split = c->block_waves > 1 && c->heavy_cut > 0;
             const bool mid = split && c->block_waves == 4 && c->mid_cut > 0;
             if (c->block_order || split) {
-                ord = (int*)(w + c->L.sorder);
+                // the orders of up to ORDER_STEPS steps at a time
+                int* ord0 = (int*)(w + c->L.sorder);
                 const int cut = split ? c->heavy_cut : DRYMAX + 2;
-                k_order<<<1, 1024, 0, c->stream>>>(off, c->B, cut, mid ? c->mid_cut : cut, ord);
+                if (t % ORDER_STEPS == 0)
+                    k_order<<<std::min(ORDER_STEPS, n_steps - t), 1024, 0, c->stream>>>(
+                        off, c->B, cut, mid ? c->mid_cut : cut, ord0);
+                ord = ord0 + (long long)(t % ORDER_STEPS) * (c->B + 2);
             }
             hipStream_t mws = c->stream;
             if (split) {  // heavy (and middle) blocks on side streams, at the same time as the others
