@@ -1085,6 +1085,37 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     const int npair = with_q ? k * (k - 1) / 2 : 0;
     const int nqg = with_q && S.link[k - 1] == GHOST ? 2 * (k - 1) : 0;
     const int ncand = ntrip + npair + nqg;
+    bool done = false;
+    // The common case first (a short move keeps the star's shape): with q
+    // strictly left of every link edge and no link vertex inside the
+    // perturbed circle of any fan triangle (q_s, q_s+1, q), the fan is the
+    // whole retriangulation.  Its k triangles are Delaunay among the link
+    // vertices and q and tile the polygon; any other triple that passed
+    // every test would lie outside the polygon, in a pocket behind a
+    // concave chain, and a pocket triangle is clockwise in link order, so
+    // the search below would find exactly the fan.  The keys go in the
+    // order that search lists them (pairs (i < j) by j, then i; the pair
+    // (0, k-1) reversed to counter-clockwise), so everything after this
+    // point is the same either way.  Same predicates, same argument order.
+    if (with_q && !ballot(lane < k && S.link[lane] == GHOST)) {
+        const int sh = k <= 8 ? 3 : 4;  // lanes per link edge (k <= EMK - 1 here)
+        bool bad = false;
+        for (int x = lane; x < (k << sh); x += WAVE) {
+            const int s = x >> sh, m = x & ((1 << sh) - 1);
+            const int s1 = s + 1 < k ? s + 1 : 0;
+            if (m >= k || m == s1) continue;
+            const int2 a = S.lxy[s], b = S.lxy[s1];
+            if (m == s) bad = bad || !(orient(a, b, q) > 0);
+            else bad = bad || incircle_star(a, S.link[s], b, S.link[s1], q, qv, S.lxy[m], S.link[m]) >= 0;
+        }
+        if (!ballot(bad)) {
+            if (lane < k)
+                S.hole_key[lane] = lane < k - 2 ? pack3(lane, lane + 1, k)
+                                                : (lane == k - 2 ? pack3(k - 1, 0, k) : pack3(k - 2, k - 1, k));
+            if (lane == 0) S.nhole = k;
+            done = true;
+        }
+    }
     // Two phases: the candidates that pass orientation (and keep q out)
     // are compacted into S.emat, their verdicts in S.cav_ent (both idle
     // here), and then tested against every link vertex, one (candidate,
@@ -1092,8 +1123,7 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     // the link neighbours of its vertices, which reject most non-Delaunay
     // triples.  Too many survivors: every lane tests its candidate against
     // every vertex.
-    bool done = false;
-    {
+    if (!done) {
         int nsurv = 0;
         for (int t0 = 0; t0 < ncand; t0 += WAVE) {
             TriCand c = tri_cand(S, k, t0 + lane, ntrip, npair, ncand, qv, q, with_q);
