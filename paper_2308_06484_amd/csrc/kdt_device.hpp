@@ -1085,7 +1085,7 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     const int npair = with_q ? k * (k - 1) / 2 : 0;
     const int nqg = with_q && S.link[k - 1] == GHOST ? 2 * (k - 1) : 0;
     const int ncand = ntrip + npair + nqg;
-    bool done = false;
+    bool done = false, fan = false;
     // The common case first (a short move keeps the star's shape): with q
     // strictly left of every link edge and no link vertex inside the
     // perturbed circle of any fan triangle (q_s, q_s+1, q), the fan is the
@@ -1093,10 +1093,11 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     // vertices and q and tile the polygon; any other triple that passed
     // every test would lie outside the polygon, in a pocket behind a
     // concave chain, and a pocket triangle is clockwise in link order, so
-    // the search below would find exactly the fan.  The keys go in the
-    // order that search lists them (pairs (i < j) by j, then i; the pair
-    // (0, k-1) reversed to counter-clockwise), so everything after this
-    // point is the same either way.  Same predicates, same argument order.
+    // the search below would find exactly the fan.  The fan's records are
+    // then built straight from the link (below), in the order that search
+    // lists them: pairs (i < j) by j, then i, so t_s = (s, s+1, q) comes
+    // at s for s < k-2, then t_k-1 = (k-1, 0, q), then t_k-2.  Same
+    // predicates, same argument order.
     if (with_q && !ballot(lane < k && S.link[lane] == GHOST)) {
         const int sh = k <= 8 ? 3 : 4;  // lanes per link edge (k <= EMK - 1 here)
         bool bad = false;
@@ -1108,13 +1109,7 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
             if (m == s) bad = bad || !(orient(a, b, q) > 0);
             else bad = bad || incircle_star(a, S.link[s], b, S.link[s1], q, qv, S.lxy[m], S.link[m]) >= 0;
         }
-        if (!ballot(bad)) {
-            if (lane < k)
-                S.hole_key[lane] = lane < k - 2 ? pack3(lane, lane + 1, k)
-                                                : (lane == k - 2 ? pack3(k - 1, 0, k) : pack3(k - 2, k - 1, k));
-            if (lane == 0) S.nhole = k;
-            done = true;
-        }
+        done = fan = !ballot(bad);
     }
     // Two phases: the candidates that pass orientation (and keep q out)
     // are compacted into S.emat, their verdicts in S.cav_ent (both idle
@@ -1182,14 +1177,14 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     wsync();
     // the new triangles in the order the candidates were found (the same on
     // every run: compaction by ballot and prefix count)
-    const int nh = S.nhole;
+    const int nh = fan ? k : S.nhole;
     if (nh != (with_q ? k : k - 2)) return ST_INTERNAL;
     const int nv = with_q ? k + 1 : k;  // vertices of the polygon (+ q)
     const bool small = nv <= EMK;
-    if (small)
+    if (small && !fan)
         for (int x = lane; x < nv * EMK; x += WAVE) S.emat[x] = -1;
     wsync();
-    if (small && lane < nh) {
+    if (small && !fan && lane < nh) {
         const int hk = S.hole_key[lane];
         const int d0 = hk >> 16, d1 = (hk >> 8) & 255, d2 = hk & 255;
         S.emat[d1 * EMK + d2] = lane * 4 + 0;
@@ -1201,7 +1196,25 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     int herr = 0;
     Tri h;
     bool has_q = false;
-    if (lane < nh) {
+    if (fan) {
+        // fan triangle t_s = (s, s+1, q) at s (s < k-2), k-2 (s = k-1) or
+        // k-1 (s = k-2): its edge 0, (s+1, q), borders t_s+1 at that one's
+        // edge 1; its edge 1, (q, s), borders t_s-1 at that one's edge 0;
+        // its edge 2 is link edge s
+        if (lane < nh) {
+            const int s = lane < k - 2 ? lane : (lane == k - 2 ? k - 1 : k - 2);
+            const int s1 = s + 1 < k ? s + 1 : 0, sp = s > 0 ? s - 1 : k - 1;
+            const int a1 = s1 < k - 2 ? s1 : (s1 == k - 1 ? k - 2 : k - 1);
+            const int a2 = sp < k - 2 ? sp : (sp == k - 1 ? k - 2 : k - 1);
+            const int2 p0 = S.lxy[s], p1 = S.lxy[s1];
+            h.v = make_int4(S.link[s], S.link[s1], qv, 0);
+            h.n = make_int4(S.star_slot[a1] * 4 + 1, S.star_slot[a2] * 4 + 0, S.outref[s], 0);
+            h.c01 = make_int4(p0.x, p0.y, p1.x, p1.y);
+            h.c2 = make_int4(q.x, q.y, 0, 0);
+            S.edge_tri[s] = lane * 4 + 2;
+            has_q = true;
+        }
+    } else if (lane < nh) {
         const int hk = S.hole_key[lane];
         const int cs[3] = {hk >> 16, (hk >> 8) & 255, hk & 255};
         const TriCand c = tri_cand_of(S, k, cs[0], cs[1], cs[2], qv, q);
@@ -1241,7 +1254,7 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     }
     if (ballot(herr)) return ST_INTERNAL;
     wsync();
-    if (ballot(lane < k && S.edge_tri[lane] < 0)) return ST_INTERNAL;
+    if (!fan && ballot(lane < k && S.edge_tri[lane] < 0)) return ST_INTERNAL;
     if (with_q && !ballot(has_q)) return ST_INTERNAL;
     if (direct) {
         // every check passed: the region's new records, the outside
