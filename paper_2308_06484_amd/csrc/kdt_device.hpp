@@ -400,12 +400,20 @@ __device__ __forceinline__ void tnote(WL& S, bool mine, int e, int* used) {
 
 template <class WL>
 __device__ __forceinline__ int tget(const BlockView& B, WL& S, bool want, int s, int* used) {
+    // The record leaves memory before the claim, so the claim's LDS round
+    // trips run while it is in flight; a lane whose slot is in the table
+    // already drops what it read.
+    int4 r0 = make_int4(0, 0, 0, 0), r1 = r0, r2 = r0, r3 = r0;
+    if (want && !bad_slot(B, s)) {
+        const int4* src = reinterpret_cast<const int4*>(B.tri + s);
+        r0 = src[0];
+        r1 = src[1];
+        r2 = src[2];
+        r3 = src[3];
+    }
     bool mine;
     const int e = tclaim(S, want, s, &mine);
     if (mine) {
-        // all four parts in flight before the first is stored
-        const int4* src = reinterpret_cast<const int4*>(B.tri + s);
-        const int4 r0 = src[0], r1 = src[1], r2 = src[2], r3 = src[3];
         int4* dst = reinterpret_cast<int4*>(&S.trec[e]);
         dst[0] = r0;
         dst[1] = r1;
