@@ -1078,6 +1078,107 @@ __device__ __forceinline__ bool cand_killed_by(const TriCand& c, int m, int vm, 
                    : incircle_star(c.pi, c.vi, c.pj, c.vj, c.pl, c.vl, pm, vm) >= 0;
 }
 
+// Lawson flips inside the polygon q_0..q_{k-1} + q (index k), from the fan
+// (q_s, q_s+1, q), with q in the polygon's kernel; see fill_star.  The
+// triangles live in S.emat (idle here): 8 ints each, vertices at 0..2
+// counter-clockwise, at 4 + e the triangle across the edge opposite vertex
+// e (-1 on the polygon's boundary).  On success writes the k triangles'
+// keys to S.hole_key in candidate order and k to S.nhole; false when the
+// flips hit the cap (S.hole_key untouched).
+constexpr int LAWSON_MAX_FLIPS = 32;
+template <class WL>
+__device__ __forceinline__ bool lawson_from_fan(WL& S, int k, int qv, int2 q, int ntrip) {
+    const int lane = lane_id();
+    int* T = S.emat;
+    static_assert(EMK * EMK >= 8 * (EMK - 1), "the flip triangles fit the edge matrix");
+    if (lane < k) {
+        const int s1 = lane + 1 < k ? lane + 1 : 0, sp = lane > 0 ? lane - 1 : k - 1;
+        T[lane * 8 + 0] = lane;
+        T[lane * 8 + 1] = s1;
+        T[lane * 8 + 2] = k;
+        T[lane * 8 + 4] = s1;  // across (s+1, q)
+        T[lane * 8 + 5] = sp;  // across (q, s)
+        T[lane * 8 + 6] = -1;  // link edge
+    }
+    wsync();
+    bool settled = false;
+    for (int it = 0; it <= LAWSON_MAX_FLIPS; ++it) {
+        // one lane per (triangle, edge); each inner edge tested once, from
+        // its lower-numbered triangle: t = (c, a, b) and u = (d, b, a)
+        // share edge (a, b), and a flip makes them t = (c, a, d) and u =
+        // (c, d, b), sharing (c, d)
+        const int t = lane >> 2, e = lane & 3;
+        bool flip = false;
+        int u = -1, c = 0, a = 0, b = 0, d = 0, n_bc = -1, n_ca = -1, n_ad = -1, n_db = -1;
+        if (t < k && e < 3) {
+            const int e1 = e == 2 ? 0 : e + 1, e2 = e == 0 ? 2 : e - 1;
+            u = T[t * 8 + 4 + e];
+            c = T[t * 8 + e];
+            a = T[t * 8 + e1];
+            b = T[t * 8 + e2];
+            n_bc = T[t * 8 + 4 + e1];
+            n_ca = T[t * 8 + 4 + e2];
+            if (u > t) {
+                const int u0 = T[u * 8 + 0], u1 = T[u * 8 + 1];
+                const int f = u0 != a && u0 != b ? 0 : (u1 != a && u1 != b ? 1 : 2);
+                const int f1 = f == 2 ? 0 : f + 1, f2 = f == 0 ? 2 : f - 1;
+                d = T[u * 8 + f];
+                n_ad = T[u * 8 + 4 + f1];
+                n_db = T[u * 8 + 4 + f2];
+                const int2 pc = c < k ? S.lxy[c] : q, pa = a < k ? S.lxy[a] : q;
+                const int2 pb = b < k ? S.lxy[b] : q, pd = d < k ? S.lxy[d] : q;
+                const int vc = c < k ? S.link[c] : qv, va = a < k ? S.link[a] : qv;
+                const int vb = b < k ? S.link[b] : qv, vd = d < k ? S.link[d] : qv;
+                flip = incircle_star(pc, vc, pa, va, pb, vb, pd, vd) > 0;
+            }
+        }
+        const uint64_t m = ballot(flip);
+        if (!m) {
+            settled = true;
+            break;
+        }
+        if (it == LAWSON_MAX_FLIPS) break;
+        if (lane == first_lane(m)) {  // the first edge that fails flips
+            T[t * 8 + 0] = c; T[t * 8 + 1] = a; T[t * 8 + 2] = d;
+            T[t * 8 + 4] = n_ad; T[t * 8 + 5] = u; T[t * 8 + 6] = n_ca;
+            T[u * 8 + 0] = c; T[u * 8 + 1] = d; T[u * 8 + 2] = b;
+            T[u * 8 + 4] = n_db; T[u * 8 + 5] = n_bc; T[u * 8 + 6] = t;
+            if (n_ad >= 0)
+                for (int g = 4; g < 7; ++g)
+                    if (T[n_ad * 8 + g] == u) T[n_ad * 8 + g] = t;
+            if (n_bc >= 0)
+                for (int g = 4; g < 7; ++g)
+                    if (T[n_bc * 8 + g] == t) T[n_bc * 8 + g] = u;
+        }
+        wsync();
+    }
+    if (!settled) return false;
+    // keys and candidate indices as the search forms them: a triangle with
+    // q is the pair candidate (i, j, q), counter-clockwise; one without is
+    // the link triple in increasing order
+    int key = 0, cidx = 0x7fffffff;
+    if (lane < k) {
+        const int v0 = T[lane * 8 + 0], v1 = T[lane * 8 + 1], v2 = T[lane * 8 + 2];
+        if (v0 == k || v1 == k || v2 == k) {
+            const int i = v2 == k ? v0 : (v0 == k ? v1 : v2);
+            const int j = v2 == k ? v1 : (v0 == k ? v2 : v0);
+            const int lo = min(i, j), hi = max(i, j);
+            key = pack3(i, j, k);
+            cidx = ntrip + hi * (hi - 1) / 2 + lo;
+        } else {
+            const int a = min(v0, min(v1, v2)), c = max(v0, max(v1, v2)), b = v0 + v1 + v2 - a - c;
+            key = pack3(a, b, c);
+            cidx = c * (c - 1) * (c - 2) / 6 + b * (b - 1) / 2 + a;
+        }
+    }
+    int rank = 0;
+    for (int u = 0; u < k; ++u) rank += __builtin_amdgcn_readlane(cidx, u) < cidx ? 1 : 0;
+    wsync();
+    if (lane < k) S.hole_key[rank] = key;
+    if (lane == 0) S.nhole = k;
+    return true;
+}
+
 template <class WL>
 __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int qv, int2 q, bool with_q, int* used,
                          int* nvt, BlockStats* st, bool direct = false) {
@@ -1108,16 +1209,28 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
     // predicates, same argument order.
     if (with_q && !ballot(lane < k && S.link[lane] == GHOST)) {
         const int sh = k <= 8 ? 3 : 4;  // lanes per link edge (k <= EMK - 1 here)
-        bool bad = false;
+        bool bad = false, side = false;
         for (int x = lane; x < (k << sh); x += WAVE) {
             const int s = x >> sh, m = x & ((1 << sh) - 1);
             const int s1 = s + 1 < k ? s + 1 : 0;
             if (m >= k || m == s1) continue;
             const int2 a = S.lxy[s], b = S.lxy[s1];
-            if (m == s) bad = bad || !(orient(a, b, q) > 0);
+            if (m == s) side = side || !(orient(a, b, q) > 0);
             else bad = bad || incircle_star(a, S.link[s], b, S.link[s1], q, qv, S.lxy[m], S.link[m]) >= 0;
         }
-        done = fan = !ballot(bad);
+        const bool kernel = !ballot(side);  // q strictly left of every link edge
+        done = fan = kernel && !ballot(bad);
+        // Not the fan but q in the polygon's kernel (most of the rest): the
+        // fan is still a triangulation of the polygon, and Lawson flips of
+        // its edges that fail the perturbed test reach the triangulation
+        // whose inner edges all pass it.  No triangle outside the region is
+        // destroyed, so that is the part of DT*(S - p + q) inside the
+        // region: the triangles the search would find.  Each flip raises
+        // the lifted surface, so the flips end; they are capped all the
+        // same, and a capped run leaves the work to the search.  The
+        // triangles are then listed in the search's order (by candidate
+        // index), so everything after this point is the same either way.
+        if (kernel && !fan) done = lawson_from_fan(S, k, qv, q, ntrip);
     }
     // Two phases: the candidates that pass orientation (and keep q out)
     // are compacted into S.emat, their verdicts in S.cav_ent (both idle
