@@ -1225,7 +1225,7 @@ __device__ __forceinline__ int fill_star(const BlockView& B, WL& S, int k, int q
         // its edges that fail the perturbed test reach the triangulation
         // whose inner edges all pass it.  No triangle outside the region is
         // destroyed, so that is the part of DT*(S - p + q) inside the
-        // region: the triangles the search would find.  Each flip raises
+        // region: the triangles the search would find.  Each flip lowers
         // the lifted surface, so the flips end; they are capped all the
         // same, and a capped run leaves the work to the search.  The
         // triangles are then listed in the search's order (by candidate
