@@ -1855,28 +1855,21 @@ __global__ void __launch_bounds__(NW * WAVE) k_step_mw(DevState s, const kdt_mov
         }
         if (lane == 0) M.outcome[w] = i >= 0 ? outc : 2;
         __syncthreads();  // commits done, outcomes known
-        if (tid == 0) {
-            // the round took list[head .. head + nt); the plans that lost go
-            // back just before the moves no wavefront took (list order kept)
+        if (w == 0) {
+            // the round took list[head .. head + nt), one lane each; the plans
+            // that lost go back just before the moves no wavefront took (list
+            // order kept), the first error in list order fails the block
             const int nt = min(NW, np - head);
-            int keep[NW];
-            int nk = 0;
-            for (int j = 0; j < nt; ++j) {
-                const int mi = M.list[head + j];
-                const int o = M.outcome[j];
-                if (o == 2) {
-                    keep[nk++] = mi;
-                } else if (o == 3) {
-                    M.mstate[mi] = MWS_REST;
-                } else if (o < 0) {
-                    if (M.fail == ST_OK) M.fail = o;
-                } else {
-                    M.mstate[mi] = MWS_DONE;
-                }
-            }
-            const int nh = head + nt - nk;
-            for (int j = 0; j < nk; ++j) M.list[nh + j] = keep[j];
-            M.head = nh;
+            const bool on = lane < nt;
+            const int mi = on ? M.list[head + lane] : 0;
+            const int o = on ? M.outcome[lane] : 0;
+            const uint64_t lost = ballot(on && o == 2), bad = ballot(on && o < 0);
+            const int nh = head + nt - __popcll(lost);
+            if (on && o == 3) M.mstate[mi] = MWS_REST;
+            else if (on && (o == 0 || o == 1)) M.mstate[mi] = MWS_DONE;
+            if (bad && lane == first_lane(bad) && M.fail == ST_OK) M.fail = o;
+            if (on && o == 2) M.list[nh + lanes_below(lost)] = mi;
+            if (lane == 0) M.head = nh;
         }
         __syncthreads();
     }
